@@ -1,0 +1,145 @@
+/*
+ * snc.h -- exact bivariate resultants and integer gcds on one AMD MI355X.
+ *
+ * The two symbolic operations that the curve and curve-pair analyses of
+ * Berberich, Emeliyanenko, Kobel and Sagraloff, "Arrangement Computation for
+ * Planar Algebraic Curves", rely on:
+ *
+ *   res_y(f, g) in Z[x] for f, g in Z[x, y]   -- the projection resultant
+ *       R = res(f, f_y, y) (Section 2.1, "Projection Phase") and the
+ *       curve-pair resultant R_CD = res(f, g, y) (Section 3);
+ *   gcd(a, b) in Z[x]                          -- Yun's square-free
+ *       factorisation of R (Section 2.1) and the content of f (Section 2.1).
+ *
+ * Both follow the modular "divide-conquer-combine" scheme of Section 4
+ * ("Symbolic Speedups"): modular and evaluation homomorphisms, independent
+ * problems over prime fields, interpolation and Chinese remaindering.
+ *
+ * Integers.  Every integer array is a sequence of little-endian 32-bit limbs
+ * in two's complement with a fixed number of limbs per coefficient
+ * (nlimbs >= 1).  An int64 array is exactly nlimbs = 2 (no copy needed).
+ *
+ * Results.  res_y is returned as the determinant of the Sylvester matrix
+ * (content and sign kept): rows 0..n-1 hold f's coefficients f_m .. f_0,
+ * rows n..n+m-1 hold g's g_n .. g_0, each row shifted one column right of
+ * the row above, m and n the y-degrees over Z[x].  res_y(f, g) = 0 when f = 0
+ * or g = 0, and 1 when m = n = 0.  gcd(a, b) is the gcd in Z[x] including
+ * the integer content, with a positive leading coefficient; gcd(0, 0) = 0.
+ *
+ * Memory.  Inputs and outputs are HOST buffers.  Device memory is owned by
+ * the caller: each compute call takes a device workspace (d_ws, ws_bytes)
+ * whose size the matching *_plan call reports, and a HIP stream (passed as
+ * void*, a hipStream_t; NULL = the default stream).  The library never
+ * allocates device memory.  A call returns after its result is on the host.
+ *
+ * Errors.  Every function returns an snc_status; nothing aborts or prints.
+ * snc_last_error() gives a message for the last failure on a context.
+ *
+ * Threads.  One snc_ctx per host thread.  A server (snc_server_*) is
+ * internally synchronised and may be used from several threads.
+ */
+#ifndef SNC_H
+#define SNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SNC_OK = 0,
+  SNC_EINVAL = -1,    /* invalid argument (NULL pointer, negative size, nlimbs < 1, unsupported degree) */
+  SNC_ERANGE = -2,    /* output buffer too small; required deg / nlimbs written back into *out */
+  SNC_ENOMEM = -3,    /* workspace (or server pool) smaller than the plan requires */
+  SNC_EDEVICE = -4,   /* HIP runtime error; see snc_last_error */
+  SNC_EAGAIN = -5,    /* server: request not finished yet */
+  SNC_EINTERNAL = -6  /* an internal consistency check failed (a bug) */
+} snc_status;
+
+/* f = sum_{i<=dy} sum_{k<=dx} c_{i,k} x^k y^i, coefficient c_{i,k} at
+ * limbs[(i*(dx+1)+k)*nlimbs .. +nlimbs).  dy = -1 denotes f = 0 (limbs may
+ * be NULL).  Rows of zeros above the true y-degree are allowed: the y-degree
+ * over Z[x] is the highest non-zero row. */
+typedef struct {
+  const uint32_t* limbs;
+  int32_t dy, dx, nlimbs;
+} snc_bipoly;
+
+/* a = sum_{i<=deg} c_i x^i, c_i at limbs[i*nlimbs .. +nlimbs).  deg = -1 is
+ * the zero polynomial.  As an OUTPUT: on entry deg is the capacity (highest
+ * degree that fits) and nlimbs the limb stride of the caller's buffer; on
+ * return deg is the degree of the result and nlimbs is unchanged (values are
+ * sign-extended to the stride).  On SNC_ERANGE, deg and nlimbs receive the
+ * required capacity and stride and nothing else is written. */
+typedef struct {
+  uint32_t* limbs;
+  int32_t deg, nlimbs;
+} snc_upoly;
+
+typedef struct {
+  int32_t deg_bound;      /* bound on the degree of the result */
+  int32_t out_nlimbs;     /* limbs per output coefficient that always suffice */
+  int32_t nprimes;        /* number of primes the computation starts with */
+  int32_t reserved;
+  size_t workspace_bytes; /* device workspace the compute call needs */
+} snc_plan;
+
+typedef struct snc_ctx snc_ctx;
+typedef struct snc_server snc_server;
+
+/* Version of this interface (major*10000 + minor*100 + patch). */
+int snc_version(void);
+const char* snc_status_str(int status);
+
+/* Create a context bound to HIP device `device` (makes it current).  Builds
+ * the prime table on the host; does no device allocation. */
+int snc_create(int device, snc_ctx** out);
+int snc_destroy(snc_ctx* ctx);
+const char* snc_last_error(const snc_ctx* ctx);
+
+/* Per-stage timing of the last compute call on this context, measured with
+ * HIP events on the call's stream when enabled (off by default).  names and
+ * ms receive up to `cap` entries; returns the number of stages recorded. */
+int snc_set_timing(snc_ctx* ctx, int enable);
+int snc_get_timing(const snc_ctx* ctx, const char** names, float* ms, int32_t* launches, int cap);
+
+/* ---- resultant res_y(f, g) in Z[x] --------------------------------------
+ * Host-only planning: degree bound D (Sylvester weighted-degree bound),
+ * Hadamard-type coefficient bound B, number of primes k with prod p > 2B,
+ * output limbs L = ceil((log2 B + 2)/32), device workspace. */
+int snc_resultant_y_plan(const snc_bipoly* f, const snc_bipoly* g, snc_plan* out);
+
+/* One resultant: reduce mod k primes -> evaluate at D+1 points and eliminate
+ * per (prime, point) -> interpolate per prime -> CRT per coefficient.  The
+ * result is exact (not probabilistic).  out: see snc_upoly. */
+int snc_resultant_y(snc_ctx* ctx, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                    size_t ws_bytes, void* stream, snc_upoly* out);
+
+/* n independent resultants in one submission: every stage runs once over
+ * all pairs (one launch per stage and degree class), captured once into a
+ * HIP graph per batch shape and replayed.  f, g, out are arrays of n. */
+int snc_resultant_y_batch_plan(int32_t n, const snc_bipoly* f, const snc_bipoly* g,
+                               snc_plan* out_each /* n entries or NULL */, snc_plan* out_total);
+int snc_resultant_y_batch(snc_ctx* ctx, int32_t n, const snc_bipoly* f, const snc_bipoly* g,
+                          void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
+
+/* ---- gcd in Z[x] ---------------------------------------------------------
+ * Modular (small primes) gcd: contents on the host, monic gcd and cofactors
+ * mod each prime on the device, primes of minimal gcd degree kept, CRT, and
+ * an exact certificate (norm bound on the lifted product) before the result
+ * is accepted; unlucky primes are replaced by more primes. */
+int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out);
+int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
+              void* stream, snc_upoly* out);
+
+/* ---- host-side helpers (no device work) --------------------------------- */
+/* i-th prime of the modulus table (descending below 2^30), 0 if out of range. */
+uint32_t snc_prime(int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNC_H */

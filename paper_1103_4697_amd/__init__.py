@@ -1,0 +1,351 @@
+"""Exact bivariate resultants and integer gcds on the MI355X.
+
+Thin ctypes binding over libsnc.so (C ABI in include/snc.h).  Python only
+marshals integers to and from 32-bit two's-complement limbs and provides
+device workspaces from PyTorch; every step of the computation runs in the
+library's HIP kernels.  If the library is missing the binding raises; there
+is no fallback path.
+
+    import paper_1103_4697_amd as snc
+    R = snc.resultant_y(f, g)        # f, g: [i][k] integer arrays, y^i x^k
+    G = snc.gcd_z(a, b)              # a, b: ascending integer lists
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnc.so")
+
+SNC_OK, SNC_EINVAL, SNC_ERANGE, SNC_ENOMEM, SNC_EDEVICE, SNC_EAGAIN, SNC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+
+class SncError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"snc status {status} ({_status_name(status)}): {msg}")
+        self.status = status
+
+
+class Bipoly(C.Structure):
+    _fields_ = [("limbs", C.POINTER(C.c_uint32)), ("dy", C.c_int32), ("dx", C.c_int32), ("nlimbs", C.c_int32)]
+
+
+class Upoly(C.Structure):
+    _fields_ = [("limbs", C.POINTER(C.c_uint32)), ("deg", C.c_int32), ("nlimbs", C.c_int32)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("deg_bound", C.c_int32), ("out_nlimbs", C.c_int32), ("nprimes", C.c_int32),
+                ("reserved", C.c_int32), ("workspace_bytes", C.c_size_t)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def lib():
+    """Load libsnc.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} not found: build it with python -m paper_1103_4697_amd.build")
+            L = C.CDLL(LIB_PATH)
+            P, I32, SZ, VP = C.POINTER, C.c_int32, C.c_size_t, C.c_void_p
+            sig = {
+                "snc_version": (C.c_int, []),
+                "snc_status_str": (C.c_char_p, [C.c_int]),
+                "snc_create": (C.c_int, [C.c_int, P(VP)]),
+                "snc_destroy": (C.c_int, [VP]),
+                "snc_last_error": (C.c_char_p, [VP]),
+                "snc_set_timing": (C.c_int, [VP, C.c_int]),
+                "snc_get_timing": (C.c_int, [VP, P(C.c_char_p), P(C.c_float), P(I32), C.c_int]),
+                "snc_prime": (C.c_uint32, [I32]),
+                "snc_resultant_y_plan": (C.c_int, [P(Bipoly), P(Bipoly), P(Plan)]),
+                "snc_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
+                "snc_resultant_y_batch_plan": (C.c_int, [I32, P(Bipoly), P(Bipoly), P(Plan), P(Plan)]),
+                "snc_resultant_y_batch": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
+                "snc_gcd_z_plan": (C.c_int, [P(Upoly), P(Upoly), P(Plan)]),
+                "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
+            }
+            for name, (res, args) in sig.items():
+                fn = getattr(L, name, None)
+                if fn is None:
+                    continue
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+        return _lib
+
+
+def _status_name(s):
+    try:
+        return lib().snc_status_str(s).decode()
+    except Exception:
+        return str(s)
+
+
+# ---------------------------------------------------------------------------
+# Integer marshalling (two's complement 32-bit limbs)
+# ---------------------------------------------------------------------------
+
+def _limbs_needed(vals) -> int:
+    n = 1
+    for v in vals:
+        v = int(v)
+        while not (-(1 << (32 * n - 1)) <= v < (1 << (32 * n - 1))):
+            n += 1
+    return n
+
+
+def ints_to_limbs(vals, nl: int) -> np.ndarray:
+    """Flat sequence of Python ints -> uint32 array [len][nl]."""
+    vals = list(vals)
+    out = np.empty((len(vals), nl), dtype=np.uint32)
+    nbytes = 4 * nl
+    for i, v in enumerate(vals):
+        out[i] = np.frombuffer(int(v).to_bytes(nbytes, "little", signed=True), dtype="<u4")
+    return out
+
+
+def limbs_to_ints(arr: np.ndarray) -> list:
+    """uint32 array [n][nl] -> list of Python ints."""
+    arr = np.ascontiguousarray(arr, dtype=np.uint32)
+    return [int.from_bytes(row.tobytes(), "little", signed=True) for row in arr]
+
+
+def bivariate_limbs(F):
+    """Coefficient array F[i][k] -> (uint32 limbs [dy+1][dx+1][nl], dy, dx, nl)."""
+    if isinstance(F, np.ndarray) and F.dtype == np.int64:
+        A = np.ascontiguousarray(F)
+        if A.size == 0:
+            return None, -1, -1, 1
+        return A.view(np.uint32).reshape(A.shape[0], A.shape[1], 2), A.shape[0] - 1, A.shape[1] - 1, 2
+    rows = [[int(c) for c in r] for r in F]
+    if not rows:
+        return None, -1, -1, 1
+    dx = max((len(r) for r in rows), default=1) - 1
+    dx = max(dx, 0)
+    flat = []
+    for r in rows:
+        flat.extend(r + [0] * (dx + 1 - len(r)))
+    nl = _limbs_needed(flat)
+    L = ints_to_limbs(flat, nl).reshape(len(rows), dx + 1, nl)
+    return L, len(rows) - 1, dx, nl
+
+
+def _as_bipoly(F, keep):
+    L, dy, dx, nl = bivariate_limbs(F)
+    b = Bipoly()
+    if L is None:
+        b.limbs, b.dy, b.dx, b.nlimbs = None, -1, 0, 1
+        return b
+    L = np.ascontiguousarray(L, dtype=np.uint32)
+    keep.append(L)
+    b.limbs = L.ctypes.data_as(C.POINTER(C.c_uint32))
+    b.dy, b.dx, b.nlimbs = dy, dx, nl
+    return b
+
+
+def _as_upoly(a, keep):
+    vals = [int(c) for c in a]
+    while vals and vals[-1] == 0:
+        vals.pop()
+    u = Upoly()
+    if not vals:
+        u.limbs, u.deg, u.nlimbs = None, -1, 1
+        return u
+    nl = _limbs_needed(vals)
+    L = ints_to_limbs(vals, nl)
+    keep.append(L)
+    u.limbs = L.ctypes.data_as(C.POINTER(C.c_uint32))
+    u.deg, u.nlimbs = len(vals) - 1, nl
+    return u
+
+
+def _out_upoly(deg_cap, nl, keep):
+    buf = np.zeros((max(deg_cap, 0) + 1, max(nl, 1)), dtype=np.uint32)
+    keep.append(buf)
+    u = Upoly()
+    u.limbs = buf.ctypes.data_as(C.POINTER(C.c_uint32))
+    u.deg, u.nlimbs = deg_cap, max(nl, 1)
+    return u, buf
+
+
+def _read_upoly(u, buf):
+    if u.deg < 0:
+        return []
+    return limbs_to_ints(buf[: u.deg + 1])
+
+
+# ---------------------------------------------------------------------------
+# Context and device workspace
+# ---------------------------------------------------------------------------
+
+class Context:
+    """A library context on one device plus a growable device workspace
+    (a torch uint8 tensor) and the stream the calls run on."""
+
+    def __init__(self, device: int = 0):
+        import torch  # device memory and streams only
+        self._torch = torch
+        self.device = device
+        h = C.c_void_p()
+        st = lib().snc_create(device, C.byref(h))
+        if st != SNC_OK:
+            raise SncError(st, "snc_create failed")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return lib().snc_last_error(self.h).decode()
+
+    def workspace(self, nbytes: int):
+        torch = self._torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def stream_handle(self, stream=None):
+        torch = self._torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    def check(self, st, what):
+        if st != SNC_OK:
+            raise SncError(st, f"{what}: {self.error()}")
+
+    def set_timing(self, on: bool):
+        lib().snc_set_timing(self.h, 1 if on else 0)
+
+    def timing(self):
+        cap = 32
+        names = (C.c_char_p * cap)()
+        ms = (C.c_float * cap)()
+        launches = (C.c_int32 * cap)()
+        n = lib().snc_get_timing(self.h, names, ms, launches, cap)
+        return [(names[i].decode(), float(ms[i]), int(launches[i])) for i in range(min(n, cap))]
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+# ---------------------------------------------------------------------------
+# Resultants
+# ---------------------------------------------------------------------------
+
+def resultant_plan(f, g) -> Plan:
+    keep = []
+    bf, bg = _as_bipoly(f, keep), _as_bipoly(g, keep)
+    p = Plan()
+    st = lib().snc_resultant_y_plan(C.byref(bf), C.byref(bg), C.byref(p))
+    if st != SNC_OK:
+        raise SncError(st, "snc_resultant_y_plan")
+    return p
+
+
+def resultant_y(f, g, ctx: Context | None = None, stream=None) -> list:
+    """res_y(f, g) in Z[x] as an ascending list of Python ints ([] for 0)."""
+    ctx = ctx or default_context()
+    keep = []
+    bf, bg = _as_bipoly(f, keep), _as_bipoly(g, keep)
+    p = Plan()
+    ctx.check(lib().snc_resultant_y_plan(C.byref(bf), C.byref(bg), C.byref(p)), "plan")
+    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
+    ws = ctx.workspace(p.workspace_bytes)
+    st = lib().snc_resultant_y(ctx.h, C.byref(bf), C.byref(bg), C.c_void_p(ws.data_ptr()),
+                               C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
+    ctx.check(st, "snc_resultant_y")
+    return _read_upoly(u, buf)
+
+
+class ResultantBatch:
+    """A prepared batch of resultants: marshalled once, run many times
+    (the device pipeline is captured once as a HIP graph and replayed)."""
+
+    def __init__(self, pairs, ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self.keep = []
+        n = len(pairs)
+        self.n = n
+        self.F = (Bipoly * n)()
+        self.G = (Bipoly * n)()
+        for i, (f, g) in enumerate(pairs):
+            self.F[i] = _as_bipoly(f, self.keep)
+            self.G[i] = _as_bipoly(g, self.keep)
+        each = (Plan * n)()
+        total = Plan()
+        st = lib().snc_resultant_y_batch_plan(n, self.F, self.G, each, C.byref(total))
+        if st != SNC_OK:
+            raise SncError(st, "snc_resultant_y_batch_plan")
+        self.plan = total
+        self.out = (Upoly * n)()
+        self.bufs = []
+        self.caps = []
+        for i in range(n):
+            u, buf = _out_upoly(each[i].deg_bound, each[i].out_nlimbs, self.keep)
+            self.out[i] = u
+            self.bufs.append(buf)
+            self.caps.append((each[i].deg_bound, each[i].out_nlimbs))
+
+    def run(self, stream=None):
+        for i, (d, nl) in enumerate(self.caps):
+            self.out[i].deg = d
+            self.out[i].nlimbs = nl
+        ws = self.ctx.workspace(self.plan.workspace_bytes)
+        st = lib().snc_resultant_y_batch(self.ctx.h, self.n, self.F, self.G, C.c_void_p(ws.data_ptr()),
+                                         C.c_size_t(ws.numel()), self.ctx.stream_handle(stream), self.out)
+        self.ctx.check(st, "snc_resultant_y_batch")
+
+    def results(self):
+        return [_read_upoly(self.out[i], self.bufs[i]) for i in range(self.n)]
+
+
+def resultant_y_batch(pairs, ctx: Context | None = None, stream=None) -> list:
+    b = ResultantBatch(pairs, ctx)
+    b.run(stream)
+    return b.results()
+
+
+# ---------------------------------------------------------------------------
+# gcd in Z[x]
+# ---------------------------------------------------------------------------
+
+def gcd_z(a, b, ctx: Context | None = None, stream=None) -> list:
+    """gcd(a, b) in Z[x] (content kept, positive leading coefficient)."""
+    ctx = ctx or default_context()
+    keep = []
+    ua, ub = _as_upoly(a, keep), _as_upoly(b, keep)
+    p = Plan()
+    ctx.check(lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)), "gcd plan")
+    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
+    ws = ctx.workspace(p.workspace_bytes)
+    st = lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
+                         C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
+    ctx.check(st, "snc_gcd_z")
+    return _read_upoly(u, buf)
+
+
+def prime(i: int) -> int:
+    return int(lib().snc_prime(i))

@@ -1,0 +1,387 @@
+// Workspace layout and launch sequence of the resultant pipeline, shared by
+// the single-resultant call (direct launches, optional per-stage timing) and
+// the batched call (one captured HIP graph per batch shape, replayed).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "runtime_internal.hpp"
+
+int snc_ctx::stage_in(size_t bytes) {
+  if (bytes <= h_in_bytes) return SNC_OK;
+  if (h_in) (void)hipHostFree(h_in);
+  h_in = nullptr;
+  size_t nb = std::max(bytes, h_in_bytes * 2);
+  if (hipHostMalloc(&h_in, nb, hipHostMallocDefault) != hipSuccess) { h_in_bytes = 0; h_in = nullptr; return SNC_EDEVICE; }
+  h_in_bytes = nb;
+  return SNC_OK;
+}
+
+int snc_ctx::stage_out(size_t bytes) {
+  if (bytes <= h_out_bytes) return SNC_OK;
+  if (h_out) (void)hipHostFree(h_out);
+  h_out = nullptr;
+  size_t nb = std::max(bytes, h_out_bytes * 2);
+  if (hipHostMalloc(&h_out, nb, hipHostMallocDefault) != hipSuccess) { h_out_bytes = 0; h_out = nullptr; return SNC_EDEVICE; }
+  h_out_bytes = nb;
+  return SNC_OK;
+}
+
+void snc_ctx::release() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  gexec = nullptr;
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
+  for (auto e : events) (void)hipEventDestroy(e);
+  events.clear();
+  if (h_in) (void)hipHostFree(h_in);
+  if (h_out) (void)hipHostFree(h_out);
+  h_in = h_out = nullptr;
+  h_in_bytes = h_out_bytes = 0;
+}
+
+namespace snc {
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
+  lay = BatchLayout();
+  for (int i = 0; i < (int)plans.size(); ++i)
+    if (!plans[i].trivial) lay.dev.push_back(i);
+  const int NJ = (int)lay.dev.size();
+  lay.jobs.resize(NJ);
+  size_t off = 0;
+  lay.jobs_off = off; off = align256(off + sizeof(ResJob) * NJ);
+  int nrows = 0;
+  for (int j = 0; j < NJ; ++j) nrows += 2 * plans[lay.dev[j]].rstride;
+  lay.n_rows = nrows;
+  lay.rows_off = off; off = align256(off + sizeof(RowDesc) * nrows);
+  lay.pref_red = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_interp = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_crtd = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_crtc = off; off = align256(off + 8 * (NJ + 1));
+  for (int j = 0; j < NJ; ++j) {
+    const ResPlan& P = plans[lay.dev[j]];
+    if (P.cls >= 0) lay.n_ee_jobs[P.cls]++; else lay.n_gen_jobs++;
+  }
+  for (int c = 0; c < NCLS; ++c) {
+    lay.pref_ee[c] = off; off = align256(off + 8 * (lay.n_ee_jobs[c] + 1));
+    lay.list_ee[c] = off; off = align256(off + 4 * std::max(lay.n_ee_jobs[c], 1));
+  }
+  lay.pref_gen = off; off = align256(off + 8 * (lay.n_gen_jobs + 1));
+  lay.list_gen = off; off = align256(off + 4 * std::max(lay.n_gen_jobs, 1));
+  lay.coef_off = off;
+  size_t cw = 0;
+  for (int j = 0; j < NJ; ++j) { const ResPlan& P = plans[lay.dev[j]]; cw += (size_t)P.T * P.nl; }
+  lay.coef_words = cw;
+  off = align256(off + 4 * cw);
+  lay.header_bytes = off;
+  // per-job device regions
+  size_t w = off / 4;
+  size_t coefw = lay.coef_off / 4;
+  int rows = 0;
+  for (int j = 0; j < NJ; ++j) {
+    const ResPlan& P = plans[lay.dev[j]];
+    ResJob& J = lay.jobs[j];
+    std::memset(&J, 0, sizeof J);
+    J.m = P.m; J.n = P.n;
+    J.sign = (P.swap && ((P.m * P.n) & 1)) ? 1 : 0;
+    J.D = P.D; J.k = P.k; J.T = P.T; J.L = P.L; J.nl = P.nl;
+    J.rows_off = rows; J.rstride = P.rstride;
+    rows += 2 * P.rstride;
+    J.coef_off = (int64_t)coefw; coefw += (size_t)P.T * P.nl;
+    const size_t n1 = (size_t)P.D + 1;
+    J.res_off = (int64_t)w; w += align_words((size_t)P.k * P.T);
+    J.val_off = (int64_t)w; w += align_words((size_t)P.k * n1);
+    J.dig_off = (int64_t)w; w += align_words(n1 * P.k);
+    J.acc_off = (int64_t)w; w += align_words(n1 * (size_t)lx_of(P.k));
+    lay.nb_red += (int64_t)P.k * ((P.T + 255) / 256);
+    lay.nb_interp += P.k;
+    lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
+    lay.nb_crtc += (int64_t)((n1 + 255) / 256);
+    if (P.cls >= 0) lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
+    else lay.n_gen_inst += (int64_t)P.k * n1;
+    lay.total_inst += (int64_t)P.k * n1;
+    lay.max_D = std::max(lay.max_D, P.D);
+  }
+  lay.abn_count_off = w * 4; w += 64;
+  lay.abn_list_off = w * 4;
+  lay.abn_cap = (uint32_t)std::min<int64_t>(lay.total_inst, 0x7fffffff);
+  w += align_words((size_t)lay.total_inst * (sizeof(AbnEntry) / 4));
+  lay.out_off = w * 4;
+  size_t ow = 0;
+  for (int j = 0; j < NJ; ++j) {
+    const ResPlan& P = plans[lay.dev[j]];
+    lay.jobs[j].out_off = (int64_t)(w + ow);
+    ow += ((size_t)P.D + 1) * P.L;
+  }
+  lay.out_words = ow;
+  w += align_words(ow);
+  lay.total_bytes = w * 4;
+}
+
+namespace {
+
+struct StageTimer {
+  snc_ctx* c;
+  hipStream_t s;
+  bool on;
+  int n = 0;
+  void start() {
+    if (!on) return;
+    c->stage_names.clear(); c->stage_ms.clear(); c->stage_launches.clear();
+    mark(nullptr, 0);
+  }
+  void mark(const char* name, int launches) {
+    if (!on) return;
+    if ((int)c->events.size() <= n) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      c->events.push_back(e);
+    }
+    (void)hipEventRecord(c->events[n], s);
+    if (name) { c->stage_names.push_back(name); c->stage_launches.push_back(launches); }
+    ++n;
+  }
+  void finish() {
+    if (!on) return;
+    for (int i = 1; i < n; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, c->events[i - 1], c->events[i]);
+      c->stage_ms.push_back(ms);
+    }
+  }
+};
+
+// Device launch sequence for a laid-out batch (everything after the upload).
+void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm) {
+  uint32_t* wsw = (uint32_t*)ws;
+  const ResJob* jobs = (const ResJob*)(ws + lay.jobs_off);
+  const RowDesc* rows = (const RowDesc*)(ws + lay.rows_off);
+  const int NJ = (int)lay.jobs.size();
+  uint32_t* abn_count = (uint32_t*)(ws + lay.abn_count_off);
+  AbnEntry* abn_list = (AbnEntry*)(ws + lay.abn_list_off);
+  launch_zero_u32(abn_count, 1, s);
+  launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, s);
+  if (tm) tm->mark("reduce", 1);
+  int nee = 0;
+  for (int c = 0; c < NCLS; ++c) {
+    if (!lay.n_ee_jobs[c]) continue;
+    launch_eval_elim(c, jobs, (const int32_t*)(ws + lay.list_ee[c]), (const int64_t*)(ws + lay.pref_ee[c]),
+                     lay.n_ee_jobs[c], lay.nb_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap, s);
+    ++nee;
+  }
+  if (lay.n_gen_jobs) {
+    launch_elim_general_all(jobs, (const int32_t*)(ws + lay.list_gen), (const int64_t*)(ws + lay.pref_gen),
+                            lay.n_gen_jobs, lay.n_gen_inst, rows, wsw, s);
+    ++nee;
+  }
+  if (tm) tm->mark("eval_elim", nee);
+  launch_elim_general(jobs, rows, wsw, abn_count, abn_list,
+                      (int)std::min<int64_t>(std::max<int64_t>(lay.total_inst, 64), 16384), s);
+  if (tm) tm->mark("elim_general", 1);
+  launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, s);
+  if (tm) tm->mark("interp", 1);
+  const CrtTables tb = global_crt_tables();
+  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
+  if (tm) tm->mark("crt_digits", 1);
+  launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, wsw, s);
+  if (tm) tm->mark("crt_combine", 1);
+}
+
+// Fill the upload block: job descriptors, row descriptors, block prefixes,
+// class job lists and the packed input coefficients.
+void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, const std::vector<Operand>& F,
+                 const std::vector<Operand>& G, uint8_t* h) {
+  const int NJ = (int)lay.dev.size();
+  std::memcpy(h + lay.jobs_off, lay.jobs.data(), sizeof(ResJob) * NJ);
+  RowDesc* rows = (RowDesc*)(h + lay.rows_off);
+  uint32_t* coef = (uint32_t*)(h + lay.coef_off);
+  int64_t* pr = (int64_t*)(h + lay.pref_red);
+  int64_t* pi = (int64_t*)(h + lay.pref_interp);
+  int64_t* pd = (int64_t*)(h + lay.pref_crtd);
+  int64_t* pc = (int64_t*)(h + lay.pref_crtc);
+  int64_t* pe[NCLS];
+  int32_t* le[NCLS];
+  int ne[NCLS] = {0};
+  for (int c = 0; c < NCLS; ++c) {
+    pe[c] = (int64_t*)(h + lay.pref_ee[c]);
+    le[c] = (int32_t*)(h + lay.list_ee[c]);
+    pe[c][0] = 0;
+  }
+  int64_t* pg = (int64_t*)(h + lay.pref_gen);
+  int32_t* lg = (int32_t*)(h + lay.list_gen);
+  int ng = 0;
+  pg[0] = 0;
+  pr[0] = pi[0] = pd[0] = pc[0] = 0;
+  size_t cw = 0;
+  for (int j = 0; j < NJ; ++j) {
+    const int idx = lay.dev[j];
+    const ResPlan& P = plans[idx];
+    const ResJob& J = lay.jobs[j];
+    const Operand& A = P.swap ? G[idx] : F[idx];
+    const Operand& B = P.swap ? F[idx] : G[idx];
+    RowDesc* ra = rows + J.rows_off;
+    int off = 0;
+    auto emit = [&](const Operand& O, RowDesc* rd, int deg) {
+      for (int t = 0; t < P.rstride; ++t) {
+        rd[t].off = 0; rd[t].len = 0;
+        if (t > deg) continue;
+        const int row = deg - t;
+        const int len = O.rowdeg[row] + 1;
+        rd[t].off = off; rd[t].len = len;
+        for (int k = 0; k < len; ++k) {
+          const uint32_t* src = O.limbs + ((size_t)row * (O.dx + 1) + k) * O.nl;
+          uint32_t* dst = coef + cw + (size_t)(off + k) * P.nl;
+          const uint32_t ext = (src[O.nl - 1] >> 31) ? 0xffffffffu : 0u;
+          for (int l = 0; l < P.nl; ++l) dst[l] = l < O.nl ? src[l] : ext;
+        }
+        off += len;
+      }
+    };
+    emit(A, ra, P.m);
+    emit(B, ra + P.rstride, P.n);
+    cw += (size_t)P.T * P.nl;
+    const int64_t n1 = P.D + 1;
+    pr[j + 1] = pr[j] + (int64_t)P.k * ((P.T + 255) / 256);
+    pi[j + 1] = pi[j] + P.k;
+    pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+    pc[j + 1] = pc[j] + (n1 + 255) / 256;
+    if (P.cls >= 0) {
+      const int c = P.cls;
+      le[c][ne[c]] = j;
+      pe[c][ne[c] + 1] = pe[c][ne[c]] + (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
+      ne[c]++;
+    } else {
+      lg[ng] = j;
+      pg[ng + 1] = pg[ng] + (int64_t)P.k * n1;
+      ng++;
+    }
+  }
+}
+
+void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& key) {
+  key.clear();
+  key.push_back((int64_t)(intptr_t)ws);
+  key.push_back((int64_t)lay.total_bytes);
+  key.push_back((int64_t)lay.jobs.size());
+  key.push_back(lay.nb_red); key.push_back(lay.nb_interp); key.push_back(lay.nb_crtd);
+  key.push_back(lay.nb_crtc); key.push_back(lay.n_gen_inst); key.push_back(lay.max_D);
+  key.push_back(lay.total_inst);
+  for (int c = 0; c < NCLS; ++c) { key.push_back(lay.nb_ee[c]); key.push_back(lay.n_ee_jobs[c]); }
+  key.push_back(lay.n_gen_jobs);
+  key.push_back((int64_t)lay.abn_count_off); key.push_back((int64_t)lay.abn_list_off);
+  for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_crtd, lay.pref_crtc,
+                   lay.pref_gen, lay.list_gen})
+    key.push_back((int64_t)o);
+  for (int c = 0; c < NCLS; ++c) { key.push_back((int64_t)lay.pref_ee[c]); key.push_back((int64_t)lay.list_ee[c]); }
+}
+
+}  // namespace
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) {                                                           \
+      c->err = std::string(#x) + ": " + hipGetErrorString(e_);                        \
+      return SNC_EDEVICE;                                                             \
+    }                                                                                 \
+  } while (0)
+
+int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                   size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph) {
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<Operand> F(n), G(n);
+  std::vector<ResPlan> P(n);
+  for (int i = 0; i < n; ++i) {
+    int st = parse_bipoly(&f[i], F[i], c->err);
+    if (!st) st = parse_bipoly(&g[i], G[i], c->err);
+    if (!st) st = plan_resultant(F[i], G[i], P[i], c->err);
+    if (st) { c->err = "pair " + std::to_string(i) + ": " + c->err; return st; }
+  }
+  bool range_err = false;
+  for (int i = 0; i < n; ++i) {
+    const int need_deg = P[i].trivial ? (P[i].trivial_value ? 0 : -1) : P[i].D;
+    const int need_nl = P[i].trivial ? 1 : P[i].L;
+    if (out[i].deg < need_deg || out[i].nlimbs < need_nl || (need_deg >= 0 && !out[i].limbs)) {
+      out[i].deg = need_deg;
+      out[i].nlimbs = need_nl;
+      range_err = true;
+    }
+  }
+  if (range_err) { c->err = "output buffer too small"; return SNC_ERANGE; }
+  BatchLayout lay;
+  layout_batch(P, lay);
+  // trivial results
+  for (int i = 0; i < n; ++i) {
+    if (!P[i].trivial) continue;
+    if (P[i].trivial_value) {
+      for (int l = 0; l < out[i].nlimbs; ++l) out[i].limbs[l] = l == 0 ? 1u : 0u;
+      out[i].deg = 0;
+    } else {
+      out[i].deg = -1;
+    }
+  }
+  if (lay.dev.empty()) return SNC_OK;
+  if (!d_ws || ws_bytes < lay.total_bytes) {
+    c->err = "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(lay.total_bytes);
+    return SNC_ENOMEM;
+  }
+  uint8_t* ws = (uint8_t*)d_ws;
+  if (c->stage_in(lay.header_bytes) || c->stage_out(lay.out_words * 4)) { c->err = "pinned staging allocation failed"; return SNC_EDEVICE; }
+  fill_header(lay, P, F, G, (uint8_t*)c->h_in);
+  StageTimer tm{c, stream, c->timing && !use_graph};
+  tm.start();
+  HIPCHK(hipMemcpyAsync(ws, c->h_in, lay.header_bytes, hipMemcpyHostToDevice, stream));
+  tm.mark("h2d", 1);
+  if (use_graph) {
+    std::vector<int64_t> key;
+    launch_key(lay, ws, key);
+    if (!c->gexec || key != c->gkey) {
+      if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+      if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      launch_pipeline(lay, ws, c->cap_stream, nullptr);
+      HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+      hipError_t e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) { c->gexec = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
+      c->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(c->gexec, stream));
+  } else {
+    launch_pipeline(lay, ws, stream, tm.on ? &tm : nullptr);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->h_out, ws + lay.out_off, lay.out_words * 4, hipMemcpyDeviceToHost, stream));
+  tm.mark("d2h", 1);
+  HIPCHK(hipStreamSynchronize(stream));
+  tm.finish();
+  // unpack
+  const uint32_t* ho = (const uint32_t*)c->h_out;
+  const size_t base = lay.out_off / 4;
+  for (int j = 0; j < (int)lay.dev.size(); ++j) {
+    const int i = lay.dev[j];
+    const ResJob& J = lay.jobs[j];
+    const uint32_t* src = ho + (J.out_off - base);
+    int deg = -1;
+    for (int t = J.D; t >= 0 && deg < 0; --t)
+      for (int l = 0; l < J.L; ++l)
+        if (src[(size_t)t * J.L + l]) { deg = t; break; }
+    const int stride = out[i].nlimbs;
+    for (int t = 0; t <= deg; ++t) {
+      const uint32_t* s = src + (size_t)t * J.L;
+      uint32_t* d = out[i].limbs + (size_t)t * stride;
+      const uint32_t ext = (s[J.L - 1] >> 31) ? 0xffffffffu : 0u;
+      for (int l = 0; l < stride; ++l) d[l] = l < J.L ? s[l] : ext;
+    }
+    out[i].deg = deg;
+  }
+  return SNC_OK;
+}
+
+}  // namespace snc

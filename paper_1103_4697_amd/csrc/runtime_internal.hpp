@@ -1,0 +1,97 @@
+// Host-side structures of the runtime: parsed operands, plans, workspace
+// layout and the context object behind the opaque snc_ctx handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "snc.h"
+#include "snc_internal.hpp"
+
+namespace snc {
+
+constexpr int NCLS = 5;        // register classes of the fused evaluate+eliminate kernel
+constexpr int MAX_D = 13000;   // interpolation keeps 3(D+1) words in LDS
+
+struct Tables {
+  std::vector<uint32_t> p;       // primes, descending below 2^30
+  std::vector<PrimeC> pc;        // Montgomery constants
+  std::vector<double> lg;        // lg[k] = sum_{i<k} log2 p_i
+  std::vector<uint32_t> garner;  // Montgomery form of (P_i mod p_i)^-1
+  std::vector<uint32_t> wtab;    // [j*KMAX+i] Montgomery form of P_j mod p_i
+  std::vector<uint32_t> ptab;    // [(KMAX+1)][LPS] limbs of P_j
+};
+const Tables& tables();
+int ensure_device_tables(int device, std::string& err);
+
+struct Operand {
+  int dy = -1, dx = -1, nl = 1;
+  const uint32_t* limbs = nullptr;
+  int ydeg = -1;               // y-degree over Z[x], -1 for zero
+  std::vector<int> rowdeg;     // x-degree per row (-1 zero row), size ydeg+1
+  int total_deg = -1, max_rowdeg = -1;
+  double log2S = 0.0;          // upper bound on log2(sum_i ||f_i||_1^2)
+};
+
+struct ResPlan {
+  int trivial = 0, trivial_value = 0;   // f or g zero -> 0; both constant in y -> 1
+  int swap = 0;                         // A = g (m < n)
+  int m = 0, n = 0, D = 0, k = 0, L = 1, T = 0, nl = 1, cls = -1, rstride = 0;
+  double log2B = 0.0;
+};
+
+inline size_t align_words(size_t w) { return (w + 63) & ~(size_t)63; }  // 256-byte sections
+
+struct BatchLayout {
+  std::vector<int> dev;              // plan index of each device job
+  std::vector<ResJob> jobs;          // device job descriptors (offsets filled)
+  size_t jobs_off = 0, rows_off = 0, coef_off = 0;        // bytes
+  size_t pref_red = 0, pref_interp = 0, pref_crtd = 0, pref_crtc = 0, pref_gen = 0;  // bytes
+  size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes
+  size_t header_bytes = 0;
+  size_t abn_count_off = 0, abn_list_off = 0;              // bytes
+  uint32_t abn_cap = 0;
+  size_t out_off = 0, out_words = 0;                       // bytes / words
+  size_t total_bytes = 0;
+  int64_t nb_red = 0, nb_interp = 0, nb_crtd = 0, nb_crtc = 0, n_gen_inst = 0;
+  int64_t nb_ee[NCLS] = {0};
+  int n_ee_jobs[NCLS] = {0}, n_gen_jobs = 0, n_rows = 0, max_D = 0;
+  int64_t total_inst = 0;
+  size_t coef_words = 0;
+};
+
+void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay);
+size_t job_region_words(const ResPlan& P);
+int parse_bipoly(const snc_bipoly* f, Operand& op, std::string& err);
+int plan_resultant(const Operand& F, const Operand& G, ResPlan& P, std::string& err);
+
+}  // namespace snc
+
+struct snc_ctx {
+  int device = 0;
+  std::string err;
+  bool timing = false;
+  std::vector<const char*> stage_names;
+  std::vector<float> stage_ms;
+  std::vector<int> stage_launches;
+  std::vector<hipEvent_t> events;
+  // pinned host staging
+  void* h_in = nullptr;
+  size_t h_in_bytes = 0;
+  void* h_out = nullptr;
+  size_t h_out_bytes = 0;
+  // captured pipeline of the last batch shape
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> gkey;
+
+  int stage_in(size_t bytes);
+  int stage_out(size_t bytes);
+  void release();
+};
+
+namespace snc {
+int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                   size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph);
+}

@@ -1,0 +1,116 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modp.hpp"
+
+namespace snc {
+
+constexpr int KMAX = 1024;        // primes in the modulus table (log2 of their product ~ 30700)
+constexpr int LPS = 964;          // limb stride of the prime-product table (30*1024/32 + 4)
+constexpr int MAXY_FAST = 64;     // largest y-degree handled by the register-resident elimination
+constexpr int MAXY_GEN = 255;     // largest y-degree handled at all
+constexpr int EE_WAVES = 1;       // wavefronts per eval_elim workgroup
+constexpr int EE_BLOCK = 64 * EE_WAVES;
+constexpr int INTERP_THREADS = 256;
+constexpr int CRT_COEF_PER_BLOCK = 4;   // one wavefront per coefficient
+constexpr int GCD_THREADS = 256;
+
+// One resultant res_y(f, g).  A is the operand of larger y-degree (m >= n);
+// rows of A and B are listed top-down (row m of A first) so that the
+// register arrays of the elimination are "top-aligned".
+struct ResJob {
+  int32_t m, n;        // y-degrees of A and B over Z[x], m >= 1, m >= n >= 0
+  int32_t sign;        // 1: operands were swapped and m*n is odd (result negated)
+  int32_t D;           // evaluation points x_j = j, j = 0..D
+  int32_t k;           // primes 0..k-1 of the table
+  int32_t T;           // residues per prime (coefficients of f and g)
+  int32_t L;           // output limbs per coefficient
+  int32_t nl;          // limbs per input coefficient
+  int32_t rows_off;    // first RowDesc of A (rstride entries, rows m..0 then len-0 padding), then B
+  int32_t rstride;     // RowDescs per operand (register class width + 1, or max(m, n) + 1)
+  int64_t coef_off;    // input limbs [T][nl] (uint32 index)
+  int64_t res_off;     // residues [k][T] (uint32 index)
+  int64_t val_off;     // values at points, then coefficients mod p: [k][D+1]
+  int64_t dig_off;     // mixed-radix digits [D+1][k]
+  int64_t acc_off;     // CRT accumulator [D+1][LX] with LX = lx_of(k)
+  int64_t out_off;     // output limbs [D+1][L]
+};
+
+struct RowDesc {
+  int32_t off;  // first residue of the row within a prime's block of T
+  int32_t len;  // number of x-coefficients (degree + 1, 0 for a zero row)
+};
+
+// Constant tables of a Chinese-remainder reconstruction over primes
+// q_0..q_{k-1}: garner[i] = Montgomery form of (Q_i mod q_i)^-1 and
+// wtab[j*wstride + i] = Montgomery form of Q_j mod q_i with Q_j = prod_{l<j} q_l;
+// ptab row j (pstride limbs) = Q_j.
+struct CrtTables {
+  const PrimeC* primes;
+  const uint32_t* garner;
+  const uint32_t* wtab;
+  const uint32_t* ptab;
+  int32_t wstride, pstride;
+};
+
+// One gcd problem in Z[x]: a and b of degrees da, db >= 1; its primes are
+// "slots" (table index per slot), filled in rounds of nslots starting at slot0.
+struct GcdDesc {
+  int32_t da, db;          // degrees of a and b
+  int32_t nl;              // limbs per input coefficient
+  int32_t slot0;           // first slot of this round
+  int32_t wl;              // row length of w: min(da, db) + 1
+  int32_t pad;
+  int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl] (uint32 index)
+  int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
+  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a)^-1, cont(b)^-1, beta mod p (plain)
+  int64_t res_off;         // residues [slot][da+db+2] (Montgomery)
+  int64_t e_off;           // int32 per slot: degree of the gcd mod p
+  int64_t w_off;           // [slot][wl]   beta * monic gcd mod p (plain)
+  int64_t u_off;           // [slot][da+1] cofactor of a mod p (plain)
+  int64_t v_off;           // [slot][db+1] cofactor of b mod p (plain)
+};
+
+// abnormal (prime, point) instance queued for the general elimination
+struct AbnEntry {
+  int32_t job, prime, point, pad;
+};
+
+__host__ __device__ inline int lx_of(int k) { return (30 * k + 31) / 32 + 2; }
+
+// launchers (kernels_res.hip)
+void upload_tables(const PrimeC* primes, const uint32_t* garner_c, const uint32_t* wtab,
+                   const uint32_t* ptab, hipStream_t s);
+hipError_t configure_kernels();
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
+                   const uint32_t* ws, uint32_t* res_base, hipStream_t s);
+void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
+                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, const RowDesc* rows_d,
+                      uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
+                      hipStream_t s);
+void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,
+                         const uint32_t* abn_count, const AbnEntry* abn_list, int nthreads,
+                         hipStream_t s);
+void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
+                             const int64_t* inst_prefix_d, int njobs, int64_t ninst,
+                             const RowDesc* rows_d, uint32_t* ws, hipStream_t s);
+void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
+                   int max_D, uint32_t* ws, hipStream_t s);
+void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
+                       int64_t nblocks, uint32_t* ws, hipStream_t s);
+void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
+                        int64_t nblocks, uint32_t* ws, hipStream_t s);
+CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
+
+void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);
+void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, int ks, int e, uint32_t* ws, int64_t wv,
+                       int64_t uv, int64_t vv, hipStream_t s);
+hipError_t configure_gcd_kernels();
+
+int fast_class_of(int maxy);  // index of the register class for a y-degree, -1 if none
+int fast_class_cap(int cls);
+
+}  // namespace snc

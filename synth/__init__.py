@@ -93,7 +93,7 @@ def bivariate_product(A, B) -> list[list[int]]:
     A = [[int(c) for c in row] for row in A]
     B = [[int(c) for c in row] for row in B]
     ny = len(A) + len(B) - 1
-    nx = len(A[0]) + len(B[0]) - 1
+    nx = max(len(r) for r in A) + max(len(r) for r in B) - 1
     C = [[0] * nx for _ in range(ny)]
     for i, ra in enumerate(A):
         for k, a in enumerate(ra):

@@ -1,0 +1,107 @@
+"""GPU parity of gcd(a, b) in Z[x] through the C ABI against the CPU oracle
+(Euclid over Q where it is fast enough, the oracle's certificate at larger
+sizes).  Results are exact integers compared bit for bit."""
+import json
+import os
+import random
+from math import gcd as igcd
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gcd as G
+from oracle import resultant as R
+from oracle import zx
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def snc():
+    import paper_1103_4697_amd as m
+    return m
+
+
+def rpoly(rng, deg, bits):
+    lim = 1 << (bits - 1)
+    c = [rng.randrange(-lim, lim) for _ in range(deg + 1)]
+    if c[-1] == 0:
+        c[-1] = 1
+    return c
+
+
+def test_golden(snc):
+    data = json.load(open(os.path.join(GOLDEN, "worked_examples.json")))
+    for ex in data["gcds"]:
+        assert snc.gcd_z(ex["a"], ex["b"]) == ex["gcd"], ex["name"]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_by_construction_vs_euclid(snc, seed):
+    rng = random.Random(100 + seed)
+    h = rpoly(rng, rng.randint(0, 8), rng.choice([4, 16, 40]))
+    u = rpoly(rng, rng.randint(0, 30), rng.choice([8, 32, 70]))
+    v = rpoly(rng, rng.randint(0, 30), rng.choice([8, 32, 70]))
+    if seed % 3 == 0:
+        u = zx.scale(u, 6)
+        v = zx.scale(v, 10)
+    a, b = synth.univariate_product(h, u), synth.univariate_product(h, v)
+    got = snc.gcd_z(a, b)
+    assert got == G.gcd_zx(a, b)
+
+
+def test_special_cases(snc):
+    assert snc.gcd_z([], []) == []
+    assert snc.gcd_z([0, -2, -4], []) == [0, 2, 4]
+    assert snc.gcd_z([], [-7]) == [7]
+    assert snc.gcd_z([12], [0, 18, 6]) == [6]
+    assert snc.gcd_z([4, 0, 2], [-6]) == [2]
+    assert snc.gcd_z([1, 1], [1, 1]) == [1, 1]
+    assert snc.gcd_z([-3, -3], [6, 6]) == [3, 3]
+
+
+def test_unlucky_prime_and_lc_divisible(snc):
+    p0 = snc.prime(0)
+    rng = random.Random(5)
+    u = rpoly(rng, 12, 20)
+    v = rpoly(rng, 9, 20)
+    lin = [1, 1]
+    # b = v (x+1) + p0 x^3: coprime to a = u (x+1) over Q, common factor mod p0
+    a = synth.univariate_product(u, lin)
+    b = zx.add(synth.univariate_product(v, lin), [0, 0, 0, p0])
+    assert snc.gcd_z(a, b) == G.gcd_zx(a, b)
+    # same with a shared factor h: the gcd is h, prime p0 sees h (x+1)
+    h = rpoly(rng, 4, 16)
+    a2 = synth.univariate_product(h, a)
+    b2 = synth.univariate_product(h, b)
+    assert snc.gcd_z(a2, b2) == G.gcd_zx(a2, b2)
+    # leading coefficients divisible by p0 (p0 divides beta: that prime is skipped)
+    a3 = synth.univariate_product(h, u[:-1] + [p0 * 3])
+    b3 = synth.univariate_product(h, v[:-1] + [p0 * 5])
+    assert snc.gcd_z(a3, b3) == G.gcd_zx(a3, b3)
+
+
+def test_resultant_squarefree_config0(snc):
+    f, g = synth.config0()
+    r = snc.resultant_y(f, g)
+    rp = zx.deriv(r)
+    assert snc.gcd_z(r, rp) == G.gcd_zx(r, rp)
+
+
+def test_config1_squarefree_against_golden(snc):
+    ref = json.load(open(os.path.join(GOLDEN, "config1.json")))
+    f, g = synth.config1()
+    r = snc.resultant_y(f, g)
+    gg = snc.gcd_z(r, zx.deriv(r))
+    assert gg == [int(c) for c in ref["gcd_r_rprime"]]
+
+
+@pytest.mark.parametrize("target,dh", [(300, 12), (1200, 40)])
+def test_serving_shape_certified(snc, target, dh):
+    rng = np.random.default_rng(target)
+    a, b, h = synth.gcd_request(rng, target, target, dh, dh, 8, 32)
+    got = snc.gcd_z(a, b)
+    assert zx.deg(got) >= dh
+    assert G.certify_gcd(a, b, got)

@@ -1,0 +1,180 @@
+"""GPU parity of res_y(f, g) through the C ABI against the CPU oracle.
+
+Exact integers: every comparison is bit-identical (tolerance 0).
+* small and medium random pairs (several point tiles, ragged tails, all
+  register classes, multi-limb coefficients) against the oracle;
+* edge cases: zero operands, constants in y, swapped degrees, leading
+  coefficients vanishing at a point or modulo a table prime, a root shared
+  at x = 0, a common factor, y-degree above the register classes;
+* the curve-analysis workload against stored oracle values;
+* the large workload on sampled outputs (exact bottom and top coefficients,
+  values modulo 61-bit primes at random points).
+"""
+import hashlib
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import resultant as R
+from oracle import zx
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+Q61 = (1 << 61) - 1
+
+
+@pytest.fixture(scope="module")
+def snc():
+    import paper_1103_4697_amd as m
+    return m
+
+
+def rand_pair(rng, m, n, dxf, dxg, bits):
+    lim = 1 << (bits - 1)
+
+    def draw(dy, dx):
+        rows = [[int(v) for v in rng.integers(-lim, lim, size=dx + 1, dtype=np.int64)] if bits <= 63
+                else [random.Random(int(rng.integers(1 << 30))).randrange(-lim, lim) for _ in range(dx + 1)]
+                for _ in range(dy + 1)]
+        if all(v == 0 for v in rows[-1]):
+            rows[-1][0] = 1
+        return rows
+    return draw(m, dxf), draw(n, dxg)
+
+
+def check(snc, f, g, ref=None):
+    got = snc.resultant_y(f, g)
+    if ref is None:
+        ref = R.resultant_y_by_points(f, g, processes=1)
+    assert got == ref
+    return got
+
+
+def test_config0_exact(snc):
+    f, g = synth.config0()
+    assert snc.resultant_y(f, g) == R.resultant_y(f, g)
+
+
+@pytest.mark.parametrize("seed", range(14))
+def test_random_parity(snc, seed):
+    rng = np.random.default_rng(5000 + seed)
+    m = int(rng.integers(0, 13))
+    n = int(rng.integers(0, 13))
+    dxf = int(rng.integers(0, 9))
+    dxg = int(rng.integers(0, 9))
+    bits = [8, 20, 32, 63, 100][seed % 5]
+    f, g = rand_pair(rng, m, n, dxf, dxg, bits)
+    if seed % 4 == 1 and m > 0:
+        f[m - 1] = [0] * (dxf + 1)           # a zero row inside
+    check(snc, f, g)
+
+
+def test_register_classes_and_ragged_tiles(snc):
+    # y-degrees hitting each register class (<=8, <=16, <=32, <=48, <=64)
+    rng = np.random.default_rng(77)
+    for m, n, dx in [(8, 5, 3), (16, 9, 2), (20, 20, 1), (40, 33, 1), (60, 2, 1)]:
+        f, g = rand_pair(rng, m, n, dx, dx, 16)
+        check(snc, f, g)
+
+
+def test_edge_cases(snc):
+    one = [[1]]
+    f = [[3, 1], [0, 2], [1]]
+    assert snc.resultant_y([[0]], f) == []                         # f = 0
+    assert snc.resultant_y(f, [[0], [0]]) == []                    # g = 0
+    assert snc.resultant_y([[2, 3]], [[7, 0, 1]]) == [1]            # m = n = 0
+    assert snc.resultant_y([[1, 1]], f) == R.resultant_y([[1, 1]], f)  # m = 0
+    assert snc.resultant_y(f, [[5, 0, 2]]) == R.resultant_y(f, [[5, 0, 2]])  # n = 0
+    assert snc.resultant_y(one, one) == [1]
+    # swapped degrees with m*n odd (sign)
+    rng = np.random.default_rng(3)
+    a, b = rand_pair(rng, 1, 3, 2, 2, 10)
+    check(snc, a, b)
+    check(snc, b, a)
+    # leading y-coefficient vanishing at x = 0 (formal degree kept there)
+    f2 = [[1, 2], [3, 0, 1], [0, 1]]
+    g2 = [[2, 1], [1, 1], [0, 0, 3]]
+    check(snc, f2, g2)
+    # f(0, y) and g(0, y) share the root y = 1: abnormal remainder at x = 0
+    f3 = [[-1, 2], [0, 1], [1, 3]]
+    g3 = [[-3, 1], [1, 1], [2, 0, 1]]
+    assert R.resultant_at(f3, g3, 0) == 0
+    check(snc, f3, g3)
+    # common factor: every instance degenerates, result 0
+    h = [[1, 1], [2], [1]]
+    ua = [[3], [1, 1]]
+    vb = [[-1, 2], [0, 0, 1], [1]]
+    fa = synth.bivariate_product(h, ua)
+    gb = synth.bivariate_product(h, vb)
+    assert snc.resultant_y(fa, gb) == []
+    # leading coefficient divisible by the first table prime
+    p0 = snc.prime(0)
+    f4 = [[1, 5, 7], [2, 1], [p0, 0, p0]]
+    g4 = [[3, 1, 1], [1, 0, 4], [1, 2], [5]]
+    check(snc, f4, g4)
+
+
+def test_general_path_above_register_classes(snc):
+    rng = np.random.default_rng(11)
+    f, g = rand_pair(rng, 70, 3, 1, 2, 12)
+    check(snc, f, g)
+
+
+def test_multilimb_and_mixed_widths(snc):
+    rng = random.Random(9)
+    f = [[rng.randrange(-(1 << 127), 1 << 127) for _ in range(3)] for _ in range(4)]
+    g = [[rng.randrange(-99, 99) for _ in range(4)] for _ in range(3)]
+    check(snc, f, g)
+    f64 = synth.dense_bivariate(np.random.default_rng(1), 5, bits=64)
+    check(snc, f64, g)
+
+
+def test_config1_against_golden(snc):
+    ref = json.load(open(os.path.join(GOLDEN, "config1.json")))
+    f, g = synth.config1()
+    r = snc.resultant_y(f, g)
+    assert len(r) - 1 == ref["degree"]
+    assert [c % Q61 for c in r] == ref["mod_2_61_minus_1"]
+    assert hashlib.sha256(",".join(str(c) for c in r).encode()).hexdigest() == ref["sha256"]
+    assert r[0] == R.resultant_at(f, g, 0)
+
+
+def test_config3_sampled(snc):
+    ref = json.load(open(os.path.join(GOLDEN, "config3.json")))
+    f, g = synth.config3()
+    r = snc.resultant_y(f, g)
+    assert len(r) - 1 <= ref["degree_bound"]
+    assert r[0] == int(ref["res_at_0"])
+    top = r[ref["top_degree"]] if len(r) > ref["top_degree"] else 0
+    assert top == int(ref["top_coefficient"])
+    assert len(r) - 1 == ref["top_degree"]
+    rng = random.Random(2024)
+    for q in (Q61, (1 << 61) - 31):
+        for _ in range(3):
+            x0 = rng.randrange(q)
+            assert zx.evaluate(r, x0) % q == R.resultant_at_mod(f, g, x0, q)
+
+
+def test_batch_matches_plain_and_oracle(snc):
+    pairs, common = synth.config2(npairs=48, frac_common=0.1)
+    batch = snc.resultant_y_batch(pairs)
+    for i, (f, g) in enumerate(pairs):
+        if i in common:
+            assert batch[i] == []
+    # plain path on a subset, oracle mod q on all pairs at one random point
+    for i in range(0, len(pairs), 6):
+        assert batch[i] == snc.resultant_y(*pairs[i])
+    rng = random.Random(7)
+    for i, (f, g) in enumerate(pairs):
+        x0 = rng.randrange(Q61)
+        assert zx.evaluate(batch[i], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
+    # replaying the captured graph gives the same results
+    b = snc.ResultantBatch(pairs)
+    b.run()
+    first = b.results()
+    b.run()
+    assert b.results() == first == batch
