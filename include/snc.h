@@ -87,6 +87,7 @@ typedef struct {
 } snc_plan;
 
 typedef struct snc_ctx snc_ctx;
+typedef struct snc_prepared snc_prepared;
 typedef struct snc_server snc_server;
 
 /* Version of this interface (major*10000 + minor*100 + patch). */
@@ -124,6 +125,18 @@ int snc_resultant_y_batch_plan(int32_t n, const snc_bipoly* f, const snc_bipoly*
                                snc_plan* out_each /* n entries or NULL */, snc_plan* out_total);
 int snc_resultant_y_batch(snc_ctx* ctx, int32_t n, const snc_bipoly* f, const snc_bipoly* g,
                           void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
+
+/* Prepared resultants: plan n pairs and upload their inputs into the device
+ * workspace once (the workspace must stay valid and untouched until the
+ * handle is destroyed); each run then executes only the device pipeline,
+ * captured as a HIP graph on the first run and replayed, and writes the n
+ * results into out (same conventions as snc_resultant_y_batch).  For callers
+ * that keep inputs resident and recompute, and for timing the device path
+ * without the input transfer.  A handle belongs to its context's thread. */
+int snc_resultant_y_prepare(snc_ctx* ctx, int32_t n, const snc_bipoly* f, const snc_bipoly* g,
+                            void* d_ws, size_t ws_bytes, void* stream, snc_prepared** out);
+int snc_prepared_run(snc_prepared* prep, void* stream, snc_upoly* out);
+int snc_prepared_destroy(snc_prepared* prep);
 
 /* ---- gcd in Z[x] ---------------------------------------------------------
  * Modular (small primes) gcd: contents on the host, monic gcd and cofactors

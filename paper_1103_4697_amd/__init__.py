@@ -69,6 +69,9 @@ def lib():
                 "snc_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_resultant_y_batch_plan": (C.c_int, [I32, P(Bipoly), P(Bipoly), P(Plan), P(Plan)]),
                 "snc_resultant_y_batch": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
+                "snc_resultant_y_prepare": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(VP)]),
+                "snc_prepared_run": (C.c_int, [VP, VP, P(Upoly)]),
+                "snc_prepared_destroy": (C.c_int, [VP]),
                 "snc_gcd_z_plan": (C.c_int, [P(Upoly), P(Upoly), P(Plan)]),
                 "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
             }
@@ -281,10 +284,12 @@ def resultant_y(f, g, ctx: Context | None = None, stream=None) -> list:
 
 
 class ResultantBatch:
-    """A prepared batch of resultants: marshalled once, run many times
-    (the device pipeline is captured once as a HIP graph and replayed)."""
+    """A prepared batch of resultants: planned and uploaded once into a device
+    workspace owned by this object, then run any number of times (the device
+    pipeline is captured as a HIP graph on the first run and replayed)."""
 
-    def __init__(self, pairs, ctx: Context | None = None):
+    def __init__(self, pairs, ctx: Context | None = None, stream=None):
+        import torch
         self.ctx = ctx or default_context()
         self.keep = []
         n = len(pairs)
@@ -300,6 +305,7 @@ class ResultantBatch:
         if st != SNC_OK:
             raise SncError(st, "snc_resultant_y_batch_plan")
         self.plan = total
+        self.each = each
         self.out = (Upoly * n)()
         self.bufs = []
         self.caps = []
@@ -308,24 +314,63 @@ class ResultantBatch:
             self.out[i] = u
             self.bufs.append(buf)
             self.caps.append((each[i].deg_bound, each[i].out_nlimbs))
+        self.ws = torch.empty(max(total.workspace_bytes, 256), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        h = C.c_void_p()
+        st = lib().snc_resultant_y_prepare(self.ctx.h, n, self.F, self.G, C.c_void_p(self.ws.data_ptr()),
+                                           C.c_size_t(self.ws.numel()), self.ctx.stream_handle(stream), C.byref(h))
+        self.ctx.check(st, "snc_resultant_y_prepare")
+        self.h = h
 
     def run(self, stream=None):
         for i, (d, nl) in enumerate(self.caps):
             self.out[i].deg = d
             self.out[i].nlimbs = nl
-        ws = self.ctx.workspace(self.plan.workspace_bytes)
-        st = lib().snc_resultant_y_batch(self.ctx.h, self.n, self.F, self.G, C.c_void_p(ws.data_ptr()),
-                                         C.c_size_t(ws.numel()), self.ctx.stream_handle(stream), self.out)
-        self.ctx.check(st, "snc_resultant_y_batch")
+        st = lib().snc_prepared_run(self.h, self.ctx.stream_handle(stream), self.out)
+        self.ctx.check(st, "snc_prepared_run")
+
+    def degrees(self):
+        return [self.out[i].deg for i in range(self.n)]
 
     def results(self):
         return [_read_upoly(self.out[i], self.bufs[i]) for i in range(self.n)]
 
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snc_prepared_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 def resultant_y_batch(pairs, ctx: Context | None = None, stream=None) -> list:
-    b = ResultantBatch(pairs, ctx)
-    b.run(stream)
-    return b.results()
+    """n resultants in one submission (every stage launched once over all
+    pairs, as one HIP graph)."""
+    ctx = ctx or default_context()
+    keep = []
+    n = len(pairs)
+    F = (Bipoly * n)()
+    G = (Bipoly * n)()
+    for i, (f, g) in enumerate(pairs):
+        F[i] = _as_bipoly(f, keep)
+        G[i] = _as_bipoly(g, keep)
+    each = (Plan * n)()
+    total = Plan()
+    ctx.check(lib().snc_resultant_y_batch_plan(n, F, G, each, C.byref(total)), "batch plan")
+    out = (Upoly * n)()
+    bufs = []
+    for i in range(n):
+        u, buf = _out_upoly(each[i].deg_bound, each[i].out_nlimbs, keep)
+        out[i] = u
+        bufs.append(buf)
+    ws = ctx.workspace(total.workspace_bytes)
+    st = lib().snc_resultant_y_batch(ctx.h, n, F, G, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()),
+                                     ctx.stream_handle(stream), out)
+    ctx.check(st, "snc_resultant_y_batch")
+    return [_read_upoly(out[i], bufs[i]) for i in range(n)]
 
 
 # ---------------------------------------------------------------------------
@@ -345,6 +390,45 @@ def gcd_z(a, b, ctx: Context | None = None, stream=None) -> list:
                          C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
     ctx.check(st, "snc_gcd_z")
     return _read_upoly(u, buf)
+
+
+def gcd_z_limbs(a_limbs: np.ndarray, b_limbs: np.ndarray, ctx: Context | None = None, stream=None):
+    """gcd on limb arrays (uint32 [deg+1][nl], two's complement): returns the
+    result as a uint32 [deg+1][nl] array (empty for the zero polynomial)."""
+    ctx = ctx or default_context()
+    a_limbs = np.ascontiguousarray(a_limbs, dtype=np.uint32)
+    b_limbs = np.ascontiguousarray(b_limbs, dtype=np.uint32)
+    ua, ub = Upoly(), Upoly()
+    ua.limbs = a_limbs.ctypes.data_as(C.POINTER(C.c_uint32)); ua.deg = a_limbs.shape[0] - 1; ua.nlimbs = a_limbs.shape[1]
+    ub.limbs = b_limbs.ctypes.data_as(C.POINTER(C.c_uint32)); ub.deg = b_limbs.shape[0] - 1; ub.nlimbs = b_limbs.shape[1]
+    p = Plan()
+    ctx.check(lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)), "gcd plan")
+    keep = []
+    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
+    ws = ctx.workspace(p.workspace_bytes)
+    st = lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
+                         C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
+    ctx.check(st, "snc_gcd_z")
+    return buf[: u.deg + 1]
+
+
+def derivative_limbs(a_limbs: np.ndarray) -> np.ndarray:
+    """Formal derivative of a limb array (two's complement, [deg+1][nl]) as a
+    [deg][nl+1] limb array: marshalling for gcd(R, R') without Python ints."""
+    a = np.ascontiguousarray(a_limbs, dtype=np.uint32)
+    n, nl = a.shape
+    if n <= 1:
+        return np.zeros((0, nl + 1), dtype=np.uint32)
+    ext = np.where(a[1:, -1:] >> 31, np.uint32(0xFFFFFFFF), np.uint32(0))
+    src = np.concatenate([a[1:], ext], axis=1).astype(np.uint64)
+    k = np.arange(1, n, dtype=np.uint64)
+    out = np.empty((n - 1, nl + 1), dtype=np.uint32)
+    carry = np.zeros(n - 1, dtype=np.uint64)
+    for l in range(nl + 1):
+        v = src[:, l] * k + carry
+        out[:, l] = (v & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        carry = v >> np.uint64(32)
+    return out
 
 
 def prime(i: int) -> int:

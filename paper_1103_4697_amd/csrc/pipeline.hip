@@ -291,17 +291,54 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
     }                                                                                 \
   } while (0)
 
-int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
-                   size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph) {
+int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                       size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp) {
+  *outp = nullptr;
   HIPCHK(hipSetDevice(c->device));
   std::vector<Operand> F(n), G(n);
-  std::vector<ResPlan> P(n);
+  snc_prepared* pr = new snc_prepared();
+  pr->c = c;
+  pr->n = n;
+  pr->use_graph = use_graph;
+  pr->P.resize(n);
   for (int i = 0; i < n; ++i) {
     int st = parse_bipoly(&f[i], F[i], c->err);
     if (!st) st = parse_bipoly(&g[i], G[i], c->err);
-    if (!st) st = plan_resultant(F[i], G[i], P[i], c->err);
-    if (st) { c->err = "pair " + std::to_string(i) + ": " + c->err; return st; }
+    if (!st) st = plan_resultant(F[i], G[i], pr->P[i], c->err);
+    if (st) { c->err = "pair " + std::to_string(i) + ": " + c->err; delete pr; return st; }
   }
+  layout_batch(pr->P, pr->lay);
+  const BatchLayout& lay = pr->lay;
+  if (!lay.dev.empty()) {
+    if (!d_ws || ws_bytes < lay.total_bytes) {
+      c->err = "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(lay.total_bytes);
+      delete pr;
+      return SNC_ENOMEM;
+    }
+    pr->ws = (uint8_t*)d_ws;
+    if (c->stage_in(lay.header_bytes)) { c->err = "pinned staging allocation failed"; delete pr; return SNC_EDEVICE; }
+    if (hipHostMalloc(&pr->h_out, std::max<size_t>(lay.out_words * 4, 4), hipHostMallocDefault) != hipSuccess) {
+      pr->h_out = nullptr;
+      c->err = "pinned staging allocation failed";
+      delete pr;
+      return SNC_EDEVICE;
+    }
+    fill_header(lay, pr->P, F, G, (uint8_t*)c->h_in);
+    StageTimer tm{c, stream, c->timing && !use_graph};
+    tm.start();
+    hipError_t e = hipMemcpyAsync(pr->ws, c->h_in, lay.header_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { c->err = std::string("input upload: ") + hipGetErrorString(e); delete pr; return SNC_EDEVICE; }
+  }
+  *outp = pr;
+  return SNC_OK;
+}
+
+int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  const int n = pr->n;
+  const std::vector<ResPlan>& P = pr->P;
+  const BatchLayout& lay = pr->lay;
   bool range_err = false;
   for (int i = 0; i < n; ++i) {
     const int need_deg = P[i].trivial ? (P[i].trivial_value ? 0 : -1) : P[i].D;
@@ -313,9 +350,6 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
     }
   }
   if (range_err) { c->err = "output buffer too small"; return SNC_ERANGE; }
-  BatchLayout lay;
-  layout_batch(P, lay);
-  // trivial results
   for (int i = 0; i < n; ++i) {
     if (!P[i].trivial) continue;
     if (P[i].trivial_value) {
@@ -326,43 +360,32 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
     }
   }
   if (lay.dev.empty()) return SNC_OK;
-  if (!d_ws || ws_bytes < lay.total_bytes) {
-    c->err = "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(lay.total_bytes);
-    return SNC_ENOMEM;
-  }
-  uint8_t* ws = (uint8_t*)d_ws;
-  if (c->stage_in(lay.header_bytes) || c->stage_out(lay.out_words * 4)) { c->err = "pinned staging allocation failed"; return SNC_EDEVICE; }
-  fill_header(lay, P, F, G, (uint8_t*)c->h_in);
-  StageTimer tm{c, stream, c->timing && !use_graph};
+  HIPCHK(hipSetDevice(c->device));
+  uint8_t* ws = pr->ws;
+  StageTimer tm{c, stream, c->timing && !pr->use_graph};
   tm.start();
-  HIPCHK(hipMemcpyAsync(ws, c->h_in, lay.header_bytes, hipMemcpyHostToDevice, stream));
-  tm.mark("h2d", 1);
-  if (use_graph) {
-    std::vector<int64_t> key;
-    launch_key(lay, ws, key);
-    if (!c->gexec || key != c->gkey) {
-      if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+  if (pr->use_graph) {
+    if (!pr->gexec) {
       if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
       launch_pipeline(lay, ws, c->cap_stream, nullptr);
       HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
-      hipError_t e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      hipError_t e = hipGraphInstantiate(&pr->gexec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) { c->gexec = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
-      c->gkey = key;
+      if (e != hipSuccess) { pr->gexec = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
     }
-    HIPCHK(hipGraphLaunch(c->gexec, stream));
+    HIPCHK(hipGraphLaunch(pr->gexec, stream));
+    if (tm.on) tm.mark("pipeline", 1);
   } else {
     launch_pipeline(lay, ws, stream, tm.on ? &tm : nullptr);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->h_out, ws + lay.out_off, lay.out_words * 4, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(pr->h_out, ws + lay.out_off, lay.out_words * 4, hipMemcpyDeviceToHost, stream));
   tm.mark("d2h", 1);
   HIPCHK(hipStreamSynchronize(stream));
   tm.finish();
-  // unpack
-  const uint32_t* ho = (const uint32_t*)c->h_out;
+  const uint32_t* ho = (const uint32_t*)pr->h_out;
   const size_t base = lay.out_off / 4;
   for (int j = 0; j < (int)lay.dev.size(); ++j) {
     const int i = lay.dev[j];
@@ -382,6 +405,23 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
     out[i].deg = deg;
   }
   return SNC_OK;
+}
+
+int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                   size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph) {
+  snc_prepared* pr = nullptr;
+  int st = prepare_resultants(c, n, f, g, d_ws, ws_bytes, stream, use_graph, &pr);
+  if (st) return st;
+  st = run_prepared(pr, stream, out);
+  destroy_prepared(pr);
+  return st;
+}
+
+void destroy_prepared(snc_prepared* pr) {
+  if (!pr) return;
+  if (pr->gexec) (void)hipGraphExecDestroy(pr->gexec);
+  if (pr->h_out) (void)hipHostFree(pr->h_out);
+  delete pr;
 }
 
 }  // namespace snc

@@ -297,7 +297,7 @@ int snc_resultant_y_plan(const snc_bipoly* f, const snc_bipoly* g, snc_plan* out
   out->out_nlimbs = P.trivial ? 1 : P.L;
   out->nprimes = P.trivial ? 0 : P.k;
   out->reserved = 0;
-  out->workspace_bytes = lay.total_bytes;
+  out->workspace_bytes = lay.dev.empty() ? 0 : lay.total_bytes;
   return SNC_OK;
 }
 
@@ -337,7 +337,24 @@ int snc_resultant_y_batch_plan(int32_t n, const snc_bipoly* f, const snc_bipoly*
   out_total->out_nlimbs = maxL;
   out_total->nprimes = maxk;
   out_total->reserved = 0;
-  out_total->workspace_bytes = lay.total_bytes;
+  out_total->workspace_bytes = lay.dev.empty() ? 0 : lay.total_bytes;
+  return SNC_OK;
+}
+
+int snc_resultant_y_prepare(snc_ctx* c, int32_t n, const snc_bipoly* f, const snc_bipoly* g,
+                            void* d_ws, size_t ws_bytes, void* stream, snc_prepared** out) {
+  if (!c || !out || n < 0 || (n > 0 && (!f || !g))) return SNC_EINVAL;
+  return prepare_resultants(c, n, f, g, d_ws, ws_bytes, (hipStream_t)stream, /*graph=*/true, out);
+}
+
+int snc_prepared_run(snc_prepared* p, void* stream, snc_upoly* out) {
+  if (!p || (p->n > 0 && !out)) return SNC_EINVAL;
+  return run_prepared(p, (hipStream_t)stream, out);
+}
+
+int snc_prepared_destroy(snc_prepared* p) {
+  if (!p) return SNC_EINVAL;
+  destroy_prepared(p);
   return SNC_OK;
 }
 

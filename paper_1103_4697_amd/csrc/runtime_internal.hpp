@@ -91,7 +91,24 @@ struct snc_ctx {
   void release();
 };
 
+// A batch of resultants whose inputs have been planned and uploaded into a
+// device workspace; running it launches only the device pipeline.
+struct snc_prepared {
+  snc_ctx* c = nullptr;
+  int n = 0;
+  bool use_graph = false;
+  std::vector<snc::ResPlan> P;
+  snc::BatchLayout lay;
+  uint8_t* ws = nullptr;
+  void* h_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
 namespace snc {
+int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
+                       size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
+int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
+void destroy_prepared(snc_prepared* pr);
 int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                    size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph);
 }
