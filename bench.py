@@ -127,6 +127,13 @@ def main():
         snc.resultant_y(f, g, ctx)
         for name, ms, _n in ctx.timing():
             stages[name] = stages.get(name, 0.0) + ms / nrep
+    gstages = {}
+    Rl = batch.bufs[0][: d + 1]
+    Rpl = snc.derivative_limbs(Rl)
+    for _ in range(nrep):
+        snc.gcd_z_limbs(Rl, Rpl, ctx)
+        for name, ms, _n in ctx.timing():
+            gstages[name] = gstages.get(name, 0.0) + ms / nrep
     ctx.set_timing(False)
     ee_ms = stages.get("eval_elim", float("nan"))
     m, n = f.shape[0] - 1, g.shape[0] - 1
@@ -154,6 +161,7 @@ def main():
         "parity_ok": bool(parity),
         "mod_p_evals_per_s": round(k * (D + 1) / (ms_per_step * 1e-3), 1),
         "stage_ms": {kk: round(v, 4) for kk, v in stages.items()},
+        "gcd_stage_ms": {kk: round(v, 4) for kk, v in gstages.items()},
         "roofline": {"kernel": "eval_elim", "bound": "alu", "achieved": round(achieved, 4),
                      "peak": round(PEAK_VALU_TOPS, 3), "unit": "TOP/s (int32 VALU lane-ops)",
                      "frac": round(achieved / PEAK_VALU_TOPS, 5), "traffic": None,
@@ -161,6 +169,7 @@ def main():
     }
 
     progress(f"stages {stages}")
+    progress(f"gcd stages {gstages}")
     if not args.no_batch:
         progress("batched workload")
         pairs, _common = synth.config2()

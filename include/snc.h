@@ -147,6 +147,30 @@ int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out);
 int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
               void* stream, snc_upoly* out);
 
+/* ---- serving --------------------------------------------------------------
+ * A request loop with continuous batching.  The server owns the device pool
+ * (d_pool, pool_bytes; caller-allocated, valid until snc_server_destroy) and
+ * nstreams worker threads, each with its own context and HIP stream.
+ * Submitting copies and plans the inputs (their device footprint is the
+ * plan's workspace size; a request larger than the pool is refused with
+ * SNC_ENOMEM).  A free worker admits the waiting resultant requests that fit
+ * into the free pool bytes and the max_slots limit and runs them as one
+ * batch, or runs one gcd; work on different streams overlaps on the device.
+ * snc_poll returns SNC_EAGAIN until the request is finished, then writes the
+ * result like the synchronous calls and releases the request (SNC_ERANGE
+ * keeps it).  snc_request_times gives its submit and finish times (steady
+ * clock, seconds), also after it was polled.  snc_server_wait blocks until
+ * at least `completed` requests have finished since creation (SNC_EAGAIN on
+ * timeout).  All server functions are thread-safe. */
+int snc_server_create(snc_ctx* ctx, void* d_pool, size_t pool_bytes, int32_t max_slots, int32_t nstreams,
+                      snc_server** out);
+int snc_submit_resultant_y(snc_server* srv, const snc_bipoly* f, const snc_bipoly* g, uint64_t* ticket);
+int snc_submit_gcd_z(snc_server* srv, const snc_upoly* a, const snc_upoly* b, uint64_t* ticket);
+int snc_poll(snc_server* srv, uint64_t ticket, snc_upoly* out);
+int snc_request_times(snc_server* srv, uint64_t ticket, double* submit_s, double* done_s);
+int snc_server_wait(snc_server* srv, int64_t completed, double timeout_s);
+int snc_server_destroy(snc_server* srv);
+
 /* ---- host-side helpers (no device work) --------------------------------- */
 /* i-th prime of the modulus table (descending below 2^30), 0 if out of range. */
 uint32_t snc_prime(int32_t i);

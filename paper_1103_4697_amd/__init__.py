@@ -72,6 +72,13 @@ def lib():
                 "snc_resultant_y_prepare": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(VP)]),
                 "snc_prepared_run": (C.c_int, [VP, VP, P(Upoly)]),
                 "snc_prepared_destroy": (C.c_int, [VP]),
+                "snc_server_create": (C.c_int, [VP, VP, SZ, I32, I32, P(VP)]),
+                "snc_submit_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), P(C.c_uint64)]),
+                "snc_submit_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), P(C.c_uint64)]),
+                "snc_poll": (C.c_int, [VP, C.c_uint64, P(Upoly)]),
+                "snc_request_times": (C.c_int, [VP, C.c_uint64, P(C.c_double), P(C.c_double)]),
+                "snc_server_wait": (C.c_int, [VP, C.c_int64, C.c_double]),
+                "snc_server_destroy": (C.c_int, [VP]),
                 "snc_gcd_z_plan": (C.c_int, [P(Upoly), P(Upoly), P(Plan)]),
                 "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
             }
@@ -429,6 +436,83 @@ def derivative_limbs(a_limbs: np.ndarray) -> np.ndarray:
         out[:, l] = (v & np.uint64(0xFFFFFFFF)).astype(np.uint32)
         carry = v >> np.uint64(32)
     return out
+
+
+class Server:
+    """Request loop with continuous batching (snc_server_*): submit resultant
+    and gcd jobs as they arrive, poll their results."""
+
+    def __init__(self, pool_bytes: int = 1 << 30, max_slots: int = 64, nstreams: int = 4,
+                 ctx: Context | None = None):
+        import torch
+        self.ctx = ctx or default_context()
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        st = lib().snc_server_create(self.ctx.h, C.c_void_p(self.pool.data_ptr()), C.c_size_t(pool_bytes),
+                                     max_slots, nstreams, C.byref(h))
+        if st != SNC_OK:
+            raise SncError(st, "snc_server_create")
+        self.h = h
+        self._caps = {}
+
+    def submit_resultant(self, f, g) -> int:
+        keep = []
+        bf, bg = _as_bipoly(f, keep), _as_bipoly(g, keep)
+        t = C.c_uint64()
+        st = lib().snc_submit_resultant_y(self.h, C.byref(bf), C.byref(bg), C.byref(t))
+        if st != SNC_OK:
+            raise SncError(st, "snc_submit_resultant_y")
+        p = Plan()
+        lib().snc_resultant_y_plan(C.byref(bf), C.byref(bg), C.byref(p))
+        self._caps[t.value] = (p.deg_bound, p.out_nlimbs)
+        return t.value
+
+    def submit_gcd(self, a, b) -> int:
+        keep = []
+        ua, ub = _as_upoly(a, keep), _as_upoly(b, keep)
+        t = C.c_uint64()
+        st = lib().snc_submit_gcd_z(self.h, C.byref(ua), C.byref(ub), C.byref(t))
+        if st != SNC_OK:
+            raise SncError(st, "snc_submit_gcd_z")
+        p = Plan()
+        lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p))
+        self._caps[t.value] = (p.deg_bound, p.out_nlimbs)
+        return t.value
+
+    def poll(self, ticket: int):
+        """The result as a list of ints, or None while it is not finished."""
+        d, nl = self._caps[ticket]
+        keep = []
+        u, buf = _out_upoly(d, nl, keep)
+        st = lib().snc_poll(self.h, C.c_uint64(ticket), C.byref(u))
+        if st == SNC_EAGAIN:
+            return None
+        if st != SNC_OK:
+            raise SncError(st, "snc_poll")
+        self._caps.pop(ticket, None)
+        return _read_upoly(u, buf)
+
+    def times(self, ticket: int):
+        s, d = C.c_double(), C.c_double()
+        st = lib().snc_request_times(self.h, C.c_uint64(ticket), C.byref(s), C.byref(d))
+        if st != SNC_OK:
+            return None
+        return s.value, d.value
+
+    def wait(self, completed: int, timeout_s: float = 60.0) -> bool:
+        return lib().snc_server_wait(self.h, completed, timeout_s) == SNC_OK
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def prime(i: int) -> int:

@@ -209,18 +209,76 @@ struct BigInt {
     q.neg = a.neg != b.neg; r.neg = a.neg;
     q.trim(); r.trim();
   }
+  // x * v for an unsigned 64-bit v (sign of x kept)
+  static BigInt mul_u64(const BigInt& x, uint64_t v) {
+    BigInt r = x.mul_small((uint32_t)v);
+    const uint32_t hi = (uint32_t)(v >> 32);
+    if (hi && !x.is_zero()) {
+      BigInt t = x.mul_small(hi);
+      t.mag.insert(t.mag.begin(), 0u);
+      r = r + t;
+    }
+    return r;
+  }
+  // floor(|x| / 2^shift) truncated to 64 bits
+  static uint64_t bits_at(const BigInt& x, size_t shift) {
+    const size_t w = shift / 32, b = shift % 32;
+    unsigned __int128 acc = 0;  // words w..w+2
+
+    for (int i = 2; i >= 0; --i) {
+      const size_t k = w + (size_t)i;
+      acc = (acc << 32) | (k < x.mag.size() ? x.mag[k] : 0u);
+    }
+    return (uint64_t)(acc >> b);
+  }
+  static uint64_t mod_u64(const BigInt& x, uint64_t m) {
+    unsigned __int128 r = 0;
+    for (size_t i = x.mag.size(); i-- > 0;) r = ((r << 32) | x.mag[i]) % m;
+    return (uint64_t)r;
+  }
+  // gcd by Lehmer's method: the leading 62 bits drive runs of Euclid steps
+  // with 64-bit cofactors, applied to the full numbers as one linear
+  // combination; a full division step when the run makes no progress.
   static BigInt gcd(BigInt a, BigInt b) {
     a.neg = b.neg = false;
-    while (!b.is_zero()) {
-      if (b.mag.size() == 1) {
-        uint64_t x = b.mag[0], y = a.mod_small(b.mag[0]);
-        while (y) { uint64_t t = x % y; x = y; y = t; }
-        return BigInt::from_u64(x);
+    if (cmp_mag(a.mag, b.mag) < 0) std::swap(a, b);
+    while (b.mag.size() > 2) {
+      const size_t n = a.bitlen();
+      const size_t shift = n > 62 ? n - 62 : 0;
+      __int128 ah = (__int128)bits_at(a, shift), bh = (__int128)bits_at(b, shift);
+      __int128 A = 1, B = 0, C = 0, D = 1;
+      while (bh + C != 0 && bh + D != 0) {
+        const __int128 q1 = (ah + A) / (bh + C), q2 = (ah + B) / (bh + D);
+        if (q1 != q2) break;
+        __int128 T = A - q1 * C; A = C; C = T;
+        T = B - q1 * D; B = D; D = T;
+        T = ah - q1 * bh; ah = bh; bh = T;
       }
-      BigInt q, r; divmod(a, b, q, r); r.neg = false;
-      a = std::move(b); b = std::move(r);
+      if (B == 0) {
+        BigInt q, r;
+        divmod(a, b, q, r);
+        r.neg = false;
+        a = std::move(b);
+        b = std::move(r);
+      } else {
+        auto term = [](const BigInt& x, __int128 c) {
+          BigInt t = mul_u64(x, (uint64_t)(c < 0 ? -c : c));
+          return c < 0 ? -t : t;
+        };
+        BigInt na = term(a, A) + term(b, B);
+        BigInt nb = term(a, C) + term(b, D);
+        na.neg = nb.neg = false;
+        a = std::move(na);
+        b = std::move(nb);
+      }
+      if (cmp_mag(a.mag, b.mag) < 0) std::swap(a, b);
     }
-    return a;
+    if (b.is_zero()) return a;
+    uint64_t bb = 0;
+    for (size_t i = b.mag.size(); i-- > 0;) bb = (bb << 32) | b.mag[i];
+    uint64_t aa = mod_u64(a, bb);
+    while (aa) { uint64_t t = bb % aa; bb = aa; aa = t; }
+    return BigInt::from_u64(bb);
   }
   double log2_abs() const {  // approximate log2 |x|, -inf-ish for 0
     if (mag.empty()) return -1.0;

@@ -1,9 +1,11 @@
 // Host side of the modular gcd in Z[x] (snc_gcd_z).
 //
 // a = cont(a) abar, b = cont(b) bbar; c = gcd(cont a, cont b); beta =
-// gcd(lc abar, lc bbar).  For primes p not dividing cont(a) cont(b) beta the
-// device computes e_p = deg gcd(abar, bbar) mod p, w_p = beta * monic gcd and
-// the cofactors u_p, v_p.  deg gcd over Q <= e_p for every such p, so e_p = 0
+// gcd(lc abar, lc bbar).  For primes p dividing neither cont(a) nor cont(b)
+// nor both leading coefficients (i.e. not beta) the device computes
+// e_p = deg gcd(abar, bbar) mod p, the monic gcd mod p and the cofactors
+// u_p, v_p; w_p = beta * monic gcd is formed when the selected primes are
+// gathered (beta is only needed when the gcd is not a constant).  deg gcd over Q <= e_p for every such p, so e_p = 0
 // for one prime proves gcd = c.  Otherwise the primes of minimal e_p are kept
 // (the others are unlucky), w, u, v are lifted by Chinese remaindering with
 // balanced residues, and the result is accepted only if
@@ -14,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -25,6 +28,47 @@
 
 namespace snc {
 namespace {
+
+// host/device phase timing of one gcd call (enabled with snc_set_timing)
+struct GcdTimer {
+  snc_ctx* c;
+  hipStream_t s;
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float dev_ms = 0.f;
+  GcdTimer(snc_ctx* c_, hipStream_t s_) : c(c_), s(s_), on(c_->timing) {
+    if (on) { c->stage_names.clear(); c->stage_ms.clear(); c->stage_launches.clear(); t0 = std::chrono::steady_clock::now(); }
+  }
+  void host(const char* name) {
+    if (!on) return;
+    auto t = std::chrono::steady_clock::now();
+    c->stage_names.push_back(name);
+    c->stage_ms.push_back(std::chrono::duration<float, std::milli>(t - t0).count());
+    c->stage_launches.push_back(0);
+    t0 = t;
+  }
+  void dev_begin() {
+    if (!on) return;
+    if (!e0) { (void)hipEventCreate(&e0); (void)hipEventCreate(&e1); }
+    (void)hipEventRecord(e0, s);
+  }
+  void dev_end(const char* name, int launches) {  // call after the stream was synchronised
+    if (!on) return;
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c->stage_names.push_back(name);
+    c->stage_ms.push_back(ms);
+    c->stage_launches.push_back(launches);
+    t0 = std::chrono::steady_clock::now();
+  }
+  ~GcdTimer() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
 
 struct UPoly {
   std::vector<BigInt> c;  // ascending, trimmed
@@ -44,13 +88,37 @@ int parse_upoly(const snc_upoly* a, UPoly& P, int& nl, std::string& err) {
   return SNC_OK;
 }
 
+// |x| mod m for a 32-bit m with a table pw[i] = 2^(32 i) mod m (no divisions per limb)
+uint32_t mod_by_table(const BigInt& x, const std::vector<uint64_t>& pw, uint32_t m) {
+  unsigned __int128 acc = 0;
+  for (size_t i = 0; i < x.mag.size(); ++i) acc += (unsigned __int128)x.mag[i] * pw[i];
+  return (uint32_t)(acc % m);
+}
+
 BigInt content(const UPoly& P) {
   BigInt g;
-  for (const auto& x : P.c) {
-    g = BigInt::gcd(g, x);
-    if (g.mag.size() == 1 && g.mag[0] == 1) break;
+  size_t i = 0;
+  for (; i < P.c.size(); ++i) {
+    g = BigInt::gcd(g, P.c[i]);
+    if (g.mag.size() <= 1) break;
   }
-  return g;
+  if (g.mag.size() != 1) return g;
+  // single-limb running gcd: reduce the remaining coefficients through a power table
+  uint64_t gg = g.mag[0];
+  size_t maxl = 1;
+  for (const auto& x : P.c) maxl = std::max(maxl, x.mag.size());
+  std::vector<uint64_t> pw(maxl);
+  uint64_t table_for = 0;
+  for (++i; i < P.c.size() && gg > 1; ++i) {
+    if (table_for != gg) {
+      uint64_t v = 1;
+      for (size_t l = 0; l < maxl; ++l) { pw[l] = v; v = (v << 32) % gg; }
+      table_for = gg;
+    }
+    uint64_t r = mod_by_table(P.c[i], pw, (uint32_t)gg);
+    while (r) { uint64_t t = gg % r; gg = r; r = t; }
+  }
+  return BigInt::from_u64(gg);
 }
 
 // log2 of the 2-norm and of the 1-norm (approximate, used only for sizing)
@@ -86,7 +154,8 @@ struct GcdInfo {
   int trivial = 0;           // 1: result computed on the host
   UPoly triv;                // trivial result
   int da = 0, db = 0, nl = 1;
-  BigInt ca, cb, c, beta;
+  BigInt ca, cb, c, beta, lca_bar, lcb_bar;
+  bool have_beta = false;
   double l2a = 0, l2b = 0, l1a = 0, l1b = 0, lbeta = 0;
   int kmax = 0;
   int deg_bound = 0, out_nlimbs = 1;
@@ -138,11 +207,11 @@ int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I) {
   I.db = B.deg();
   BigInt q, r;
   BigInt::divmod(A.c.back(), I.ca, q, r);
-  BigInt lcb_a = abs_big(q);
+  I.lca_bar = abs_big(q);
   BigInt::divmod(B.c.back(), I.cb, q, r);
-  BigInt lcb_b = abs_big(q);
-  I.beta = BigInt::gcd(lcb_a, lcb_b);
-  I.lbeta = I.beta.log2_abs();
+  I.lcb_bar = abs_big(q);
+  // beta divides both leading coefficients: bound its size by the smaller
+  I.lbeta = std::min(I.lca_bar.log2_abs(), I.lcb_bar.log2_abs());
   log2_norms(A, I.l2a, I.l1a);
   log2_norms(B, I.l2b, I.l1b);
   const double lca = I.ca.log2_abs(), lcb = I.cb.log2_abs();
@@ -161,8 +230,8 @@ int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I) {
 struct GcdLayout {
   size_t coef = 0, slot_prime = 0, slot_scale = 0, res = 0, e = 0, w = 0, u = 0, v = 0;   // words
   // CRT area (words)
-  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0;
-  size_t wv = 0, uv = 0, vv = 0, dig = 0, acc = 0, out = 0;
+  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0, betas = 0;
+  size_t wv = 0, uv = 0, vv = 0, dig = 0, out = 0;
   size_t header_words = 0, crt_header_words = 0, total_words = 0;
   int lpg = 0, lg = 0;
 };
@@ -191,13 +260,13 @@ void layout_gcd(const GcdInfo& I, GcdLayout& L) {
   L.prefd = w; w += align_words(8);
   L.prefc = w; w += align_words(8);
   L.sel = w; w += align_words(K);
+  L.betas = w; w += align_words(K);
   L.crt_header_words = w - crt0;
   const size_t nmax = (size_t)std::max(I.da, I.db) + 1;
   L.wv = w; w += align_words((size_t)K * wl);
   L.uv = w; w += align_words((size_t)K * (I.da + 1));
   L.vv = w; w += align_words((size_t)K * (I.db + 1));
   L.dig = w; w += align_words(3 * nmax * K);
-  L.acc = w; w += align_words(3 * nmax * lx_of(K));
   L.out = w; w += align_words(3 * nmax * L.lg);
   L.total_words = w;
 }
@@ -232,14 +301,17 @@ int write_upoly(const UPoly& G, snc_upoly* out, std::string& err) {
 static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
                     hipStream_t stream, snc_upoly* out) {
   HIPCHK(hipSetDevice(ctx->device));
+  GcdTimer tm(ctx, stream);
   UPoly A, B;
   int nla = 1, nlb = 1;
   int st = parse_upoly(a, A, nla, ctx->err);
   if (!st) st = parse_upoly(b, B, nlb, ctx->err);
   if (st) return st;
+  tm.host("gcd_parse");
   GcdInfo I;
   st = analyse(A, B, nla, nlb, I);
   if (st) return st;
+  tm.host("gcd_contents");
   if (I.trivial) return write_upoly(I.triv, out, ctx->err);
   if (out->deg < I.deg_bound || out->nlimbs < I.out_nlimbs || !out->limbs) {
     out->deg = I.deg_bound;
@@ -284,23 +356,28 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
     const int first = ns;
     while (ns < target && next_prime < KMAX) {
       const uint32_t p = TB.p[next_prime];
-      const uint32_t cam = I.ca.mod_small(p), cbm = I.cb.mod_small(p), bm = I.beta.mod_small(p);
-      if (cam && cbm && bm) {
+      const uint32_t cam = I.ca.mod_small(p), cbm = I.cb.mod_small(p);
+      const bool lc_ok = I.lca_bar.mod_small(p) != 0 || I.lcb_bar.mod_small(p) != 0;  // p does not divide beta
+      if (cam && cbm && lc_ok) {
         slot_prime[ns] = next_prime;
         slot_scale[3 * ns + 0] = powmod32(cam, p - 2, p);
         slot_scale[3 * ns + 1] = powmod32(cbm, p - 2, p);
-        slot_scale[3 * ns + 2] = bm;
+        slot_scale[3 * ns + 2] = 0;
         ++ns;
       }
       ++next_prime;
     }
     if (ns == first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
+    tm.host("gcd_select_primes");
     HIPCHK(hipMemcpyAsync(ws, h, L.header_words * 4, hipMemcpyHostToDevice, stream));
+    tm.dev_begin();
     G.slot0 = first;
     launch_gcd_round(G, ns - first, ws, stream);
     HIPCHK(hipGetLastError());
+    tm.dev_end("gcd_modp_round", 2);
     HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.e, (size_t)ns * 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
+    tm.host("gcd_d2h_sync");
     e_host.assign((int32_t*)ctx->h_out, (int32_t*)ctx->h_out + ns);
     for (int s = 0; s < ns; ++s) {
       if (e_host[s] < 0 || e_host[s] > std::min(I.da, I.db)) {
@@ -313,6 +390,10 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
       UPoly R;
       R.c = {I.c};
       return write_upoly(R, out, ctx->err);
+    }
+    if (!I.have_beta) {
+      I.beta = BigInt::gcd(I.lca_bar, I.lcb_bar);
+      I.have_beta = true;
     }
     std::vector<int32_t> sel;
     for (int s = 0; s < ns; ++s) if (e_host[s] == emin) sel.push_back(s);
@@ -361,18 +442,21 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
       jb[t].L = L.lg;
       jb[t].val_off = (int64_t)vals[t];
       jb[t].dig_off = (int64_t)(L.dig + t * nmax * ks);
-      jb[t].acc_off = (int64_t)(L.acc + t * nmax * lx_of(ks));
+      jb[t].acc_off = 0;
       jb[t].out_off = (int64_t)(L.out + t * nmax * L.lg);
       pd[t + 1] = pd[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-      pcb[t + 1] = pcb[t] + (lens[t] + 255) / 256;
+      pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     }
     int32_t* hsel = (int32_t*)at(L.sel);
     for (int j = 0; j < ks; ++j) hsel[j] = sel[j];
+    uint32_t* hbeta = at(L.betas);
+    for (int j = 0; j < ks; ++j) hbeta[j] = I.beta.mod_small(q[j]);
     HIPCHK(hipMemcpyAsync(ws + crt0, hc, L.crt_header_words * 4, hipMemcpyHostToDevice, stream));
-    launch_gcd_gather(G, (const int32_t*)(ws + L.sel), ks, emin, ws, (int64_t)L.wv, (int64_t)L.uv, (int64_t)L.vv, stream);
+    launch_gcd_gather(G, (const int32_t*)(ws + L.sel), ws + L.betas, (const PrimeC*)(ws + L.primes), ks, emin, ws,
+                      (int64_t)L.wv, (int64_t)L.uv, (int64_t)L.vv, stream);
     CrtTables tb{(const PrimeC*)(ws + L.primes), ws + L.garner, ws + L.wtab, ws + L.ptab, ks, L.lpg};
     launch_crt_digits(tb, (const ResJob*)(ws + L.jobs), (const int64_t*)(ws + L.prefd), 3, pd[3], ws, stream);
-    launch_crt_combine(tb, (const ResJob*)(ws + L.jobs), (const int64_t*)(ws + L.prefc), 3, pcb[3], ws, stream);
+    launch_crt_combine(tb, (const ResJob*)(ws + L.jobs), (const int64_t*)(ws + L.prefc), 3, pcb[3], ks, ws, stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.out, 3 * nmax * L.lg * 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const Prime
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
-  const uint32_t ia = to_mont(sc[0], c), ib = to_mont(sc[1], c), bt = to_mont(sc[2], c);
+  const uint32_t ia = to_mont(sc[0], c), ib = to_mont(sc[1], c);
   const int maxd = G.da > G.db ? G.da : G.db;
   uint32_t* P0 = sm;
   uint32_t* P1 = sm + (maxd + 1);
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const Prime
   for (int i = tid; i <= e; i += GCD_THREADS) Gm[i] = mmulc(A[i], inv, c.p, c.pinv);
   __syncthreads();
   uint32_t* w = ws + G.w_off + (int64_t)slot * G.wl;
-  for (int i = tid; i < G.wl; i += GCD_THREADS) w[i] = i <= e ? from_mont(mmulc(bt, Gm[i], c.p, c.pinv), c) : 0u;
+  for (int i = tid; i < G.wl; i += GCD_THREADS) w[i] = i <= e ? from_mont(Gm[i], c) : 0u;
   if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
   if (e == 0) {
     // constant gcd: the cofactors are the primitive parts themselves
@@ -120,14 +120,17 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const Prime
   }
 }
 
-// copy the rows of the selected primes into compact [k][len] arrays
-__global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, int ks, int e, uint32_t* ws, int64_t wv,
-                             int64_t uv, int64_t vv) {
+// copy the rows of the selected primes into compact [k][len] arrays; the
+// monic gcd is scaled by beta mod p on the way (w = beta * monic gcd)
+__global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* betas, const PrimeC* sprimes,
+                             int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv) {
   const int j = blockIdx.y;
   const int s = sel[j];
+  const PrimeC c = sprimes[j];
+  const uint32_t bm = to_mont(betas[j], c);
   const int nw = e + 1, nu = G.da - e + 1, nv = G.db - e + 1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nw + nu + nv; i += gridDim.x * blockDim.x) {
-    if (i < nw) ws[wv + (int64_t)j * nw + i] = ws[G.w_off + (int64_t)s * G.wl + i];
+    if (i < nw) ws[wv + (int64_t)j * nw + i] = mmulc(bm, ws[G.w_off + (int64_t)s * G.wl + i], c.p, c.pinv);
     else if (i < nw + nu) ws[uv + (int64_t)j * nu + (i - nw)] = ws[G.u_off + (int64_t)s * (G.da + 1) + (i - nw)];
     else ws[vv + (int64_t)j * nv + (i - nw - nu)] = ws[G.v_off + (int64_t)s * (G.db + 1) + (i - nw - nu)];
   }
@@ -144,10 +147,11 @@ void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s)
   hipLaunchKernelGGL(k_gcd_modp, dim3(nslots), dim3(GCD_THREADS), shmem, s, G, primes, ws);
 }
 
-void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, int ks, int e, uint32_t* ws, int64_t wv,
-                       int64_t uv, int64_t vv, hipStream_t s) {
+void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
+                       int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s) {
   const int n = G.da + G.db + 3 - e;
-  hipLaunchKernelGGL(k_gcd_gather, dim3((n + 255) / 256, ks), dim3(256), 0, s, G, sel_d, ks, e, ws, wv, uv, vv);
+  hipLaunchKernelGGL(k_gcd_gather, dim3((n + 255) / 256, ks), dim3(256), 0, s, G, sel_d, betas_d, sprimes_d, ks, e,
+                     ws, wv, uv, vv);
 }
 
 hipError_t configure_gcd_kernels() {

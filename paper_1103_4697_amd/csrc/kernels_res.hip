@@ -352,11 +352,24 @@ void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
 
 // ---------------------------------------------------------------------------
 // (4) Interpolation mod p from the values at x = 0..D, one workgroup per
-//     (resultant, prime).  Newton coefficients of equispaced data are
-//     a_k = (Delta^k v_0) / k! = sum_{i<=k} (v_i / i!) * ((-1)^{k-i} / (k-i)!),
-//     a convolution that every thread evaluates independently; the Newton
-//     form is then expanded by P <- P (x - k) + a_k, k = D..0.
+//     (resultant, prime).
+//   Newton coefficients of equispaced data, a_k = (Delta^k v_0) / k!, are the
+//   convolution a_k = sum_{i<=k} (v_i / i!) ((-1)^{k-i} / (k-i)!), evaluated by
+//   every thread independently.  The Newton form
+//     P = sum_k a_k N_k,  N_k = x (x-1) ... (x-k+1)
+//   is expanded blockwise: with blocks of 64 terms starting at b = 64j,
+//     Q_j = sum_{t<64} a_{b+t} prod_{i=b}^{b+t-1} (x - i),   F_j = prod_{i=b}^{b+63} (x - i),
+//   one wavefront builds Q_j and F_j by 64 lane-shift steps (no barriers),
+//   and P = Q_0 + F_0 (Q_1 + F_1 (Q_2 + ...)) takes one parallel polynomial
+//   product per block.
 // ---------------------------------------------------------------------------
+constexpr int IB = 64;  // Newton terms per block (one per lane)
+
+__device__ __forceinline__ uint32_t shift_up1(uint32_t v, int lane) {
+  const uint32_t u = __shfl_up(v, 1, 64);
+  return lane == 0 ? 0u : u;
+}
+
 __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, const int64_t* prefix,
                                                            int njobs, uint32_t* ws) {
   extern __shared__ uint32_t sm[];
@@ -365,73 +378,109 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
   const ResJob J = jobs[jj];
   const int pi = (int)(b - prefix[jj]);
   const PrimeC c = g_primes[pi];
-  const int n1 = J.D + 1;
+  const int D = J.D;
+  const int n1 = D + 1;
+  const int nblk = (n1 + IB - 1) / IB;
+  const int Dp = nblk * IB;  // padded buffer length
   uint32_t* V = ws + J.val_off + (int64_t)pi * n1;
-  uint32_t* s0 = sm;
-  uint32_t* s1 = sm + n1;
-  uint32_t* s2 = sm + 2 * n1;
+  uint32_t* R0 = sm;
+  uint32_t* R1 = sm + Dp;
+  uint32_t* R2 = sm + 2 * Dp;
+  uint32_t* R3 = sm + 3 * Dp;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
 
   // factorials by an inclusive prefix product (Hillis-Steele, double-buffered)
-  for (int t = tid; t < n1; t += INTERP_THREADS) s0[t] = t ? to_mont((uint32_t)t, c) : c.r1;
+  for (int t = tid; t < n1; t += INTERP_THREADS) R0[t] = t ? to_mont((uint32_t)t, c) : c.r1;
   __syncthreads();
-  uint32_t* in = s0;
-  uint32_t* out = s1;
+  uint32_t* in = R0;
+  uint32_t* out = R1;
   for (int off = 1; off < n1; off <<= 1) {
     for (int t = tid; t < n1; t += INTERP_THREADS)
       out[t] = t >= off ? mmulc(in[t], in[t - off], c.p, c.pinv) : in[t];
     __syncthreads();
     uint32_t* tmp = in; in = out; out = tmp;
   }
-  // in = factorials; inverse factorials into s2
-  for (int t = tid; t < n1; t += INTERP_THREADS) s2[t] = minv(in[t], c);
+  for (int t = tid; t < n1; t += INTERP_THREADS) R2[t] = minv(in[t], c);  // 1/t!
   __syncthreads();
-  // u_i = v_i / i!  (s0),  w_j = (-1)^j / j!  (s1)
+  // u_i = v_i / i! (R0),  w_j = (-1)^j / j! (R1)
   for (int t = tid; t < n1; t += INTERP_THREADS) {
-    const uint32_t inv = s2[t];
-    s0[t] = mmulc(canon(V[t], c.p), inv, c.p, c.pinv);
-    s1[t] = (t & 1) ? mneg(inv, c.p) : inv;
+    const uint32_t inv = R2[t];
+    R0[t] = mmulc(canon(V[t], c.p), inv, c.p, c.pinv);
+    R1[t] = (t & 1) ? mneg(inv, c.p) : inv;
   }
   __syncthreads();
-  // a_k = sum_{i<=k} u_i w_{k-i}, 64-bit lazy accumulation, reduce every 8 terms
+  // a_k = sum_{i<=k} u_i w_{k-i} (R2), 64-bit lazy accumulation, reduce every 8 terms
   for (int kk = tid; kk < n1; kk += INTERP_THREADS) {
     uint32_t sum = 0;
     int i = 0;
     while (i <= kk) {
       uint64_t acc = 0;
       const int e = min(kk, i + 7);
-      for (; i <= e; ++i) acc += (uint64_t)s0[i] * s1[kk - i];
+      for (; i <= e; ++i) acc += (uint64_t)R0[i] * R1[kk - i];
       sum = madd(sum, canon(redc(acc, c.p, c.pinv), c.p), c.p);
     }
-    s2[kk] = sum;
+    R2[kk] = sum;
   }
   __syncthreads();
-  // Newton form -> monomials: P <- P (x - k) + a_k
-  in = s0;
-  out = s1;
-  if (tid == 0) in[0] = s2[J.D];
+  // per block j: Q_j into R0[64j..], F_j (non-leading coefficients; monic) into R1[64j..]
+  for (int j = wave; j < nblk; j += INTERP_THREADS / 64) {
+    const int b0 = j * IB;
+    const int len = min(IB, n1 - b0);
+    uint32_t q = lane == 0 ? R2[b0 + len - 1] : 0u;
+    for (int kk = b0 + len - 2; kk >= b0; --kk) {  // Q <- Q (x - kk) + a_kk
+      const uint32_t nk = mneg(to_mont((uint32_t)kk, c), c.p);
+      const uint32_t prev = shift_up1(q, lane);
+      q = canon(mmul2(c.r1, prev, nk, q, c.p, c.pinv), c.p);
+      if (lane == 0) q = madd(q, R2[kk], c.p);
+    }
+    uint32_t f = lane == 0 ? c.r1 : 0u;
+    for (int i = b0; i < b0 + len; ++i) {  // F <- F (x - i)
+      const uint32_t ni = mneg(to_mont((uint32_t)i, c), c.p);
+      const uint32_t prev = shift_up1(f, lane);
+      f = canon(mmul2(c.r1, prev, ni, f, c.p, c.pinv), c.p);
+    }
+    R0[b0 + lane] = q;
+    R1[b0 + lane] = f;  // lane == len holds the leading 1 when len < 64; never read
+  }
   __syncthreads();
-  for (int kk = J.D - 1; kk >= 0; --kk) {
-    const int len = J.D - kk;  // current length of P
-    const uint32_t nk = mneg(to_mont((uint32_t)kk, c), c.p);
-    const uint32_t ak = s2[kk];
-    for (int t = tid; t <= len; t += INTERP_THREADS) {
-      const uint32_t prev = t >= 1 ? in[t - 1] : 0u;
-      const uint32_t cur = t < len ? in[t] : 0u;
-      uint32_t q = canon(mmul2(c.r1, prev, nk, cur, c.p, c.pinv), c.p);
-      if (t == 0) q = madd(q, ak, c.p);
-      out[t] = q;
+  // P = Q_{nblk-1}; P <- P F_j + Q_j for j = nblk-2 .. 0
+  uint32_t* P = R2;
+  uint32_t* Pn = R3;
+  const int lastlen = n1 - (nblk - 1) * IB;
+  for (int t = tid; t < Dp; t += INTERP_THREADS) P[t] = t < lastlen ? R0[(nblk - 1) * IB + t] : 0u;
+  int dP = lastlen - 1;
+  __syncthreads();
+  for (int j = nblk - 2; j >= 0; --j) {
+    const uint32_t* Fj = R1 + j * IB;  // degree IB, monic
+    const uint32_t* Qj = R0 + j * IB;
+    const int dN = dP + IB;
+    for (int t = tid; t <= dN; t += INTERP_THREADS) {
+      const int i0 = max(0, t - dP), i1 = min(IB - 1, t);
+      uint32_t sum = 0;
+      int i = i0;
+      while (i <= i1) {
+        uint64_t acc = 0;
+        const int e = min(i1, i + 7);
+        for (; i <= e; ++i) acc += (uint64_t)Fj[i] * P[t - i];
+        sum = madd(sum, canon(redc(acc, c.p, c.pinv), c.p), c.p);
+      }
+      if (t >= IB) sum = madd(sum, P[t - IB], c.p);  // leading coefficient of F_j
+      if (t < IB) sum = madd(sum, Qj[t], c.p);
+      Pn[t] = sum;
     }
     __syncthreads();
-    uint32_t* tmp = in; in = out; out = tmp;
+    uint32_t* tmp = P; P = Pn; Pn = tmp;
+    dP = dN;
   }
-  for (int t = tid; t < n1; t += INTERP_THREADS) V[t] = from_mont(in[t], c);
+  for (int t = tid; t < n1; t += INTERP_THREADS) V[t] = from_mont(P[t], c);
 }
 
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    int max_D, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
-  size_t shmem = (size_t)3 * (max_D + 1) * sizeof(uint32_t);
+  const size_t Dp = (size_t)((max_D + 1 + IB - 1) / IB) * IB;
+  size_t shmem = 4 * Dp * sizeof(uint32_t);
   hipLaunchKernelGGL(k_interp, dim3((unsigned)nblocks), dim3(INTERP_THREADS), shmem, s, jobs_d,
                      blk_prefix_d, njobs, ws);
 }
@@ -495,47 +544,72 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
   }
 }
 
-__global__ __launch_bounds__(256) void k_crt_combine(CrtTables tb, const ResJob* jobs, const int64_t* prefix,
-                                                     int njobs, uint32_t* ws) {
+// X = sum_j y_j P_j with one wavefront per coefficient and lanes over limbs:
+// limb l accumulates sum_j y_j P_j[l] (< 2^72) as lo (64 bits) + hi; its low
+// word stays at limb l and the rest, a carry below 2^41, goes to limb l+1.
+// One lane then propagates the carries, subtracts M = P_k when
+// X > (M-1)/2 (decided on the digits: (M-1)/2 has digits (p_j - 1)/2) and
+// writes L two's-complement limbs.
+__global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTables tb, const ResJob* jobs,
+                                                                         const int64_t* prefix, int njobs,
+                                                                         int lx_max, uint32_t* ws) {
+  extern __shared__ uint32_t csm[];
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
-  const int t = (int)(b - prefix[jj]) * 256 + threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = (int)(b - prefix[jj]) * CRT_COEF_PER_BLOCK + wave;
   if (t > J.D) return;
   const int k = J.k;
   const int lx = lx_of(k);
   const uint32_t* d = ws + J.dig_off + (int64_t)t * k;
-  uint32_t* X = ws + J.acc_off + (int64_t)t * lx;
-  int len = 1;
-  X[0] = d[k - 1];
-  for (int j = k - 2; j >= 0; --j) {
-    const uint32_t p = tb.primes[j].p;
-    uint64_t carry = d[j];
-    for (int l = 0; l < len; ++l) {
-      const uint64_t v = (uint64_t)X[l] * p + carry;
-      X[l] = (uint32_t)v;
-      carry = v >> 32;
+  uint32_t* Xlo = csm + wave * 3 * lx_max;  // [lx] low words, then [2 lx] 64-bit carries as word pairs
+  uint32_t* Xc = Xlo + lx_max;
+  for (int l0 = 0; l0 < lx; l0 += 64) {
+    const int l = l0 + lane;
+    uint64_t lo = 0;
+    uint32_t hi = 0;
+    // P_j has at most 30 j / 32 + 1 limbs, so limbs >= l0 need j >= 32 l0 / 30 - 1
+    int j0 = (32 * l0) / 30 - 1;
+    if (j0 < 0) j0 = 0;
+    for (int j = j0; j < k; ++j) {
+      const uint32_t pl = l < tb.pstride ? tb.ptab[(int64_t)j * tb.pstride + l] : 0u;
+      const uint64_t pr = (uint64_t)d[j] * pl;
+      lo += pr;
+      hi += lo < pr ? 1u : 0u;
     }
-    if (carry) X[len++] = (uint32_t)carry;
+    if (l < lx) {
+      Xlo[l] = (uint32_t)lo;
+      const uint64_t cl = (lo >> 32) | ((uint64_t)hi << 32);
+      Xc[2 * l] = (uint32_t)cl;
+      Xc[2 * l + 1] = (uint32_t)(cl >> 32);
+    }
   }
-  for (int l = len; l < lx; ++l) X[l] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane != 0) return;
   int cmp = 0;
   for (int j = k - 1; j >= 0; --j) {
     const uint32_t h = (tb.primes[j].p - 1) >> 1;
     if (d[j] != h) { cmp = d[j] > h ? 1 : -1; break; }
   }
+  const bool sub = cmp > 0;
+  const uint32_t* M = tb.ptab + (int64_t)k * tb.pstride;
   uint32_t* out = ws + J.out_off + (int64_t)t * J.L;
-  if (cmp > 0) {  // X - M, M = P_k
-    const uint32_t* M = tb.ptab + (int64_t)k * tb.pstride;
-    int64_t borrow = 0;
-    for (int l = 0; l < lx; ++l) {
-      const uint32_t ml = l < tb.pstride ? M[l] : 0u;
-      int64_t v = (int64_t)X[l] - ml - borrow;
-      borrow = v < 0;
-      X[l] = (uint32_t)(v + (borrow << 32));
+  uint64_t carry = 0;
+  int64_t borrow = 0;
+  for (int l = 0; l < lx; ++l) {
+    const uint64_t sv = (uint64_t)Xlo[l] + carry;
+    uint32_t v = (uint32_t)sv;
+    carry = (sv >> 32) + ((uint64_t)Xc[2 * l] | ((uint64_t)Xc[2 * l + 1] << 32));
+    if (sub) {
+      const int64_t dv = (int64_t)v - (int64_t)(l < tb.pstride ? M[l] : 0u) - borrow;
+      borrow = dv < 0 ? 1 : 0;
+      v = (uint32_t)(dv + (borrow << 32));
     }
+    if (l < J.L) out[l] = v;
   }
-  for (int l = 0; l < J.L; ++l) out[l] = l < lx ? X[l] : ((cmp > 0) ? 0xffffffffu : 0u);
+  for (int l = lx; l < J.L; ++l) out[l] = sub ? 0xffffffffu : 0u;
 }
 
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
@@ -546,10 +620,12 @@ void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t*
 }
 
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                        int64_t nblocks, uint32_t* ws, hipStream_t s) {
+                        int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)nblocks), dim3(256), 0, s, tb, jobs_d, prefix_d,
-                     njobs, ws);
+  const int lxm = lx_of(kmax);
+  const size_t shmem = (size_t)CRT_COEF_PER_BLOCK * 3 * lxm * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), shmem, s, tb, jobs_d,
+                     prefix_d, njobs, lxm, ws);
 }
 
 CrtTables global_crt_tables() {

@@ -97,11 +97,12 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     J.res_off = (int64_t)w; w += align_words((size_t)P.k * P.T);
     J.val_off = (int64_t)w; w += align_words((size_t)P.k * n1);
     J.dig_off = (int64_t)w; w += align_words(n1 * P.k);
-    J.acc_off = (int64_t)w; w += align_words(n1 * (size_t)lx_of(P.k));
+    J.acc_off = (int64_t)w;  // unused: the combine step keeps its accumulators in LDS
     lay.nb_red += (int64_t)P.k * ((P.T + 255) / 256);
     lay.nb_interp += P.k;
     lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
-    lay.nb_crtc += (int64_t)((n1 + 255) / 256);
+    lay.nb_crtc += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
+    lay.max_k = std::max(lay.max_k, P.k);
     if (P.cls >= 0) lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
     else lay.n_gen_inst += (int64_t)P.k * n1;
     lay.total_inst += (int64_t)P.k * n1;
@@ -188,7 +189,7 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   const CrtTables tb = global_crt_tables();
   launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
   if (tm) tm->mark("crt_digits", 1);
-  launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, wsw, s);
+  launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, lay.max_k, wsw, s);
   if (tm) tm->mark("crt_combine", 1);
 }
 
@@ -249,7 +250,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     pr[j + 1] = pr[j] + (int64_t)P.k * ((P.T + 255) / 256);
     pi[j + 1] = pi[j] + P.k;
     pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-    pc[j + 1] = pc[j] + (n1 + 255) / 256;
+    pc[j + 1] = pc[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     if (P.cls >= 0) {
       const int c = P.cls;
       le[c][ne[c]] = j;

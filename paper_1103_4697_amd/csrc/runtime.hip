@@ -206,7 +206,7 @@ int plan_resultant(const Operand& F, const Operand& G, ResPlan& P, std::string& 
 size_t job_region_words(const ResPlan& P) {
   const size_t n1 = (size_t)P.D + 1;
   return align_words((size_t)P.k * P.T) + align_words((size_t)P.k * n1) + align_words(n1 * P.k) +
-         align_words(n1 * (size_t)lx_of(P.k));
+         0;
 }
 
 }  // namespace snc

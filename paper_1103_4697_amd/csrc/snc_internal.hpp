@@ -65,10 +65,10 @@ struct GcdDesc {
   int32_t pad;
   int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl] (uint32 index)
   int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
-  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a)^-1, cont(b)^-1, beta mod p (plain)
+  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a)^-1, cont(b)^-1 mod p (plain), unused
   int64_t res_off;         // residues [slot][da+db+2] (Montgomery)
   int64_t e_off;           // int32 per slot: degree of the gcd mod p
-  int64_t w_off;           // [slot][wl]   beta * monic gcd mod p (plain)
+  int64_t w_off;           // [slot][wl]   monic gcd mod p (plain)
   int64_t u_off;           // [slot][da+1] cofactor of a mod p (plain)
   int64_t v_off;           // [slot][db+1] cofactor of b mod p (plain)
 };
@@ -102,12 +102,12 @@ void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
                        int64_t nblocks, uint32_t* ws, hipStream_t s);
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                        int64_t nblocks, uint32_t* ws, hipStream_t s);
+                        int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
 
 void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);
-void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, int ks, int e, uint32_t* ws, int64_t wv,
-                       int64_t uv, int64_t vv, hipStream_t s);
+void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
+                       int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();
 
 int fast_class_of(int maxy);  // index of the register class for a y-degree, -1 if none
