@@ -100,7 +100,7 @@ BigInt content(const UPoly& P) {
   size_t i = 0;
   for (; i < P.c.size(); ++i) {
     g = BigInt::gcd(g, P.c[i]);
-    if (g.mag.size() <= 1) break;
+    if (g.mag.size() == 1) break;  // non-zero and one word: switch to the table reduction
   }
   if (g.mag.size() != 1) return g;
   // single-limb running gcd: reduce the remaining coefficients through a power table

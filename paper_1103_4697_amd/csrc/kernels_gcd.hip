@@ -120,6 +120,141 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const Prime
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant: one wavefront per prime, degrees below 64*E.
+// Polynomials are top-aligned (element i = coefficient of x^(deg-i)) and
+// lane-blocked (element i in lane i/E, slot i%E), values lazy in [0, 3p).
+// An elementary Euclid step X <- lc(Y) X - lc(X) x^(dX-dY) Y pairs X[i] with
+// Y[i] (tops aligned) and shifts X down one element: E fused updates per
+// lane plus one lane shift, no LDS and no barrier.  Leading coefficients are
+// read from lane 0.  Exact division by the monic gcd is the same step with
+// lc(Y) = 1 and the quotient coefficient as lc(X).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {  // lane l gets lane l+1 (0 for lane 63)
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t lead(uint32_t v0, uint32_t p) {
+  return canon((uint32_t)__builtin_amdgcn_readfirstlane((int)v0), p);
+}
+
+template <int E>
+__device__ __forceinline__ void reg_step(uint32_t (&X)[E], const uint32_t (&Y)[E], uint32_t lcY, uint32_t nlX,
+                                         const PrimeC& c) {
+  const uint32_t t0 = mmul2(lcY, X[0], nlX, Y[0], c.p, c.pinv);
+#pragma unroll
+  for (int s = 0; s + 1 < E; ++s) X[s] = mmul2(lcY, X[s + 1], nlX, Y[s + 1], c.p, c.pinv);
+  X[E - 1] = from_next_lane(t0);
+}
+
+template <int E>
+__device__ __forceinline__ void reg_shift(uint32_t (&X)[E]) {
+  const uint32_t n0 = from_next_lane(X[0]);
+#pragma unroll
+  for (int s = 0; s + 1 < E; ++s) X[s] = X[s + 1];
+  X[E - 1] = n0;
+}
+
+// drop vanishing leading coefficients: returns the degree
+template <int E>
+__device__ __forceinline__ int reg_trim(uint32_t (&X)[E], int d, const PrimeC& c) {
+  while (d >= 0 && lead(X[0], c.p) == 0) { reg_shift<E>(X); --d; }
+  return d;
+}
+
+// reduce X by Y until deg X < deg Y (Y fixed, deg Y >= 0)
+template <int E>
+__device__ __forceinline__ int reg_reduce(uint32_t (&X)[E], int dX, const uint32_t (&Y)[E], int dY,
+                                          const PrimeC& c) {
+  const uint32_t lcY = lead(Y[0], c.p);
+  while (dX >= dY) {
+    const uint32_t lcX = lead(X[0], c.p);
+    reg_step<E>(X, Y, lcY, c.p - lcX, c);
+    dX = reg_trim<E>(X, dX - 1, c);
+  }
+  return dX;
+}
+
+// load coefficients 0..deg of a residue row (scaled by sc) top-aligned
+template <int E>
+__device__ __forceinline__ void reg_load(uint32_t (&X)[E], const uint32_t* row, int deg, uint32_t sc, int lane,
+                                         const PrimeC& c) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int i = lane * E + s;
+    X[s] = i <= deg ? mmul(row[deg - i], sc, c.p, c.pinv) : 0u;
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void reg_cofactor(uint32_t (&R)[E], const uint32_t (&G)[E], int e, const uint32_t* row,
+                                             int deg, uint32_t sc, uint32_t* q, int lane, const PrimeC& c) {
+  reg_load<E>(R, row, deg, sc, lane, c);
+  for (int i = lane; i <= deg; i += 64) q[i] = 0u;
+  const int dR = reg_trim<E>(R, deg, c);
+  for (int t = dR - e; t >= 0; --t) {
+    const uint32_t qt = lead(R[0], c.p);  // coefficient of x^t of the quotient (G is monic)
+    if (lane == 0) q[t] = from_mont(qt, c);
+    reg_step<E>(R, G, c.r1, mneg(qt, c.p), c);
+  }
+}
+
+template <int E>
+__global__ __launch_bounds__(64) void k_gcd_modp_reg(GcdDesc G, const PrimeC* primes, uint32_t* ws) {
+  const int lane = threadIdx.x;
+  const int slot = G.slot0 + blockIdx.x;
+  const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
+  const PrimeC c = primes[pidx];
+  const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
+  const uint32_t ia = to_mont(sc[0], c), ib = to_mont(sc[1], c);
+  const int T = G.da + G.db + 2;
+  const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
+  const uint32_t* rb = ra + G.da + 1;
+  uint32_t X[E], Y[E], Gm[E];
+  reg_load<E>(X, ra, G.da, ia, lane, c);
+  reg_load<E>(Y, rb, G.db, ib, lane, c);
+  int dX = reg_trim<E>(X, G.da, c);
+  int dY = reg_trim<E>(Y, G.db, c);
+  int e;
+  while (true) {
+    if (dY < 0) {
+      e = dX;
+#pragma unroll
+      for (int s = 0; s < E; ++s) Gm[s] = X[s];
+      break;
+    }
+    if (dX >= dY) dX = reg_reduce<E>(X, dX, Y, dY, c);
+    if (dX < 0) {
+      e = dY;
+#pragma unroll
+      for (int s = 0; s < E; ++s) Gm[s] = Y[s];
+      break;
+    }
+    dY = reg_reduce<E>(Y, dY, X, dX, c);
+  }
+  const uint32_t inv = minv(lead(Gm[0], c.p), c);
+#pragma unroll
+  for (int s = 0; s < E; ++s) Gm[s] = mmulc(Gm[s], inv, c.p, c.pinv);
+  uint32_t* w = ws + G.w_off + (int64_t)slot * G.wl;
+  for (int i = lane; i < G.wl; i += 64) w[i] = 0u;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int i = lane * E + s;
+    if (i <= e) w[e - i] = from_mont(Gm[s], c);
+  }
+  if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+  uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
+  uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
+  if (e == 0) {
+    for (int i = lane; i <= G.da; i += 64) u[i] = from_mont(mmulc(ra[i], ia, c.p, c.pinv), c);
+    for (int i = lane; i <= G.db; i += 64) v[i] = from_mont(mmulc(rb[i], ib, c.p, c.pinv), c);
+    return;
+  }
+  reg_cofactor<E>(X, Gm, e, ra, G.da, ia, u, lane, c);
+  reg_cofactor<E>(X, Gm, e, rb, G.db, ib, v, lane, c);
+}
+
+static const int kGcdE[] = {2, 4, 6, 9, 12, 16, 24, 32};
+
 // copy the rows of the selected primes into compact [k][len] arrays; the
 // monic gcd is scaled by beta mod p on the way (w = beta * monic gcd)
 __global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* betas, const PrimeC* sprimes,
@@ -143,6 +278,20 @@ void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s)
   const PrimeC* primes = global_crt_tables().primes;
   hipLaunchKernelGGL(k_gcd_reduce, dim3((T + 255) / 256, nslots), dim3(256), 0, s, G, primes, ws);
   const int maxd = G.da > G.db ? G.da : G.db;
+  int E = 0;
+  for (int e : kGcdE)
+    if (64 * e >= maxd + 1) { E = e; break; }
+  switch (E) {
+    case 2: hipLaunchKernelGGL(k_gcd_modp_reg<2>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 4: hipLaunchKernelGGL(k_gcd_modp_reg<4>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 6: hipLaunchKernelGGL(k_gcd_modp_reg<6>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 9: hipLaunchKernelGGL(k_gcd_modp_reg<9>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 12: hipLaunchKernelGGL(k_gcd_modp_reg<12>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 16: hipLaunchKernelGGL(k_gcd_modp_reg<16>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 24: hipLaunchKernelGGL(k_gcd_modp_reg<24>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 32: hipLaunchKernelGGL(k_gcd_modp_reg<32>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    default: break;
+  }
   const size_t shmem = (size_t)(3 * (maxd + 1)) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_gcd_modp, dim3(nslots), dim3(GCD_THREADS), shmem, s, G, primes, ws);
 }

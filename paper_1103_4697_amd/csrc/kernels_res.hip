@@ -116,17 +116,44 @@ void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 // point (formal degree not attained, or a remainder of lower degree) is
 // queued for the general elimination below; the schedule stays uniform.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t horner_row(const uint32_t* coef, int len, uint32_t X,
-                                               uint32_t p, uint32_t pinv) {
+// one row q (0..3) of a row group
+__device__ __forceinline__ uint32_t horner_grouped(const uint32_t* r, const RowDesc& d, int q, uint32_t X,
+                                                   const PrimeC& c) {
   uint32_t acc = 0;
-#pragma nounroll
-  for (int i = len - 1; i >= 0; --i) acc = mhorner(acc, X, coef[i], p, pinv);
+  for (int i = d.len - 1; i >= 0; --i) acc = mhorner(acc, X, r[d.off + ROWGRP * i + q], c.p, c.pinv);
   return acc;
 }
 
 // One remainder step X <- prem(X, Y) on the first C+1 entries of the
 // register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
 // above each degree zero).  Branch-free inside an elementary step.
+// The N+1 rows of one operand evaluated at X, four rows at a time from the
+// interleaved group layout: one 16-byte scalar load per step feeds four
+// independent Horner chains (instruction-level parallelism for a lone
+// wavefront).  Zero padding at the top keeps a Horner accumulator at zero.
+template <int N>
+__device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* r, const RowDesc* rd,
+                                          uint32_t X, const PrimeC& c) {
+#pragma unroll
+  for (int t0 = 0; t0 <= N; t0 += ROWGRP) {
+    const RowDesc d = rd[t0 / ROWGRP];
+    const uint4* q = reinterpret_cast<const uint4*>(r + d.off);
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 2
+    for (int k = d.len - 1; k >= 0; --k) {
+      const uint4 v = q[k];
+      a0 = mhorner(a0, X, v.x, c.p, c.pinv);
+      a1 = mhorner(a1, X, v.y, c.p, c.pinv);
+      a2 = mhorner(a2, X, v.z, c.p, c.pinv);
+      a3 = mhorner(a3, X, v.w, c.p, c.pinv);
+    }
+    A[t0] = a0;
+    if (t0 + 1 <= N) A[t0 + 1] = a1;
+    if (t0 + 2 <= N) A[t0 + 2] = a2;
+    if (t0 + 3 <= N) A[t0 + 3] = a3;
+  }
+}
+
 template <int N, int C>
 __device__ __forceinline__ void rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, int b,
                                       int s, bool& ok, uint32_t& den, const PrimeC& c) {
@@ -180,10 +207,8 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   const RowDesc* ra = rows + J.rows_off;
   const RowDesc* rb = ra + J.rstride;  // J.rstride == N + 1 on this path
   uint32_t A[N + 1], B[N + 1];
-#pragma unroll
-  for (int t = 0; t <= N; ++t) A[t] = horner_row(r + ra[t].off, ra[t].len, X, c.p, c.pinv);
-#pragma unroll
-  for (int t = 0; t <= N; ++t) B[t] = horner_row(r + rb[t].off, rb[t].len, X, c.p, c.pinv);
+  eval_rows<N>(A, r, ra, X, c);
+  eval_rows<N>(B, r, rb, X, c);
 
   bool ok = canon(A[0], c.p) != 0;
   if (J.n >= 1 && canon(B[0], c.p) == 0) ok = false;
@@ -303,8 +328,8 @@ __device__ void general_instance(const ResJob& J, const RowDesc* rows, uint32_t*
   const RowDesc* ra = rows + J.rows_off;
   const RowDesc* rb = ra + J.rstride;
   uint32_t F[MAXY_GEN + 1], G[MAXY_GEN + 1];
-  for (int t = 0; t <= J.m; ++t) F[J.m - t] = canon(horner_row(r + ra[t].off, ra[t].len, X, c.p, c.pinv), c.p);
-  for (int t = 0; t <= J.n; ++t) G[J.n - t] = canon(horner_row(r + rb[t].off, rb[t].len, X, c.p, c.pinv), c.p);
+  for (int t = 0; t <= J.m; ++t) F[J.m - t] = canon(horner_grouped(r, ra[t / ROWGRP], t % ROWGRP, X, c), c.p);
+  for (int t = 0; t <= J.n; ++t) G[J.n - t] = canon(horner_grouped(r, rb[t / ROWGRP], t % ROWGRP, X, c), c.p);
   uint32_t res = res_general(F, J.m, G, J.n, c);
   if (J.sign) res = mneg(res, c.p);
   ws[J.val_off + (int64_t)pi * (J.D + 1) + j] = res;

@@ -25,7 +25,11 @@ struct PrimeC {
 
 __device__ __forceinline__ uint32_t redc(uint64_t t, uint32_t p, uint32_t pinv) {
   uint32_t m = (uint32_t)t * pinv;
-  return (uint32_t)((t + (uint64_t)m * p) >> 32);
+  uint32_t r = (uint32_t)((t + (uint64_t)m * p) >> 32);
+  // Opaque 32-bit result: keeps the compiler from carrying it as a 64-bit
+  // value into the next product (which costs an extra 64x32 multiply-add).
+  asm("" : "+v"(r));
+  return r;
 }
 
 // a*b in Montgomery form, a,b in [0,3p) -> [0, 2p)

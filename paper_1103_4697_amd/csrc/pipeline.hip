@@ -228,19 +228,27 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     RowDesc* ra = rows + J.rows_off;
     int off = 0;
     auto emit = [&](const Operand& O, RowDesc* rd, int deg) {
-      for (int t = 0; t < P.rstride; ++t) {
-        rd[t].off = 0; rd[t].len = 0;
-        if (t > deg) continue;
-        const int row = deg - t;
-        const int len = O.rowdeg[row] + 1;
-        rd[t].off = off; rd[t].len = len;
-        for (int k = 0; k < len; ++k) {
-          const uint32_t* src = O.limbs + ((size_t)row * (O.dx + 1) + k) * O.nl;
-          uint32_t* dst = coef + cw + (size_t)(off + k) * P.nl;
-          const uint32_t ext = (src[O.nl - 1] >> 31) ? 0xffffffffu : 0u;
-          for (int l = 0; l < P.nl; ++l) dst[l] = l < O.nl ? src[l] : ext;
+      for (int g = 0; g < P.rstride; ++g) {
+        rd[g].off = 0; rd[g].len = 0;
+        const int t0 = g * ROWGRP;
+        if (t0 > deg) continue;
+        int ml = 0;
+        for (int q = 0; q < ROWGRP && t0 + q <= deg; ++q) ml = std::max(ml, O.rowdeg[deg - t0 - q] + 1);
+        rd[g].off = off; rd[g].len = ml;
+        for (int kx = 0; kx < ml; ++kx) {
+          for (int q = 0; q < ROWGRP; ++q) {
+            uint32_t* dst = coef + cw + (size_t)(off + ROWGRP * kx + q) * P.nl;
+            const int row = deg - t0 - q;
+            if (t0 + q > deg || kx > O.rowdeg[row]) {
+              for (int l = 0; l < P.nl; ++l) dst[l] = 0u;
+              continue;
+            }
+            const uint32_t* src = O.limbs + ((size_t)row * (O.dx + 1) + kx) * O.nl;
+            const uint32_t ext = (src[O.nl - 1] >> 31) ? 0xffffffffu : 0u;
+            for (int l = 0; l < P.nl; ++l) dst[l] = l < O.nl ? src[l] : ext;
+          }
         }
-        off += len;
+        off += ROWGRP * ml;
       }
     };
     emit(A, ra, P.m);

@@ -195,11 +195,19 @@ int plan_resultant(const Operand& F, const Operand& G, ResPlan& P, std::string& 
   P.L = (int)std::ceil((std::max(P.log2B, 0.0) + 2.0) / 32.0);
   if (P.L < 1) P.L = 1;
   P.nl = std::max(F.nl, G.nl);
-  P.T = 0;
-  for (int d : F.rowdeg) P.T += d + 1;
-  for (int d : G.rowdeg) P.T += d + 1;
   P.cls = fast_class_of(P.m);
-  P.rstride = P.cls >= 0 ? fast_class_cap(P.cls) + 1 : P.m + 1;
+  const int width = P.cls >= 0 ? fast_class_cap(P.cls) : P.m;
+  P.rstride = (width + 1 + ROWGRP - 1) / ROWGRP;
+  // residues per prime: rows top-down in groups of four, each group padded to its longest row
+  P.T = 0;
+  for (const Operand* O : {&F, &G}) {
+    const int deg = O->ydeg;
+    for (int t0 = 0; t0 <= deg; t0 += ROWGRP) {
+      int ml = 0;
+      for (int q = 0; q < ROWGRP && t0 + q <= deg; ++q) ml = std::max(ml, O->rowdeg[deg - t0 - q] + 1);
+      P.T += ROWGRP * ml;
+    }
+  }
   return SNC_OK;
 }
 

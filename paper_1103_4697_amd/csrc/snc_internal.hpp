@@ -28,8 +28,8 @@ struct ResJob {
   int32_t T;           // residues per prime (coefficients of f and g)
   int32_t L;           // output limbs per coefficient
   int32_t nl;          // limbs per input coefficient
-  int32_t rows_off;    // first RowDesc of A (rstride entries, rows m..0 then len-0 padding), then B
-  int32_t rstride;     // RowDescs per operand (register class width + 1, or max(m, n) + 1)
+  int32_t rows_off;    // first RowDesc of A (rstride groups), then those of B
+  int32_t rstride;     // row groups per operand: ceil((width + 1) / 4), width = register class or m
   int64_t coef_off;    // input limbs [T][nl] (uint32 index)
   int64_t res_off;     // residues [k][T] (uint32 index)
   int64_t val_off;     // values at points, then coefficients mod p: [k][D+1]
@@ -38,10 +38,15 @@ struct ResJob {
   int64_t out_off;     // output limbs [D+1][L]
 };
 
+// Rows of an operand are stored top-down (row of y^deg first) in groups of
+// four: group g holds rows 4g..4g+3 interleaved coefficient-major, zero-padded
+// to the longest of the four: residue off + 4c + q = coefficient of x^c of row
+// 4g + q.
 struct RowDesc {
-  int32_t off;  // first residue of the row within a prime's block of T
-  int32_t len;  // number of x-coefficients (degree + 1, 0 for a zero row)
+  int32_t off;  // first residue of the group within a prime's block of T
+  int32_t len;  // coefficients per row of the group (0 for an all-zero group)
 };
+constexpr int ROWGRP = 4;
 
 // Constant tables of a Chinese-remainder reconstruction over primes
 // q_0..q_{k-1}: garner[i] = Montgomery form of (Q_i mod q_i)^-1 and
