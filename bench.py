@@ -59,6 +59,65 @@ def cpu_baseline(f, g, cores: int):
     return r, dt
 
 
+def serving(snc, synth, ctx, nreq, progress):
+    """Request stream of resultants and gcds (4:1) through the serving loop:
+    saturation throughput with everything queued, then Poisson arrivals at
+    0.5x and 0.8x of it; latency = finish - submit on the server's clock."""
+    import numpy as np
+
+    reqs = synth.config4(nreq)
+    srv = snc.Server(pool_bytes=8 << 30, max_slots=256, nstreams=4, ctx=ctx)
+
+    def submit(kind, x, y):
+        return srv.submit_resultant(x, y) if kind == "res" else srv.submit_gcd(x, y)
+
+    done = 0
+    res = {"workload": "4:1 mix of res_y requests (total degrees 10..50, 8..64-bit) and gcd requests "
+                       "(degree 100..2000 with a shared factor of degree 5..50)", "requests": nreq}
+    # saturation
+    t0 = time.perf_counter()
+    tickets = [submit(k, x, y) for k, x, y in reqs]
+    ok = srv.wait(done + nreq, 600.0)
+    t1 = time.perf_counter()
+    done += nreq
+    sat = nreq / (t1 - t0)
+    lat = np.array([srv.times(t)[1] - srv.times(t)[0] for t in tickets])
+    results = [srv.poll(t) for t in tickets]
+    # each result equals the same request computed alone (sampled)
+    sample = list(range(0, nreq, max(1, nreq // 24)))
+    same = all(results[i] == (snc.resultant_y(reqs[i][1], reqs[i][2], ctx) if reqs[i][0] == "res"
+                              else snc.gcd_z(reqs[i][1], reqs[i][2], ctx)) for i in sample)
+    res.update({"saturation_req_per_s": round(sat, 2), "all_finished": bool(ok),
+                "saturation_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "saturation_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "alone_vs_mix_identical_sample": bool(same), "sample_size": len(sample)})
+    progress(f"serving saturation {sat:.1f} req/s")
+    rng = np.random.default_rng(4321)
+    for frac in (0.5, 0.8):
+        rate = frac * sat
+        arr = synth.poisson_arrivals(rng, rate, nreq)
+        tickets = []
+        start = time.perf_counter()
+        for (k, x, y), at in zip(reqs, arr):
+            while time.perf_counter() - start < at:
+                pass
+            tickets.append(submit(k, x, y))
+        ok = srv.wait(done + nreq, 600.0)
+        t_end = time.perf_counter()
+        done += nreq
+        lat = np.array([srv.times(t)[1] - srv.times(t)[0] for t in tickets])
+        for t in tickets:
+            srv.poll(t)
+        res[f"rate_{frac}"] = {"offered_req_per_s": round(rate, 2),
+                               "completed_req_per_s": round(nreq / (t_end - start), 2),
+                               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                               "all_finished": bool(ok)}
+        progress(f"serving at {frac} x saturation: p50 {res[f'rate_{frac}']['p50_ms']} ms")
+    srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +125,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (reference for HBM byte counters)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many resultant+gcd steps (for profilers) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on a single GPU; --gpus must be 1", file=sys.stderr)
@@ -85,6 +150,15 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        progress(f"copy calibration: {nbytes} bytes read and written")
+        del src, dst
     ctx = snc.Context(0)
     f, g = synth.config1()
     plan = snc.resultant_plan(f, g)
@@ -99,6 +173,12 @@ def main():
         G = snc.gcd_z_limbs(Rl, snc.derivative_limbs(Rl), ctx)
         return d, G
 
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            step()
+        torch.cuda.synchronize()
+        progress(f"profile run: {args.profile_steps} steps done")
+        return
     progress("warmup")
     for _ in range(args.warmup):
         step()
@@ -194,6 +274,10 @@ def main():
                           "plain_resultants_per_s": round(1.0 / pt, 2),
                           "speedup": round((len(pairs) / bt) * pt, 3),
                           "batched_ms": round(bt * 1e3, 3)}
+
+    if not args.no_serving:
+        progress("serving workload")
+        out["serving"] = serving(snc, synth, ctx, args.serving_requests, progress)
 
     if not args.no_cpu_baseline:
         progress("cpu baseline")

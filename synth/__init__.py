@@ -112,12 +112,9 @@ def univariate_product(a: list[int], b: list[int]) -> list[int]:
     Used only to plant a common factor into generated gcd inputs."""
     if not a or not b:
         return []
-    c = [0] * (len(a) + len(b) - 1)
-    for i, x in enumerate(a):
-        if x:
-            for j, y in enumerate(b):
-                c[i + j] += x * y
-    return c
+    A = np.array([int(x) for x in a], dtype=object)
+    B = np.array([int(y) for y in b], dtype=object)
+    return [int(v) for v in np.convolve(A, B)]
 
 
 def as_int64(C) -> np.ndarray:
