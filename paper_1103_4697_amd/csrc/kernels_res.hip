@@ -379,135 +379,169 @@ void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
 // (4) Interpolation mod p from the values at x = 0..D, one workgroup per
 //     (resultant, prime).
 //   Newton coefficients of equispaced data, a_k = (Delta^k v_0) / k!, are the
-//   convolution a_k = sum_{i<=k} (v_i / i!) ((-1)^{k-i} / (k-i)!), evaluated by
-//   every thread independently.  The Newton form
-//     P = sum_k a_k N_k,  N_k = x (x-1) ... (x-k+1)
-//   is expanded blockwise: with blocks of 64 terms starting at b = 64j,
+//   convolution a_k = sum_{i<=k} (v_i / i!) ((-1)^{k-i} / (k-i)!).  The Newton
+//   form P = sum_k a_k N_k, N_k = x (x-1) ... (x-k+1), is expanded blockwise:
+//   with blocks of 64 terms starting at b = 64j,
 //     Q_j = sum_{t<64} a_{b+t} prod_{i=b}^{b+t-1} (x - i),   F_j = prod_{i=b}^{b+63} (x - i),
-//   one wavefront builds Q_j and F_j by 64 lane-shift steps (no barriers),
-//   and P = Q_0 + F_0 (Q_1 + F_1 (Q_2 + ...)) takes one parallel polynomial
-//   product per block.
+//   and P = Q_0 + F_0 (Q_1 + F_1 (Q_2 + ...)).
+//   Both the convolution and the products P F_j are Toeplitz sums; a
+//   wavefront owns 64 consecutive outputs (one per lane), takes the uniform
+//   operand from a register by readlane and the sliding one from LDS (one
+//   coalesced read per product), and reduces every 8 products.  Q_j and F_j
+//   are built by the wavefront that computed a_{64j..64j+63}, by 64 steps of
+//   a one-lane shift (DPP) and a multiply-add, without barriers.
 // ---------------------------------------------------------------------------
-constexpr int IB = 64;  // Newton terms per block (one per lane)
+constexpr int IB = 64;    // Newton terms per block (one per lane)
+constexpr int IPAD = 64;  // zero words below index 0 of the sliding operands
+static_assert((4 * ((MAX_D + IB) / IB * IB) + 2 * IPAD) * 4 <= 160 * 1024,
+              "interpolation buffers for the largest degree bound exceed the LDS of a CU");
 
-__device__ __forceinline__ uint32_t shift_up1(uint32_t v, int lane) {
-  const uint32_t u = __shfl_up(v, 1, 64);
-  return lane == 0 ? 0u : u;
+// Montgomery form of 1/t! for every prime of the table and t <= MAX_D
+// (filled once per device by k_ifact_init).
+__device__ uint32_t g_ifact[(int64_t)KMAX * (MAX_D + 1)];
+
+__global__ void k_ifact_init() {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= KMAX) return;
+  const PrimeC c = g_primes[pi];
+  uint32_t f = c.r1;
+  for (int t = 2; t <= MAX_D; ++t) f = mmulc(f, to_mont((uint32_t)t, c), c.p, c.pinv);
+  uint32_t inv = minv(f, c);  // 1/MAX_D!
+  uint32_t* row = g_ifact + (int64_t)pi * (MAX_D + 1);
+  for (int t = MAX_D; t >= 1; --t) {
+    row[t] = inv;
+    inv = mmulc(inv, to_mont((uint32_t)t, c), c.p, c.pinv);
+  }
+  row[0] = inv;
+}
+
+void launch_ifact_init(hipStream_t s) {
+  hipLaunchKernelGGL(k_ifact_init, dim3(KMAX / 64), dim3(64), 0, s);
+}
+
+// lane L receives lane L-1 of v, lane 0 receives 0
+__device__ __forceinline__ uint32_t lane_shr1(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// sum_{q<64} U[q] * S[-q] with U uniform (lane q of u) and S per lane; s canonical in, out
+__device__ __forceinline__ uint32_t toeplitz64(uint32_t s, uint32_t u, const uint32_t* S, const PrimeC& c) {
+#pragma unroll
+  for (int g = 0; g < IB; g += 8) {
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = g; q < g + 8; ++q) acc += (uint64_t)bcast(u, q) * S[-q];  // 8 p^2 < 2^63
+    s = canon(s + redc(acc, c.p, c.pinv), c.p);
+  }
+  return s;
 }
 
 __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, const int64_t* prefix,
                                                            int njobs, uint32_t* ws) {
   extern __shared__ uint32_t sm[];
+  constexpr int NW = INTERP_THREADS / 64;
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
   const int pi = (int)(b - prefix[jj]);
   const PrimeC c = g_primes[pi];
-  const int D = J.D;
-  const int n1 = D + 1;
+  const int n1 = J.D + 1;
   const int nblk = (n1 + IB - 1) / IB;
-  const int Dp = nblk * IB;  // padded buffer length
+  const int Dp = nblk * IB;
   uint32_t* V = ws + J.val_off + (int64_t)pi * n1;
-  uint32_t* R0 = sm;
-  uint32_t* R1 = sm + Dp;
-  uint32_t* R2 = sm + 2 * Dp;
-  uint32_t* R3 = sm + 3 * Dp;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
+  uint32_t* Wp = sm;             // [IPAD + Dp]: zeros, then w_j = (-1)^j / j!; later a P buffer
+  uint32_t* Qb = Wp + IPAD + Dp; // [Dp]: Q_j at 64j
+  uint32_t* Fb = Qb + Dp;        // [Dp]: coefficients 0..63 of F_j at 64j (x^64 implied)
+  uint32_t* P1 = Fb + Dp;        // [IPAD + Dp]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  // factorials by an inclusive prefix product (Hillis-Steele, double-buffered)
-  for (int t = tid; t < n1; t += INTERP_THREADS) R0[t] = t ? to_mont((uint32_t)t, c) : c.r1;
-  __syncthreads();
-  uint32_t* in = R0;
-  uint32_t* out = R1;
-  for (int off = 1; off < n1; off <<= 1) {
-    for (int t = tid; t < n1; t += INTERP_THREADS)
-      out[t] = t >= off ? mmulc(in[t], in[t - off], c.p, c.pinv) : in[t];
-    __syncthreads();
-    uint32_t* tmp = in; in = out; out = tmp;
-  }
-  for (int t = tid; t < n1; t += INTERP_THREADS) R2[t] = minv(in[t], c);  // 1/t!
-  __syncthreads();
-  // u_i = v_i / i! (R0),  w_j = (-1)^j / j! (R1)
-  for (int t = tid; t < n1; t += INTERP_THREADS) {
-    const uint32_t inv = R2[t];
-    R0[t] = mmulc(canon(V[t], c.p), inv, c.p, c.pinv);
-    R1[t] = (t & 1) ? mneg(inv, c.p) : inv;
-  }
-  __syncthreads();
-  // a_k = sum_{i<=k} u_i w_{k-i} (R2), 64-bit lazy accumulation, reduce every 8 terms
-  for (int kk = tid; kk < n1; kk += INTERP_THREADS) {
-    uint32_t sum = 0;
-    int i = 0;
-    while (i <= kk) {
-      uint64_t acc = 0;
-      const int e = min(kk, i + 7);
-      for (; i <= e; ++i) acc += (uint64_t)R0[i] * R1[kk - i];
-      sum = madd(sum, canon(redc(acc, c.p, c.pinv), c.p), c.p);
+  for (int t = tid; t < IPAD + Dp; t += INTERP_THREADS) {
+    const int j = t - IPAD;
+    uint32_t w = 0;
+    if (j >= 0 && j < n1) {
+      const uint32_t f = IF[j];
+      w = (j & 1) ? mneg(f, c.p) : f;
     }
-    R2[kk] = sum;
+    Wp[t] = w;
+    P1[t] = 0;
   }
   __syncthreads();
-  // per block j: Q_j into R0[64j..], F_j (non-leading coefficients; monic) into R1[64j..]
-  for (int j = wave; j < nblk; j += INTERP_THREADS / 64) {
-    const int b0 = j * IB;
+
+  for (int ob = wave; ob < nblk; ob += NW) {
+    const int b0 = ob * IB;
+    // a_k for k = b0 + lane
+    const uint32_t* wk = Wp + IPAD + b0 + lane;
+    uint32_t a = 0;
+    for (int ib = 0; ib <= ob; ++ib) {
+      const int i = ib * IB + lane;
+      const uint32_t u = i < n1 ? mmulc(canon(V[i], c.p), IF[i], c.p, c.pinv) : 0u;
+      a = toeplitz64(a, u, wk - ib * IB, c);
+    }
+    // Q_ob and F_ob, coefficient of x^lane in lane
     const int len = min(IB, n1 - b0);
-    uint32_t q = lane == 0 ? R2[b0 + len - 1] : 0u;
-    for (int kk = b0 + len - 2; kk >= b0; --kk) {  // Q <- Q (x - kk) + a_kk
-      const uint32_t nk = mneg(to_mont((uint32_t)kk, c), c.p);
-      const uint32_t prev = shift_up1(q, lane);
-      q = canon(mmul2(c.r1, prev, nk, q, c.p, c.pinv), c.p);
-      if (lane == 0) q = madd(q, R2[kk], c.p);
-    }
+    const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
+    uint32_t q = lane == 0 ? bcast(a, len - 1) : 0u;
     uint32_t f = lane == 0 ? c.r1 : 0u;
-    for (int i = b0; i < b0 + len; ++i) {  // F <- F (x - i)
-      const uint32_t ni = mneg(to_mont((uint32_t)i, c), c.p);
-      const uint32_t prev = shift_up1(f, lane);
-      f = canon(mmul2(c.r1, prev, ni, f, c.p, c.pinv), c.p);
+    for (int s = 0; s < IB; ++s) {
+      const uint32_t fprev = lane_shr1(f);  // F <- F (x - (b0 + s))
+      f = canon(redc((uint64_t)bcast(nk, s) * f + ((uint64_t)fprev << 32), c.p, c.pinv), c.p);
+      const int kq = len - 2 - s;           // Q <- Q (x - (b0 + kq)) + a_{b0 + kq}
+      if (kq >= 0) {
+        const uint32_t add = bcast(a, kq);
+        const uint32_t qprev = lane_shr1(q) + (lane == 0 ? add : 0u);
+        q = canon(redc((uint64_t)bcast(nk, kq) * q + ((uint64_t)qprev << 32), c.p, c.pinv), c.p);
+      }
     }
-    R0[b0 + lane] = q;
-    R1[b0 + lane] = f;  // lane == len holds the leading 1 when len < 64; never read
+    Qb[b0 + lane] = q;
+    Fb[b0 + lane] = f;
   }
   __syncthreads();
-  // P = Q_{nblk-1}; P <- P F_j + Q_j for j = nblk-2 .. 0
-  uint32_t* P = R2;
-  uint32_t* Pn = R3;
-  const int lastlen = n1 - (nblk - 1) * IB;
-  for (int t = tid; t < Dp; t += INTERP_THREADS) P[t] = t < lastlen ? R0[(nblk - 1) * IB + t] : 0u;
-  int dP = lastlen - 1;
+
+  // P = Q_{nblk-1}; P <- P F_j + Q_j for j = nblk-2 .. 0.  Entries above the
+  // current degree stay zero, so whole 64-blocks are computed and stored.
+  uint32_t* Pa = Wp;
+  uint32_t* Pb = P1;
+  const int lastb = (nblk - 1) * IB;
+  const int lastlen = n1 - lastb;
+  for (int t = tid; t < IPAD + Dp; t += INTERP_THREADS) {
+    const int x = t - IPAD;
+    Pa[t] = (x >= 0 && x < lastlen) ? Qb[lastb + x] : 0u;
+  }
   __syncthreads();
+  int dP = lastlen - 1;
   for (int j = nblk - 2; j >= 0; --j) {
-    const uint32_t* Fj = R1 + j * IB;  // degree IB, monic
-    const uint32_t* Qj = R0 + j * IB;
     const int dN = dP + IB;
-    for (int t = tid; t <= dN; t += INTERP_THREADS) {
-      const int i0 = max(0, t - dP), i1 = min(IB - 1, t);
-      uint32_t sum = 0;
-      int i = i0;
-      while (i <= i1) {
-        uint64_t acc = 0;
-        const int e = min(i1, i + 7);
-        for (; i <= e; ++i) acc += (uint64_t)Fj[i] * P[t - i];
-        sum = madd(sum, canon(redc(acc, c.p, c.pinv), c.p), c.p);
-      }
-      if (t >= IB) sum = madd(sum, P[t - IB], c.p);  // leading coefficient of F_j
-      if (t < IB) sum = madd(sum, Qj[t], c.p);
-      Pn[t] = sum;
+    const int nob = dN / IB + 1;
+    const uint32_t fj = Fb[j * IB + lane];
+    for (int ob = wave; ob < nob; ob += NW) {
+      const int t = ob * IB + lane;
+      const uint32_t* pt = Pa + IPAD + t;  // P[t - i] = pt[-i]
+      uint32_t s = pt[-IB];                // x^64 term of F_j
+      if (t < IB) s = madd(s, Qb[j * IB + t], c.p);
+      Pb[IPAD + t] = toeplitz64(s, fj, pt, c);
     }
     __syncthreads();
-    uint32_t* tmp = P; P = Pn; Pn = tmp;
+    uint32_t* tmp = Pa; Pa = Pb; Pb = tmp;
     dP = dN;
   }
-  for (int t = tid; t < n1; t += INTERP_THREADS) V[t] = from_mont(P[t], c);
+  for (int t = tid; t < n1; t += INTERP_THREADS) V[t] = from_mont(Pa[IPAD + t], c);
+}
+
+size_t interp_lds_bytes(int max_D) {
+  const size_t Dp = (size_t)((max_D + 1 + IB - 1) / IB) * IB;
+  return (4 * Dp + 2 * IPAD) * sizeof(uint32_t);
 }
 
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    int max_D, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
-  const size_t Dp = (size_t)((max_D + 1 + IB - 1) / IB) * IB;
-  size_t shmem = 4 * Dp * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_interp, dim3((unsigned)nblocks), dim3(INTERP_THREADS), shmem, s, jobs_d,
-                     blk_prefix_d, njobs, ws);
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)nblocks), dim3(INTERP_THREADS), interp_lds_bytes(max_D), s,
+                     jobs_d, blk_prefix_d, njobs, ws);
 }
 
 // ---------------------------------------------------------------------------

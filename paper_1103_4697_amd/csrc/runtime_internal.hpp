@@ -12,7 +12,6 @@
 namespace snc {
 
 constexpr int NCLS = 5;        // register classes of the fused evaluate+eliminate kernel
-constexpr int MAX_D = 13000;   // interpolation keeps 3(D+1) words in LDS
 
 struct Tables {
   std::vector<uint32_t> p;       // primes, descending below 2^30

@@ -13,7 +13,8 @@ constexpr int MAXY_FAST = 64;     // largest y-degree handled by the register-re
 constexpr int MAXY_GEN = 255;     // largest y-degree handled at all
 constexpr int EE_WAVES = 1;       // wavefronts per eval_elim workgroup
 constexpr int EE_BLOCK = 64 * EE_WAVES;
-constexpr int INTERP_THREADS = 256;
+constexpr int INTERP_THREADS = 1024;
+constexpr int MAX_D = 10000;     // largest degree bound: interpolation keeps 4(D+1)+O(1) words in LDS
 constexpr int CRT_COEF_PER_BLOCK = 4;   // one wavefront per coefficient
 constexpr int GCD_THREADS = 256;
 
@@ -89,6 +90,8 @@ __host__ __device__ inline int lx_of(int k) { return (30 * k + 31) / 32 + 2; }
 void upload_tables(const PrimeC* primes, const uint32_t* garner_c, const uint32_t* wtab,
                    const uint32_t* ptab, hipStream_t s);
 hipError_t configure_kernels();
+void launch_ifact_init(hipStream_t s);
+size_t interp_lds_bytes(int max_D);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    const uint32_t* ws, uint32_t* res_base, hipStream_t s);

@@ -123,6 +123,10 @@ def test_trivial_and_invalid_plans(snc):
     ok.limbs, ok.dy, ok.dx, ok.nlimbs = None, -1, 0, 1
     pl = snc.Plan()
     assert lib.snc_resultant_y_plan(C.byref(bad), C.byref(ok), C.byref(pl)) == snc.SNC_EINVAL
+    # degree bound above the supported maximum (total degrees 101 and 100)
+    rng = np.random.default_rng(77)
+    with pytest.raises(snc.SncError):
+        snc.resultant_plan(synth.dense_bivariate(rng, 101, bits=3), synth.dense_bivariate(rng, 100, bits=3))
     # y-degree above the supported maximum
     big = np.zeros((300, 1), dtype=np.int64)
     big[299, 0] = 1

@@ -159,6 +159,22 @@ def test_config3_sampled(snc):
             assert zx.evaluate(r, x0) % q == R.resultant_at_mod(f, g, x0, q)
 
 
+def test_largest_degree_bound(snc):
+    """Total degrees 100 and 100: the degree bound 10000 is the largest the
+    library accepts (interpolation buffers fill the LDS of a CU), y-degree
+    100 takes the general elimination.  Checked on sampled values."""
+    rng = np.random.default_rng(77)
+    f = synth.dense_bivariate(rng, 100, bits=3)
+    g = synth.dense_bivariate(rng, 100, bits=3)
+    assert snc.resultant_plan(f, g).deg_bound == 10000
+    r = snc.resultant_y(f, g)
+    assert len(r) - 1 <= 10000
+    rs = random.Random(5)
+    for q in (Q61, (1 << 61) - 31):
+        for x0 in (0, 1, 9999, rs.randrange(q)):
+            assert zx.evaluate(r, x0) % q == R.resultant_at_mod(f, g, x0, q)
+
+
 def test_batch_matches_plain_and_oracle(snc):
     pairs, common = synth.config2(npairs=48, frac_common=0.1)
     batch = snc.resultant_y_batch(pairs)
