@@ -123,7 +123,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const Prime
 // ---------------------------------------------------------------------------
 // Register-resident variant: one wavefront per prime, degrees below 64*E.
 // Polynomials are top-aligned (element i = coefficient of x^(deg-i)) and
-// lane-blocked (element i in lane i/E, slot i%E), values lazy in [0, 3p).
+// lane-blocked (element i in lane i/E, slot i%E), values lazy in [0, 4p).
 // An elementary Euclid step X <- lc(Y) X - lc(X) x^(dX-dY) Y pairs X[i] with
 // Y[i] (tops aligned) and shifts X down one element: E fused updates per
 // lane plus one lane shift, no LDS and no barrier.  Leading coefficients are
@@ -161,15 +161,53 @@ __device__ __forceinline__ int reg_trim(uint32_t (&X)[E], int d, const PrimeC& c
   return d;
 }
 
+// a x + b y + c z with a, b, c canonical and x, y, z < 4p: the sum stays
+// below 12 p^2 + 2^32 p < 2^64 (p < 2^30) and the result below 4p.
+__device__ __forceinline__ uint32_t mmul3(uint32_t a, uint32_t x, uint32_t b, uint32_t y, uint32_t cc,
+                                          uint32_t z, uint32_t p, uint32_t pinv) {
+  const uint64_t t = (uint64_t)a * x + (uint64_t)b * y + (uint64_t)cc * z;
+  return redc(t, p, pinv);
+}
+
+// The normal remainder step (deg X = deg Y + 1) as one update: the pseudo-
+// remainder lc(Y)^2 X - (lc(Y) lc(X) x + lc(Y) X_1 - lc(X) Y_1) Y, top-aligned
+// at degree deg Y - 1, is R[i] = a X[i+2] + b Y[i+2] + cc Y[i+1] with
+// a = lc(Y)^2, b = -lc(Y) lc(X), cc = lc(X) Y_1 - lc(Y) X_1.  Elements i+1,
+// i+2 past the last slot come from the first two slots of the next lane.
+template <int E>
+__device__ __forceinline__ void reg_step2(uint32_t (&X)[E], const uint32_t (&Y)[E], uint32_t a, uint32_t b,
+                                          uint32_t cc, const PrimeC& c) {
+  static_assert(E >= 2, "two slots per lane");
+  const uint32_t nx0 = from_next_lane(X[0]), nx1 = from_next_lane(X[1]);
+  const uint32_t ny0 = from_next_lane(Y[0]), ny1 = from_next_lane(Y[1]);
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const uint32_t x2 = s + 2 < E ? X[s + 2] : (s + 2 == E ? nx0 : nx1);
+    const uint32_t y2 = s + 2 < E ? Y[s + 2] : (s + 2 == E ? ny0 : ny1);
+    const uint32_t y1 = s + 1 < E ? Y[s + 1] : ny0;
+    X[s] = mmul3(a, x2, b, y2, cc, y1, c.p, c.pinv);
+  }
+}
+
 // reduce X by Y until deg X < deg Y (Y fixed, deg Y >= 0)
 template <int E>
 __device__ __forceinline__ int reg_reduce(uint32_t (&X)[E], int dX, const uint32_t (&Y)[E], int dY,
                                           const PrimeC& c) {
   const uint32_t lcY = lead(Y[0], c.p);
+  const uint32_t y1 = lead(Y[1], c.p);
+  const uint32_t a = mmulc(lcY, lcY, c.p, c.pinv);
   while (dX >= dY) {
     const uint32_t lcX = lead(X[0], c.p);
-    reg_step<E>(X, Y, lcY, c.p - lcX, c);
-    dX = reg_trim<E>(X, dX - 1, c);
+    if (dX == dY + 1 && dY >= 1) {
+      const uint32_t x1 = lead(X[1], c.p);
+      const uint32_t b = mneg(mmulc(lcY, lcX, c.p, c.pinv), c.p);
+      const uint32_t cc = msub(mmulc(lcX, y1, c.p, c.pinv), mmulc(lcY, x1, c.p, c.pinv), c.p);
+      reg_step2<E>(X, Y, a, b, cc, c);
+      dX = reg_trim<E>(X, dX - 2, c);
+    } else {
+      reg_step<E>(X, Y, lcY, c.p - lcX, c);
+      dX = reg_trim<E>(X, dX - 1, c);
+    }
   }
   return dX;
 }
