@@ -212,6 +212,48 @@ __device__ __forceinline__ int reg_reduce(uint32_t (&X)[E], int dX, const uint32
   return dX;
 }
 
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Multipliers of the fused step from the canonical top pairs (p0, p1) of the
+// dividend and (q0, q1) of the divisor, computed on the vector unit with
+// lane 0's values (other lanes compute garbage that is never read) and then
+// made uniform: cheaper than the same Montgomery products on the scalar unit.
+__device__ __forceinline__ void step2_coefs(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1, uint32_t& a,
+                                            uint32_t& b, uint32_t& cc, const PrimeC& c) {
+  a = uni(mmulc(q0, q0, c.p, c.pinv));
+  b = uni(c.p - mmulc(q0, p0, c.p, c.pinv));  // -q0 p0, in (0, p]
+  cc = uni(msub(mmulc(p0, q1, c.p, c.pinv), mmulc(q0, p1, c.p, c.pinv), c.p));
+}
+
+// Runs of normal remainder steps (each remainder one degree below its
+// divisor) with fixed register roles: X <- prem(X, Y), then Y <- prem(Y, X).
+// The divisor's top pair is carried over from the step that produced it, so
+// a step reads only the two top coefficients of its new remainder.  Returns
+// at the first step that is not normal (the general loop takes over).
+template <int E>
+__device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (&Y)[E], int& dY, const PrimeC& c) {
+  if (dX != dY + 1 || dY < 1) return;
+  uint32_t x0 = canon(X[0], c.p), x1 = canon(X[1], c.p);
+  uint32_t y0 = canon(Y[0], c.p), y1 = canon(Y[1], c.p);
+  uint32_t a, b, cc;
+  while (true) {
+    step2_coefs(x0, x1, y0, y1, a, b, cc, c);
+    reg_step2<E>(X, Y, a, b, cc, c);
+    dX -= 2;
+    x0 = canon(X[0], c.p);
+    if (uni(x0) == 0) { dX = reg_trim<E>(X, dX, c); return; }
+    if (dX < 1) return;
+    x1 = canon(X[1], c.p);
+    step2_coefs(y0, y1, x0, x1, a, b, cc, c);
+    reg_step2<E>(Y, X, a, b, cc, c);
+    dY -= 2;
+    y0 = canon(Y[0], c.p);
+    if (uni(y0) == 0) { dY = reg_trim<E>(Y, dY, c); return; }
+    if (dY < 1) return;
+    y1 = canon(Y[1], c.p);
+  }
+}
+
 // load coefficients 0..deg of a residue row (scaled by sc) top-aligned
 template <int E>
 __device__ __forceinline__ void reg_load(uint32_t (&X)[E], const uint32_t* row, int deg, uint32_t sc, int lane,
@@ -254,6 +296,7 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(GcdDesc G, const PrimeC* pr
   int dY = reg_trim<E>(Y, G.db, c);
   int e;
   while (true) {
+    normal_run<E>(X, dX, Y, dY, c);
     if (dY < 0) {
       e = dX;
 #pragma unroll

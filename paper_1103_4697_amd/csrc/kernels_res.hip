@@ -124,29 +124,37 @@ __device__ __forceinline__ uint32_t horner_grouped(const uint32_t* r, const RowD
   return acc;
 }
 
-// One remainder step X <- prem(X, Y) on the first C+1 entries of the
-// register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
-// above each degree zero).  Branch-free inside an elementary step.
 // The N+1 rows of one operand evaluated at X, four rows at a time from the
-// interleaved group layout: one 16-byte scalar load per step feeds four
-// independent Horner chains (instruction-level parallelism for a lone
-// wavefront).  Zero padding at the top keeps a Horner accumulator at zero.
+// interleaved group layout: each 64-byte scalar load holds four Horner steps
+// of four independent chains (instruction-level parallelism for a lone
+// wavefront), so one load latency is paid per 48 multiply-adds.  Group
+// lengths are padded at the top with zeros, which keep a Horner accumulator
+// at zero.
+struct alignas(16) HChunk {
+  uint4 v[HCHUNK];
+};
+
+__device__ __forceinline__ void horner_chunk(uint32_t& a0, uint32_t& a1, uint32_t& a2, uint32_t& a3,
+                                             const HChunk& h, uint32_t X, const PrimeC& c) {
+#pragma unroll
+  for (int u = HCHUNK - 1; u >= 0; --u) {
+    const uint4 v = h.v[u];
+    a0 = mhorner(a0, X, v.x, c.p, c.pinv);
+    a1 = mhorner(a1, X, v.y, c.p, c.pinv);
+    a2 = mhorner(a2, X, v.z, c.p, c.pinv);
+    a3 = mhorner(a3, X, v.w, c.p, c.pinv);
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* r, const RowDesc* rd,
                                           uint32_t X, const PrimeC& c) {
 #pragma unroll
   for (int t0 = 0; t0 <= N; t0 += ROWGRP) {
     const RowDesc d = rd[t0 / ROWGRP];
-    const uint4* q = reinterpret_cast<const uint4*>(r + d.off);
+    const HChunk* q = reinterpret_cast<const HChunk*>(r + d.off);
     uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll 2
-    for (int k = d.len - 1; k >= 0; --k) {
-      const uint4 v = q[k];
-      a0 = mhorner(a0, X, v.x, c.p, c.pinv);
-      a1 = mhorner(a1, X, v.y, c.p, c.pinv);
-      a2 = mhorner(a2, X, v.z, c.p, c.pinv);
-      a3 = mhorner(a3, X, v.w, c.p, c.pinv);
-    }
+    for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) horner_chunk(a0, a1, a2, a3, q[ch], X, c);
     A[t0] = a0;
     if (t0 + 1 <= N) A[t0 + 1] = a1;
     if (t0 + 2 <= N) A[t0 + 2] = a2;
@@ -154,6 +162,9 @@ __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* 
   }
 }
 
+// One remainder step X <- prem(X, Y) on the first C+1 entries of the
+// register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
+// above each degree zero).  Branch-free inside an elementary step.
 template <int N, int C>
 __device__ __forceinline__ void rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, int b,
                                       int s, bool& ok, uint32_t& den, const PrimeC& c) {

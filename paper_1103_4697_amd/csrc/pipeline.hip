@@ -234,6 +234,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
         if (t0 > deg) continue;
         int ml = 0;
         for (int q = 0; q < ROWGRP && t0 + q <= deg; ++q) ml = std::max(ml, O.rowdeg[deg - t0 - q] + 1);
+        ml = padded_group_len(ml);
         rd[g].off = off; rd[g].len = ml;
         for (int kx = 0; kx < ml; ++kx) {
           for (int q = 0; q < ROWGRP; ++q) {

@@ -200,13 +200,14 @@ int plan_resultant(const Operand& F, const Operand& G, ResPlan& P, std::string& 
   const int width = P.cls >= 0 ? fast_class_cap(P.cls) : P.m;
   P.rstride = (width + 1 + ROWGRP - 1) / ROWGRP;
   // residues per prime: rows top-down in groups of four, each group padded to its longest row
+  // (rounded up to a whole number of 64-byte chunks)
   P.T = 0;
   for (const Operand* O : {&F, &G}) {
     const int deg = O->ydeg;
     for (int t0 = 0; t0 <= deg; t0 += ROWGRP) {
       int ml = 0;
       for (int q = 0; q < ROWGRP && t0 + q <= deg; ++q) ml = std::max(ml, O->rowdeg[deg - t0 - q] + 1);
-      P.T += ROWGRP * ml;
+      P.T += ROWGRP * padded_group_len(ml);
     }
   }
   return SNC_OK;

@@ -48,6 +48,8 @@ struct RowDesc {
   int32_t len;  // coefficients per row of the group (0 for an all-zero group)
 };
 constexpr int ROWGRP = 4;
+constexpr int HCHUNK = 4;   // Horner steps per 64-byte scalar load; group lengths are padded to a multiple
+__host__ __device__ inline int padded_group_len(int ml) { return (ml + HCHUNK - 1) / HCHUNK * HCHUNK; }
 
 // Constant tables of a Chinese-remainder reconstruction over primes
 // q_0..q_{k-1}: garner[i] = Montgomery form of (Q_i mod q_i)^-1 and
