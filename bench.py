@@ -170,7 +170,7 @@ def main():
         batch.run()
         d = batch.out[0].deg
         Rl = batch.bufs[0][: d + 1]
-        G = snc.gcd_z_limbs(Rl, snc.derivative_limbs(Rl), ctx)
+        G = snc.gcd_z_deriv_limbs(Rl, ctx)
         return d, G
 
     if args.profile_steps:
@@ -209,9 +209,8 @@ def main():
             stages[name] = stages.get(name, 0.0) + ms / nrep
     gstages = {}
     Rl = batch.bufs[0][: d + 1]
-    Rpl = snc.derivative_limbs(Rl)
     for _ in range(nrep):
-        snc.gcd_z_limbs(Rl, Rpl, ctx)
+        snc.gcd_z_deriv_limbs(Rl, ctx)
         for name, ms, _n in ctx.timing():
             gstages[name] = gstages.get(name, 0.0) + ms / nrep
     ctx.set_timing(False)

@@ -143,9 +143,25 @@ int snc_prepared_destroy(snc_prepared* prep);
  * mod each prime on the device, primes of minimal gcd degree kept, CRT, and
  * an exact certificate (norm bound on the lifted product) before the result
  * is accepted; unlucky primes are replaced by more primes. */
+/* gcd(a, b) of a, b in Z[x] (see snc_upoly), normalised to a positive
+ * leading coefficient; the zero polynomial (deg -1) when a = b = 0.
+ * plan: deg_bound and out_nlimbs bound the result, workspace_bytes sizes
+ *   d_ws (0: the result needs no device work).
+ * d_ws: device workspace of ws_bytes, caller-owned, not retained; SNC_ENOMEM
+ *   if smaller than the plan asks.  out: caller-allocated; on SNC_ERANGE
+ *   out->deg and out->nlimbs hold the sizes needed and nothing is written.
+ * stream: HIP stream for the device work; the call returns when the result
+ *   is in out (host memory). */
 int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out);
 int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
               void* stream, snc_upoly* out);
+
+/* gcd(a, a') with a' the formal derivative of a, formed inside the library:
+ * the square-free part of the resultant R in the projection phase
+ * (Section 2.1) is R / gcd(R, R').  Same conventions as snc_gcd_z. */
+int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out);
+int snc_gcd_z_deriv(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream,
+                    snc_upoly* out);
 
 /* ---- serving --------------------------------------------------------------
  * A request loop with continuous batching.  The server owns the device pool

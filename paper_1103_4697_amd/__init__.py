@@ -81,6 +81,8 @@ def lib():
                 "snc_server_destroy": (C.c_int, [VP]),
                 "snc_gcd_z_plan": (C.c_int, [P(Upoly), P(Upoly), P(Plan)]),
                 "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
+                "snc_gcd_z_deriv_plan": (C.c_int, [P(Upoly), P(Plan)]),
+                "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(L, name, None)
@@ -384,58 +386,98 @@ def resultant_y_batch(pairs, ctx: Context | None = None, stream=None) -> list:
 # gcd in Z[x]
 # ---------------------------------------------------------------------------
 
-def gcd_z(a, b, ctx: Context | None = None, stream=None) -> list:
-    """gcd(a, b) in Z[x] (content kept, positive leading coefficient)."""
-    ctx = ctx or default_context()
-    keep = []
-    ua, ub = _as_upoly(a, keep), _as_upoly(b, keep)
-    p = Plan()
-    ctx.check(lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)), "gcd plan")
-    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
-    ws = ctx.workspace(p.workspace_bytes)
-    st = lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
-                         C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
-    ctx.check(st, "snc_gcd_z")
-    return _read_upoly(u, buf)
+def _limbs_upoly(x: np.ndarray):
+    """Upoly view of a uint32 [deg+1][nl] limb array (rows ascending)."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    u = Upoly()
+    if x.ndim != 2 or x.shape[0] == 0:
+        u.limbs, u.deg, u.nlimbs = None, -1, 1
+    else:
+        u.limbs = x.ctypes.data_as(C.POINTER(C.c_uint32))
+        u.deg, u.nlimbs = x.shape[0] - 1, x.shape[1]
+    return u, x
+
+
+def _run_gcd(ctx: Context, run, plan):
+    """Call a gcd entry point with the context's workspace and a cached output
+    buffer; the plan is asked only when the call reports that the workspace
+    (SNC_ENOMEM) or the output (SNC_ERANGE) is too small.  Returns the result
+    rows as a fresh uint32 [deg+1][nl] array."""
+    buf = getattr(ctx, "_gcd_buf", None)
+    ws = ctx._ws
+    if buf is None or ws is None:
+        p = Plan()
+        ctx.check(plan(p), "gcd plan")
+        buf = np.zeros((max(p.deg_bound, 0) + 1, max(p.out_nlimbs, 1)), dtype=np.uint32)
+        ws = ctx.workspace(p.workspace_bytes)
+    for _ in range(3):
+        u = Upoly()
+        u.limbs = buf.ctypes.data_as(C.POINTER(C.c_uint32))
+        u.deg, u.nlimbs = buf.shape[0] - 1, buf.shape[1]
+        st = run(ws, u)
+        if st == SNC_OK:
+            ctx._gcd_buf = buf
+            return buf[: u.deg + 1].copy()
+        if st == SNC_ERANGE:
+            buf = np.zeros((max(u.deg, buf.shape[0] - 1) + 1, max(u.nlimbs, buf.shape[1])), dtype=np.uint32)
+        elif st == SNC_ENOMEM:
+            p = Plan()
+            ctx.check(plan(p), "gcd plan")
+            ws = ctx.workspace(p.workspace_bytes)
+        else:
+            break
+    ctx.check(st, "gcd")
+    raise SncError(st, "gcd: sizes did not settle")
 
 
 def gcd_z_limbs(a_limbs: np.ndarray, b_limbs: np.ndarray, ctx: Context | None = None, stream=None):
     """gcd on limb arrays (uint32 [deg+1][nl], two's complement): returns the
     result as a uint32 [deg+1][nl] array (empty for the zero polynomial)."""
     ctx = ctx or default_context()
-    a_limbs = np.ascontiguousarray(a_limbs, dtype=np.uint32)
-    b_limbs = np.ascontiguousarray(b_limbs, dtype=np.uint32)
-    ua, ub = Upoly(), Upoly()
-    ua.limbs = a_limbs.ctypes.data_as(C.POINTER(C.c_uint32)); ua.deg = a_limbs.shape[0] - 1; ua.nlimbs = a_limbs.shape[1]
-    ub.limbs = b_limbs.ctypes.data_as(C.POINTER(C.c_uint32)); ub.deg = b_limbs.shape[0] - 1; ub.nlimbs = b_limbs.shape[1]
-    p = Plan()
-    ctx.check(lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)), "gcd plan")
+    ua, a_limbs = _limbs_upoly(a_limbs)
+    ub, b_limbs = _limbs_upoly(b_limbs)
+    sh = ctx.stream_handle(stream)
+    return _run_gcd(ctx,
+                    lambda ws, u: lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
+                                                  C.c_size_t(ws.numel()), sh, C.byref(u)),
+                    lambda p: lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)))
+
+
+def gcd_z(a, b, ctx: Context | None = None, stream=None) -> list:
+    """gcd(a, b) in Z[x] (content kept, positive leading coefficient)."""
+    ctx = ctx or default_context()
     keep = []
-    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
-    ws = ctx.workspace(p.workspace_bytes)
-    st = lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
-                         C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
-    ctx.check(st, "snc_gcd_z")
-    return buf[: u.deg + 1]
+    ua, ub = _as_upoly(a, keep), _as_upoly(b, keep)
+    sh = ctx.stream_handle(stream)
+    rows = _run_gcd(ctx,
+                    lambda ws, u: lib().snc_gcd_z(ctx.h, C.byref(ua), C.byref(ub), C.c_void_p(ws.data_ptr()),
+                                                  C.c_size_t(ws.numel()), sh, C.byref(u)),
+                    lambda p: lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)))
+    return limbs_to_ints(rows) if len(rows) else []
 
 
-def derivative_limbs(a_limbs: np.ndarray) -> np.ndarray:
-    """Formal derivative of a limb array (two's complement, [deg+1][nl]) as a
-    [deg][nl+1] limb array: marshalling for gcd(R, R') without Python ints."""
-    a = np.ascontiguousarray(a_limbs, dtype=np.uint32)
-    n, nl = a.shape
-    if n <= 1:
-        return np.zeros((0, nl + 1), dtype=np.uint32)
-    ext = np.where(a[1:, -1:] >> 31, np.uint32(0xFFFFFFFF), np.uint32(0))
-    src = np.concatenate([a[1:], ext], axis=1).astype(np.uint64)
-    k = np.arange(1, n, dtype=np.uint64)
-    out = np.empty((n - 1, nl + 1), dtype=np.uint32)
-    carry = np.zeros(n - 1, dtype=np.uint64)
-    for l in range(nl + 1):
-        v = src[:, l] * k + carry
-        out[:, l] = (v & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-        carry = v >> np.uint64(32)
-    return out
+def gcd_z_deriv_limbs(a_limbs: np.ndarray, ctx: Context | None = None, stream=None):
+    """gcd(a, a') on a limb array (the derivative is formed in the library)."""
+    ctx = ctx or default_context()
+    ua, a_limbs = _limbs_upoly(a_limbs)
+    sh = ctx.stream_handle(stream)
+    return _run_gcd(ctx,
+                    lambda ws, u: lib().snc_gcd_z_deriv(ctx.h, C.byref(ua), C.c_void_p(ws.data_ptr()),
+                                                        C.c_size_t(ws.numel()), sh, C.byref(u)),
+                    lambda p: lib().snc_gcd_z_deriv_plan(C.byref(ua), C.byref(p)))
+
+
+def gcd_z_deriv(a, ctx: Context | None = None, stream=None) -> list:
+    """gcd(a, a') in Z[x] for a list of Python ints (ascending)."""
+    ctx = ctx or default_context()
+    keep = []
+    ua = _as_upoly(a, keep)
+    sh = ctx.stream_handle(stream)
+    rows = _run_gcd(ctx,
+                    lambda ws, u: lib().snc_gcd_z_deriv(ctx.h, C.byref(ua), C.c_void_p(ws.data_ptr()),
+                                                        C.c_size_t(ws.numel()), sh, C.byref(u)),
+                    lambda p: lib().snc_gcd_z_deriv_plan(C.byref(ua), C.byref(p)))
+    return limbs_to_ints(rows) if len(rows) else []
 
 
 class Server:

@@ -298,6 +298,21 @@ int write_upoly(const UPoly& G, snc_upoly* out, std::string& err) {
     }                                                                          \
   } while (0)
 
+// b = a' (formal derivative), with the limb count its coefficients need
+void derivative(const UPoly& A, UPoly& B, int& nlb) {
+  B.c.clear();
+  nlb = 1;
+  if (A.c.size() <= 1) return;
+  B.c.resize(A.c.size() - 1);
+  for (size_t i = 0; i + 1 < A.c.size(); ++i) {
+    B.c[i] = A.c[i + 1].mul_small((uint32_t)(i + 1));
+    nlb = std::max(nlb, B.c[i].twos_limbs());
+  }
+}
+
+static int gcd_core(snc_ctx* ctx, GcdTimer& tm, const UPoly& A, const UPoly& B, int nla, int nlb, void* d_ws,
+                    size_t ws_bytes, hipStream_t stream, snc_upoly* out);
+
 static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
                     hipStream_t stream, snc_upoly* out) {
   HIPCHK(hipSetDevice(ctx->device));
@@ -308,8 +323,26 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
   if (!st) st = parse_upoly(b, B, nlb, ctx->err);
   if (st) return st;
   tm.host("gcd_parse");
+  return gcd_core(ctx, tm, A, B, nla, nlb, d_ws, ws_bytes, stream, out);
+}
+
+static int gcd_deriv_impl(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                          snc_upoly* out) {
+  HIPCHK(hipSetDevice(ctx->device));
+  GcdTimer tm(ctx, stream);
+  UPoly A, B;
+  int nla = 1, nlb = 1;
+  int st = parse_upoly(a, A, nla, ctx->err);
+  if (st) return st;
+  derivative(A, B, nlb);
+  tm.host("gcd_parse");
+  return gcd_core(ctx, tm, A, B, nla, nlb, d_ws, ws_bytes, stream, out);
+}
+
+static int gcd_core(snc_ctx* ctx, GcdTimer& tm, const UPoly& A, const UPoly& B, int nla, int nlb, void* d_ws,
+                    size_t ws_bytes, hipStream_t stream, snc_upoly* out) {
   GcdInfo I;
-  st = analyse(A, B, nla, nlb, I);
+  int st = analyse(A, B, nla, nlb, I);
   if (st) return st;
   tm.host("gcd_contents");
   if (I.trivial) return write_upoly(I.triv, out, ctx->err);
@@ -360,8 +393,8 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
       const bool lc_ok = I.lca_bar.mod_small(p) != 0 || I.lcb_bar.mod_small(p) != 0;  // p does not divide beta
       if (cam && cbm && lc_ok) {
         slot_prime[ns] = next_prime;
-        slot_scale[3 * ns + 0] = powmod32(cam, p - 2, p);
-        slot_scale[3 * ns + 1] = powmod32(cbm, p - 2, p);
+        slot_scale[3 * ns + 0] = cam == 1 ? 1u : powmod32(cam, p - 2, p);
+        slot_scale[3 * ns + 1] = cbm == 1 ? 1u : powmod32(cbm, p - 2, p);
         slot_scale[3 * ns + 2] = 0;
         ++ns;
       }
@@ -505,18 +538,9 @@ static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* 
 
 using namespace snc;
 
-extern "C" {
-
-int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out) {
-  if (!out) return SNC_EINVAL;
-  std::string err;
-  UPoly A, B;
-  int nla = 1, nlb = 1;
-  int st = parse_upoly(a, A, nla, err);
-  if (!st) st = parse_upoly(b, B, nlb, err);
-  if (st) return st;
+static int gcd_plan(const UPoly& A, const UPoly& B, int nla, int nlb, snc_plan* out) {
   GcdInfo I;
-  st = analyse(A, B, nla, nlb, I);
+  const int st = analyse(A, B, nla, nlb, I);
   if (st) return st;
   out->deg_bound = I.deg_bound;
   out->out_nlimbs = I.out_nlimbs;
@@ -530,6 +554,35 @@ int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out) {
     out->workspace_bytes = L.total_words * 4;
   }
   return SNC_OK;
+}
+
+extern "C" {
+
+int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out) {
+  if (!out) return SNC_EINVAL;
+  std::string err;
+  UPoly A, B;
+  int nla = 1, nlb = 1;
+  int st = parse_upoly(a, A, nla, err);
+  if (!st) st = parse_upoly(b, B, nlb, err);
+  if (st) return st;
+  return gcd_plan(A, B, nla, nlb, out);
+}
+
+int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
+  if (!out) return SNC_EINVAL;
+  std::string err;
+  UPoly A, B;
+  int nla = 1, nlb = 1;
+  int st = parse_upoly(a, A, nla, err);
+  if (st) return st;
+  derivative(A, B, nlb);
+  return gcd_plan(A, B, nla, nlb, out);
+}
+
+int snc_gcd_z_deriv(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {
+  if (!ctx || !out) return SNC_EINVAL;
+  return gcd_deriv_impl(ctx, a, d_ws, ws_bytes, (hipStream_t)stream, out);
 }
 
 int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,

@@ -105,3 +105,41 @@ def test_serving_shape_certified(snc, target, dh):
     got = snc.gcd_z(a, b)
     assert zx.deg(got) >= dh
     assert G.certify_gcd(a, b, got)
+
+
+def test_gcd_with_derivative_against_oracle(snc):
+    """gcd(a, a') with a' formed in the library: polynomials with repeated
+    factors (a = h^2 u, a = h^3), square-free ones, contents, negative leading
+    coefficients; equal to the oracle and to gcd(a, a') through snc_gcd_z."""
+    rng = random.Random(31)
+    cases = []
+    for _ in range(6):
+        h = rpoly(rng, rng.randint(1, 6), 8)
+        u = rpoly(rng, rng.randint(0, 30), 12)
+        cases.append(zx.mul(zx.mul(h, h), u))
+        cases.append(zx.mul(zx.mul(h, h), h))
+        cases.append([c * 6 for c in rpoly(rng, rng.randint(1, 40), 20)])
+        cases.append([-c for c in rpoly(rng, rng.randint(1, 25), 70)])
+    for a in cases:
+        ref = G.gcd_zx(a, zx.deriv(a))
+        assert snc.gcd_z_deriv(a) == ref
+        assert snc.gcd_z(a, zx.deriv(a)) == ref
+
+
+def test_gcd_with_derivative_edge_cases(snc):
+    assert snc.gcd_z_deriv([]) == []
+    assert snc.gcd_z_deriv([-7]) == [7]          # gcd(-7, 0)
+    assert snc.gcd_z_deriv([4, 6]) == [2]        # gcd(6x + 4, 6)
+    assert snc.gcd_z_deriv([1, 2, 1]) == [1, 1]  # (x + 1)^2
+    assert snc.gcd_z_deriv([0, 0, 0, 5]) == [0, 0, 5]  # gcd(5x^3, 15x^2) = 5x^2
+
+
+def test_gcd_with_derivative_of_curve_resultant(snc):
+    """The projection step: gcd(R, R') of R = res_y(f, f_y) on the curve-analysis
+    workload, from limbs, against the stored oracle value."""
+    ref = json.load(open(os.path.join(GOLDEN, "config1.json")))
+    f, g = synth.config1()
+    r = snc.resultant_y(f, g)
+    limbs = snc.ints_to_limbs(r, max(1, max(c.bit_length() for c in r) // 32 + 2))
+    got = snc.limbs_to_ints(snc.gcd_z_deriv_limbs(limbs))
+    assert got == [int(c) for c in ref["gcd_r_rprime"]]
