@@ -101,8 +101,11 @@ int snc_destroy(snc_ctx* ctx);
 const char* snc_last_error(const snc_ctx* ctx);
 
 /* Per-stage timing of the last compute call on this context, measured with
- * HIP events on the call's stream when enabled (off by default).  names and
- * ms receive up to `cap` entries; returns the number of stages recorded. */
+ * HIP events on the call's stream (device stages) or the host clock (host
+ * stages) when enabled (off by default).  names, ms and launches receive up
+ * to `cap` entries; returns the number of stages recorded.  launches is the
+ * number of kernel launches of a device stage (0 for a host stage); for the
+ * gcd stages it is the number of primes the stage processed. */
 int snc_set_timing(snc_ctx* ctx, int enable);
 int snc_get_timing(const snc_ctx* ctx, const char** names, float* ms, int32_t* launches, int cap);
 

@@ -403,11 +403,14 @@ static int gcd_core(snc_ctx* ctx, GcdTimer& tm, const UPoly& A, const UPoly& B, 
     if (ns == first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
     tm.host("gcd_select_primes");
     HIPCHK(hipMemcpyAsync(ws, h, L.header_words * 4, hipMemcpyHostToDevice, stream));
-    tm.dev_begin();
     G.slot0 = first;
-    launch_gcd_round(G, ns - first, ws, stream);
+    tm.dev_begin();
+    launch_gcd_reduce(G, ns - first, ws, stream);
+    tm.dev_end("gcd_reduce", ns - first);
+    tm.dev_begin();
+    launch_gcd_euclid(G, ns - first, ws, stream);
     HIPCHK(hipGetLastError());
-    tm.dev_end("gcd_modp_round", 2);
+    tm.dev_end("gcd_euclid", ns - first);
     HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.e, (size_t)ns * 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     tm.host("gcd_d2h_sync");

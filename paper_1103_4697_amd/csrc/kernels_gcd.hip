@@ -229,9 +229,11 @@ __device__ __forceinline__ void step2_coefs(uint32_t p0, uint32_t p1, uint32_t q
 // divisor) with fixed register roles: X <- prem(X, Y), then Y <- prem(Y, X).
 // The divisor's top pair is carried over from the step that produced it, so
 // a step reads only the two top coefficients of its new remainder.  Returns
-// at the first step that is not normal (the general loop takes over).
+// at the first step that is not normal (the general loop takes over), or
+// once both degrees are below dstop.
 template <int E>
-__device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (&Y)[E], int& dY, const PrimeC& c) {
+__device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (&Y)[E], int& dY, int dstop,
+                                           const PrimeC& c) {
   if (dX != dY + 1 || dY < 1) return;
   uint32_t x0 = canon(X[0], c.p), x1 = canon(X[1], c.p);
   uint32_t y0 = canon(Y[0], c.p), y1 = canon(Y[1], c.p);
@@ -242,15 +244,67 @@ __device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (
     dX -= 2;
     x0 = canon(X[0], c.p);
     if (uni(x0) == 0) { dX = reg_trim<E>(X, dX, c); return; }
-    if (dX < 1) return;
+    if (dX < 1 || dY < dstop) return;
     x1 = canon(X[1], c.p);
     step2_coefs(y0, y1, x0, x1, a, b, cc, c);
     reg_step2<E>(Y, X, a, b, cc, c);
     dY -= 2;
     y0 = canon(Y[0], c.p);
     if (uni(y0) == 0) { dY = reg_trim<E>(Y, dY, c); return; }
-    if (dY < 1) return;
+    if (dY < 1 || dX < dstop) return;
     y1 = canon(Y[1], c.p);
+  }
+}
+
+// Slots per lane of the register arrays, largest first.  The Euclid loop
+// moves to the next smaller count once both remainders fit, so the work of a
+// step follows the current degree instead of the input degree.
+__host__ __device__ constexpr int next_slots(int E) {
+  return E == 32 ? 24 : E == 24 ? 16 : E == 16 ? 12 : E == 12 ? 9 : E == 9 ? 6 : E == 6 ? 4 : E == 4 ? 2 : 0;
+}
+
+template <int E>
+__device__ __forceinline__ void reg_store(const uint32_t (&X)[E], uint32_t* sm, int lane) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) sm[lane * E + s] = X[s];
+}
+
+// elements 0..d from sm (element order), zeros above
+template <int E>
+__device__ __forceinline__ void reg_fetch(uint32_t (&X)[E], const uint32_t* sm, int d, int lane) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int i = lane * E + s;
+    X[s] = i <= d ? sm[i] : 0u;
+  }
+}
+
+// Euclid's remainder sequence from (X, Y); the last non-zero remainder
+// (lazy, top-aligned) is left in sm[0..e] and e is returned.  sm holds
+// 2 * 64 * E words.
+template <int E>
+__device__ __forceinline__ int euclid_levels(uint32_t (&X)[E], int dX, uint32_t (&Y)[E], int dY, uint32_t* sm, int lane,
+                             const PrimeC& c) {
+  constexpr int EN = next_slots(E);
+  constexpr int dstop = 64 * EN;
+  while (true) {
+    normal_run<E>(X, dX, Y, dY, dstop, c);
+    if (dY < 0) { reg_store<E>(X, sm, lane); return dX; }
+    if (dX >= dY) dX = reg_reduce<E>(X, dX, Y, dY, c);
+    if (dX < 0) { reg_store<E>(Y, sm, lane); return dY; }
+    dY = reg_reduce<E>(Y, dY, X, dX, c);
+    if constexpr (EN > 0) {
+      if (dX < dstop && dY < dstop) {
+        reg_store<E>(X, sm, lane);
+        reg_store<E>(Y, sm + 64 * E, lane);
+        __syncthreads();
+        uint32_t XN[EN], YN[EN];
+        reg_fetch<EN>(XN, sm, dX, lane);
+        reg_fetch<EN>(YN, sm + 64 * E, dY, lane);
+        __syncthreads();
+        return euclid_levels<EN>(XN, dX, YN, dY, sm, lane, c);
+      }
+    }
   }
 }
 
@@ -289,29 +343,15 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(GcdDesc G, const PrimeC* pr
   const int T = G.da + G.db + 2;
   const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
   const uint32_t* rb = ra + G.da + 1;
+  extern __shared__ uint32_t sm[];  // 2 * 64 * E words
   uint32_t X[E], Y[E], Gm[E];
   reg_load<E>(X, ra, G.da, ia, lane, c);
   reg_load<E>(Y, rb, G.db, ib, lane, c);
-  int dX = reg_trim<E>(X, G.da, c);
-  int dY = reg_trim<E>(Y, G.db, c);
-  int e;
-  while (true) {
-    normal_run<E>(X, dX, Y, dY, c);
-    if (dY < 0) {
-      e = dX;
-#pragma unroll
-      for (int s = 0; s < E; ++s) Gm[s] = X[s];
-      break;
-    }
-    if (dX >= dY) dX = reg_reduce<E>(X, dX, Y, dY, c);
-    if (dX < 0) {
-      e = dY;
-#pragma unroll
-      for (int s = 0; s < E; ++s) Gm[s] = Y[s];
-      break;
-    }
-    dY = reg_reduce<E>(Y, dY, X, dX, c);
-  }
+  const int dX = reg_trim<E>(X, G.da, c);
+  const int dY = reg_trim<E>(Y, G.db, c);
+  const int e = euclid_levels<E>(X, dX, Y, dY, sm, lane, c);
+  __syncthreads();
+  reg_fetch<E>(Gm, sm, e, lane);
   const uint32_t inv = minv(lead(Gm[0], c.p), c);
 #pragma unroll
   for (int s = 0; s < E; ++s) Gm[s] = mmulc(Gm[s], inv, c.p, c.pinv);
@@ -353,24 +393,28 @@ __global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* beta
   (void)ks;
 }
 
-void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s) {
+void launch_gcd_reduce(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s) {
   if (nslots <= 0) return;
   const int T = G.da + G.db + 2;
+  hipLaunchKernelGGL(k_gcd_reduce, dim3((T + 255) / 256, nslots), dim3(256), 0, s, G, global_crt_tables().primes, ws);
+}
+
+void launch_gcd_euclid(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s) {
+  if (nslots <= 0) return;
   const PrimeC* primes = global_crt_tables().primes;
-  hipLaunchKernelGGL(k_gcd_reduce, dim3((T + 255) / 256, nslots), dim3(256), 0, s, G, primes, ws);
   const int maxd = G.da > G.db ? G.da : G.db;
   int E = 0;
   for (int e : kGcdE)
     if (64 * e >= maxd + 1) { E = e; break; }
   switch (E) {
-    case 2: hipLaunchKernelGGL(k_gcd_modp_reg<2>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 4: hipLaunchKernelGGL(k_gcd_modp_reg<4>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 6: hipLaunchKernelGGL(k_gcd_modp_reg<6>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 9: hipLaunchKernelGGL(k_gcd_modp_reg<9>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 12: hipLaunchKernelGGL(k_gcd_modp_reg<12>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 16: hipLaunchKernelGGL(k_gcd_modp_reg<16>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 24: hipLaunchKernelGGL(k_gcd_modp_reg<24>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
-    case 32: hipLaunchKernelGGL(k_gcd_modp_reg<32>, dim3(nslots), dim3(64), 0, s, G, primes, ws); return;
+    case 2: hipLaunchKernelGGL(k_gcd_modp_reg<2>, dim3(nslots), dim3(64), 2 * 64 * 2 * 4, s, G, primes, ws); return;
+    case 4: hipLaunchKernelGGL(k_gcd_modp_reg<4>, dim3(nslots), dim3(64), 2 * 64 * 4 * 4, s, G, primes, ws); return;
+    case 6: hipLaunchKernelGGL(k_gcd_modp_reg<6>, dim3(nslots), dim3(64), 2 * 64 * 6 * 4, s, G, primes, ws); return;
+    case 9: hipLaunchKernelGGL(k_gcd_modp_reg<9>, dim3(nslots), dim3(64), 2 * 64 * 9 * 4, s, G, primes, ws); return;
+    case 12: hipLaunchKernelGGL(k_gcd_modp_reg<12>, dim3(nslots), dim3(64), 2 * 64 * 12 * 4, s, G, primes, ws); return;
+    case 16: hipLaunchKernelGGL(k_gcd_modp_reg<16>, dim3(nslots), dim3(64), 2 * 64 * 16 * 4, s, G, primes, ws); return;
+    case 24: hipLaunchKernelGGL(k_gcd_modp_reg<24>, dim3(nslots), dim3(64), 2 * 64 * 24 * 4, s, G, primes, ws); return;
+    case 32: hipLaunchKernelGGL(k_gcd_modp_reg<32>, dim3(nslots), dim3(64), 2 * 64 * 32 * 4, s, G, primes, ws); return;
     default: break;
   }
   const size_t shmem = (size_t)(3 * (maxd + 1)) * sizeof(uint32_t);

@@ -115,7 +115,8 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t
                         int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
 
-void launch_gcd_round(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);
+void launch_gcd_reduce(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);   // residues of a, b per slot
+void launch_gcd_euclid(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);   // monic gcd and cofactors per slot
 void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();
