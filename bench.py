@@ -77,7 +77,8 @@ def profiled_traffic(kernel: str, source: str):
         for line in open(path):
             if ":" in line and line.strip().startswith("- "):
                 key, val = line.strip()[2:].split(":", 1)
-                fields[key.strip()] = val.strip().strip("`")
+                tok = val.split()
+                fields[key.strip()] = tok[0].strip("`") if tok else ""
         if fields.get("kernel_source_sha256") == sha and "traffic_bytes_per_launch" in fields:
             return int(float(fields["traffic_bytes_per_launch"]))
     return None
