@@ -159,6 +159,20 @@ int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out);
 int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
               void* stream, snc_upoly* out);
 
+/* n gcds in one submission.  The problems advance together in rounds: per
+ * round one upload, one reduction launch, one Euclid launch per register
+ * class and one download serve every unfinished problem; those with enough
+ * primes of minimal gcd degree are then lifted and certified, the others
+ * draw more primes.  a, b, out and out_each are arrays of n; out[i] receives
+ * gcd(a[i], b[i]) with the conventions of snc_gcd_z.  On SNC_ERANGE each
+ * entry that is too small holds the sizes it needs and no entry is valid.
+ * out_total->workspace_bytes sizes d_ws for the whole batch (out_each: the
+ * per-problem plans, or NULL).  Any invalid input fails the whole call. */
+int snc_gcd_z_batch_plan(int32_t n, const snc_upoly* a, const snc_upoly* b, snc_plan* out_each,
+                         snc_plan* out_total);
+int snc_gcd_z_batch(snc_ctx* ctx, int32_t n, const snc_upoly* a, const snc_upoly* b, void* d_ws,
+                    size_t ws_bytes, void* stream, snc_upoly* out);
+
 /* gcd(a, a') with a' the formal derivative of a, formed inside the library:
  * the square-free part of the resultant R in the projection phase
  * (Section 2.1) is R / gcd(R, R').  Same conventions as snc_gcd_z. */

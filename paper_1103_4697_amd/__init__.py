@@ -82,6 +82,8 @@ def lib():
                 "snc_gcd_z_plan": (C.c_int, [P(Upoly), P(Upoly), P(Plan)]),
                 "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv_plan": (C.c_int, [P(Upoly), P(Plan)]),
+                "snc_gcd_z_batch_plan": (C.c_int, [I32, P(Upoly), P(Upoly), P(Plan), P(Plan)]),
+                "snc_gcd_z_batch": (C.c_int, [VP, I32, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
             }
             for name, (res, args) in sig.items():
@@ -454,6 +456,35 @@ def gcd_z(a, b, ctx: Context | None = None, stream=None) -> list:
                                                   C.c_size_t(ws.numel()), sh, C.byref(u)),
                     lambda p: lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)))
     return limbs_to_ints(rows) if len(rows) else []
+
+
+def gcd_z_batch(pairs, ctx: Context | None = None, stream=None) -> list:
+    """gcd(a_i, b_i) for a list of (a, b) pairs of ascending Python-int lists,
+    in one batched submission (snc_gcd_z_batch)."""
+    ctx = ctx or default_context()
+    n = len(pairs)
+    if n == 0:
+        return []
+    keep = []
+    A = (Upoly * n)()
+    B = (Upoly * n)()
+    for i, (a, b) in enumerate(pairs):
+        A[i] = _as_upoly(a, keep)
+        B[i] = _as_upoly(b, keep)
+    each = (Plan * n)()
+    total = Plan()
+    ctx.check(lib().snc_gcd_z_batch_plan(n, A, B, each, C.byref(total)), "gcd batch plan")
+    out = (Upoly * n)()
+    bufs = []
+    for i in range(n):
+        u, buf = _out_upoly(each[i].deg_bound, each[i].out_nlimbs, keep)
+        out[i] = u
+        bufs.append(buf)
+    ws = ctx.workspace(total.workspace_bytes)
+    st = lib().snc_gcd_z_batch(ctx.h, n, A, B, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()),
+                               ctx.stream_handle(stream), out)
+    ctx.check(st, "snc_gcd_z_batch")
+    return [_read_upoly(out[i], bufs[i]) for i in range(n)]
 
 
 def gcd_z_deriv_limbs(a_limbs: np.ndarray, ctx: Context | None = None, stream=None):

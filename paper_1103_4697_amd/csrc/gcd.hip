@@ -227,50 +227,6 @@ int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I) {
   return SNC_OK;
 }
 
-struct GcdLayout {
-  size_t coef = 0, slot_prime = 0, slot_scale = 0, res = 0, e = 0, w = 0, u = 0, v = 0;   // words
-  // CRT area (words)
-  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0, betas = 0;
-  size_t wv = 0, uv = 0, vv = 0, dig = 0, out = 0;
-  size_t header_words = 0, crt_header_words = 0, total_words = 0;
-  int lpg = 0, lg = 0;
-};
-
-void layout_gcd(const GcdInfo& I, GcdLayout& L) {
-  const int K = I.kmax, T = I.da + I.db + 2, wl = std::min(I.da, I.db) + 1;
-  size_t w = 0;
-  L.coef = w; w += align_words((size_t)T * I.nl);
-  L.slot_prime = w; w += align_words(K);
-  L.slot_scale = w; w += align_words((size_t)3 * K);
-  L.header_words = w;
-  L.res = w; w += align_words((size_t)K * T);
-  L.e = w; w += align_words(K);
-  L.w = w; w += align_words((size_t)K * wl);
-  L.u = w; w += align_words((size_t)K * (I.da + 1));
-  L.v = w; w += align_words((size_t)K * (I.db + 1));
-  // CRT tables and jobs for up to K selected primes
-  L.lpg = lx_of(K);
-  L.lg = lx_of(K);
-  const size_t crt0 = w;
-  L.primes = w; w += align_words(sizeof(PrimeC) / 4 * K);
-  L.garner = w; w += align_words(K);
-  L.wtab = w; w += align_words((size_t)K * K);
-  L.ptab = w; w += align_words((size_t)(K + 1) * L.lpg);
-  L.jobs = w; w += align_words(3 * sizeof(ResJob) / 4);
-  L.prefd = w; w += align_words(8);
-  L.prefc = w; w += align_words(8);
-  L.sel = w; w += align_words(K);
-  L.betas = w; w += align_words(K);
-  L.crt_header_words = w - crt0;
-  const size_t nmax = (size_t)std::max(I.da, I.db) + 1;
-  L.wv = w; w += align_words((size_t)K * wl);
-  L.uv = w; w += align_words((size_t)K * (I.da + 1));
-  L.vv = w; w += align_words((size_t)K * (I.db + 1));
-  L.dig = w; w += align_words(3 * nmax * K);
-  L.out = w; w += align_words(3 * nmax * L.lg);
-  L.total_words = w;
-}
-
 int write_upoly(const UPoly& G, snc_upoly* out, std::string& err) {
   int need_nl = 1;
   for (const auto& x : G.c) need_nl = std::max(need_nl, x.twos_limbs());
@@ -287,17 +243,6 @@ int write_upoly(const UPoly& G, snc_upoly* out, std::string& err) {
   return SNC_OK;
 }
 
-}  // namespace
-
-#define HIPCHK(x)                                                              \
-  do {                                                                         \
-    hipError_t e_ = (x);                                                       \
-    if (e_ != hipSuccess) {                                                    \
-      ctx->err = std::string(#x) + ": " + hipGetErrorString(e_);               \
-      return SNC_EDEVICE;                                                      \
-    }                                                                          \
-  } while (0)
-
 // b = a' (formal derivative), with the limb count its coefficients need
 void derivative(const UPoly& A, UPoly& B, int& nlb) {
   B.c.clear();
@@ -310,288 +255,487 @@ void derivative(const UPoly& A, UPoly& B, int& nlb) {
   }
 }
 
-static int gcd_core(snc_ctx* ctx, GcdTimer& tm, const UPoly& A, const UPoly& B, int nla, int nlb, void* d_ws,
-                    size_t ws_bytes, hipStream_t stream, snc_upoly* out);
-
-static int gcd_impl(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
-                    hipStream_t stream, snc_upoly* out) {
-  HIPCHK(hipSetDevice(ctx->device));
-  GcdTimer tm(ctx, stream);
+// ---------------------------------------------------------------------------
+// Batched driver.  n problems share one workspace and advance in rounds.  In a
+// round every unfinished problem draws its next primes; one upload, one
+// reduction launch, one Euclid launch per register class and one download
+// serve all of them.  Problems whose minimal-degree primes suffice are then
+// lifted (gather, CRT digits and combination per problem, one upload and one
+// download in all) and certified; the others draw more primes next round.
+// ---------------------------------------------------------------------------
+struct GcdProb {
   UPoly A, B;
   int nla = 1, nlb = 1;
-  int st = parse_upoly(a, A, nla, ctx->err);
-  if (!st) st = parse_upoly(b, B, nlb, ctx->err);
-  if (st) return st;
-  tm.host("gcd_parse");
-  return gcd_core(ctx, tm, A, B, nla, nlb, d_ws, ws_bytes, stream, out);
-}
-
-static int gcd_deriv_impl(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, hipStream_t stream,
-                          snc_upoly* out) {
-  HIPCHK(hipSetDevice(ctx->device));
-  GcdTimer tm(ctx, stream);
-  UPoly A, B;
-  int nla = 1, nlb = 1;
-  int st = parse_upoly(a, A, nla, ctx->err);
-  if (st) return st;
-  derivative(A, B, nlb);
-  tm.host("gcd_parse");
-  return gcd_core(ctx, tm, A, B, nla, nlb, d_ws, ws_bytes, stream, out);
-}
-
-static int gcd_core(snc_ctx* ctx, GcdTimer& tm, const UPoly& A, const UPoly& B, int nla, int nlb, void* d_ws,
-                    size_t ws_bytes, hipStream_t stream, snc_upoly* out) {
   GcdInfo I;
-  int st = analyse(A, B, nla, nlb, I);
-  if (st) return st;
-  tm.host("gcd_contents");
-  if (I.trivial) return write_upoly(I.triv, out, ctx->err);
-  if (out->deg < I.deg_bound || out->nlimbs < I.out_nlimbs || !out->limbs) {
-    out->deg = I.deg_bound;
-    out->nlimbs = I.out_nlimbs;
-    ctx->err = "output buffer too small";
-    return SNC_ERANGE;
+  snc_upoly* out = nullptr;
+  bool done = false;
+  int K = 0, T = 0, wl = 0, lg = 0, cls = 0;
+  size_t nmax = 0;
+  GcdDesc G{};
+  // word offsets into the workspace
+  size_t coef = 0, slot_prime = 0, slot_scale = 0, e = 0;
+  size_t res = 0, w = 0, u = 0, v = 0;
+  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0, betas = 0;
+  size_t wv = 0, uv = 0, vv = 0, dig = 0, outw = 0;
+  // round state
+  int ns = 0, next_prime = 0, target = 0, first = 0;
+  bool full_tried = false;
+};
+
+struct GcdBatchLayout {
+  size_t descs = 0, items = 0, item_cap = 0;
+  size_t hdr_end = 0;                  // [0, hdr_end): descriptors, work items, inputs, slot tables
+  size_t e_begin = 0, e_end = 0;       // gcd degree of every slot
+  size_t crt_begin = 0, crt_end = 0;   // CRT tables and jobs
+  size_t out_begin = 0, out_end = 0;   // lifted w, u, v
+  size_t total = 0;                    // words
+};
+
+// Offsets of every problem (trivial ones take no space); the same function
+// sizes the plan and places the run.
+void layout_batch(std::vector<GcdProb>& P, GcdBatchLayout& L) {
+  size_t w = 0;
+  L.descs = w; w += align_words(sizeof(GcdDesc) / 4 * P.size());
+  L.item_cap = 0;
+  for (const auto& p : P) if (!p.I.trivial) L.item_cap += (size_t)p.I.kmax;
+  L.items = w; w += align_words(2 * L.item_cap);
+  for (auto& p : P) {
+    if (p.I.trivial) continue;
+    p.K = p.I.kmax;
+    p.T = p.I.da + p.I.db + 2;
+    p.wl = std::min(p.I.da, p.I.db) + 1;
+    p.nmax = (size_t)std::max(p.I.da, p.I.db) + 1;
+    p.lg = lx_of(p.K);
+    p.cls = gcd_reg_slots(std::max(p.I.da, p.I.db));
+    p.coef = w; w += align_words((size_t)p.T * p.I.nl);
+    p.slot_prime = w; w += align_words(p.K);
+    p.slot_scale = w; w += align_words((size_t)3 * p.K);
   }
-  GcdLayout L;
-  layout_gcd(I, L);
-  if (!d_ws || ws_bytes < L.total_words * 4) {
-    ctx->err = "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total_words * 4);
+  L.hdr_end = w;
+  L.e_begin = w;
+  for (auto& p : P) if (!p.I.trivial) { p.e = w; w += align_words(p.K); }
+  L.e_end = w;
+  L.crt_begin = w;
+  for (auto& p : P) {
+    if (p.I.trivial) continue;
+    const size_t K = p.K;
+    p.primes = w; w += align_words(sizeof(PrimeC) / 4 * K);
+    p.garner = w; w += align_words(K);
+    p.wtab = w; w += align_words(K * K);
+    p.ptab = w; w += align_words((K + 1) * p.lg);
+    p.jobs = w; w += align_words(3 * sizeof(ResJob) / 4);
+    p.prefd = w; w += align_words(8);
+    p.prefc = w; w += align_words(8);
+    p.sel = w; w += align_words(K);
+    p.betas = w; w += align_words(K);
+  }
+  L.crt_end = w;
+  L.out_begin = w;
+  for (auto& p : P) if (!p.I.trivial) { p.outw = w; w += align_words(3 * p.nmax * p.lg); }
+  L.out_end = w;
+  for (auto& p : P) {
+    if (p.I.trivial) continue;
+    const size_t K = p.K;
+    p.res = w; w += align_words(K * p.T);
+    p.w = w; w += align_words(K * p.wl);
+    p.u = w; w += align_words(K * (p.I.da + 1));
+    p.v = w; w += align_words(K * (p.I.db + 1));
+    p.wv = w; w += align_words(K * p.wl);
+    p.uv = w; w += align_words(K * (p.I.da + 1));
+    p.vv = w; w += align_words(K * (p.I.db + 1));
+    p.dig = w; w += align_words(3 * p.nmax * K);
+  }
+  L.total = w;
+}
+
+int parse_problem(const snc_upoly* a, const snc_upoly* b, bool deriv, GcdProb& p, std::string& err) {
+  int st = parse_upoly(a, p.A, p.nla, err);
+  if (st) return st;
+  if (deriv) derivative(p.A, p.B, p.nlb);
+  else st = parse_upoly(b, p.B, p.nlb, err);
+  return st;
+}
+
+}  // namespace
+
+#define HIPCHK(x)                                                              \
+  do {                                                                         \
+    hipError_t e_ = (x);                                                       \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#x) + ": " + hipGetErrorString(e_);               \
+      return SNC_EDEVICE;                                                      \
+    }                                                                          \
+  } while (0)
+
+// Chinese remaindering tables and jobs of one problem for its selected slots
+// (written into the staging copy of its CRT area); returns M = prod q.
+static BigInt stage_crt(GcdProb& p, const std::vector<int32_t>& sel, int emin, const int32_t* slot_prime,
+                        uint32_t* h) {
+  const Tables& TB = tables();
+  const int ks = (int)sel.size();
+  PrimeC* pc = (PrimeC*)(h + p.primes);
+  std::vector<uint32_t> q(ks);
+  for (int j = 0; j < ks; ++j) { q[j] = TB.p[slot_prime[sel[j]]]; pc[j] = TB.pc[slot_prime[sel[j]]]; }
+  uint32_t* garner = h + p.garner;
+  uint32_t* wtab = h + p.wtab;
+  for (int i = 0; i < ks; ++i) {
+    uint64_t run = 1;
+    for (int j = 0; j < i; ++j) {
+      wtab[(size_t)j * ks + i] = mont32(run, q[i]);
+      run = run * q[j] % q[i];
+    }
+    garner[i] = mont32(powmod32(run, q[i] - 2, q[i]), q[i]);
+  }
+  uint32_t* ptab = h + p.ptab;
+  std::memset(ptab, 0, (size_t)(ks + 1) * p.lg * 4);
+  BigInt Pr = BigInt::from_u64(1);
+  for (int j = 0; j <= ks; ++j) {
+    for (size_t l = 0; l < Pr.mag.size() && (int)l < p.lg; ++l) ptab[(size_t)j * p.lg + l] = Pr.mag[l];
+    if (j < ks) Pr = Pr.mul_small(q[j]);
+  }
+  const int lens[3] = {emin + 1, p.I.da - emin + 1, p.I.db - emin + 1};
+  const size_t vals[3] = {p.wv, p.uv, p.vv};
+  ResJob* jb = (ResJob*)(h + p.jobs);
+  int64_t* pd = (int64_t*)(h + p.prefd);
+  int64_t* pcb = (int64_t*)(h + p.prefc);
+  pd[0] = pcb[0] = 0;
+  for (int t = 0; t < 3; ++t) {
+    std::memset(&jb[t], 0, sizeof(ResJob));
+    jb[t].D = lens[t] - 1;
+    jb[t].k = ks;
+    jb[t].L = p.lg;
+    jb[t].val_off = (int64_t)vals[t];
+    jb[t].dig_off = (int64_t)(p.dig + t * p.nmax * ks);
+    jb[t].acc_off = 0;
+    jb[t].out_off = (int64_t)(p.outw + t * p.nmax * p.lg);
+    pd[t + 1] = pd[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+    pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+  }
+  int32_t* hsel = (int32_t*)(h + p.sel);
+  for (int j = 0; j < ks; ++j) hsel[j] = sel[j];
+  uint32_t* hbeta = h + p.betas;
+  for (int j = 0; j < ks; ++j) hbeta[j] = p.I.beta.mod_small(q[j]);
+  return Pr;
+}
+
+// All problems are parsed; this analyses, checks capacities and runs them.
+static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* d_ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  const int n = (int)P.size();
+  for (auto& p : P) {
+    const int st = analyse(p.A, p.B, p.nla, p.nlb, p.I);
+    if (st) return st;
+  }
+  tm.host("gcd_contents");
+  bool short_out = false;
+  for (auto& p : P) {
+    if (p.I.trivial) {
+      const int st = write_upoly(p.I.triv, p.out, ctx->err);
+      if (st == SNC_ERANGE) { short_out = true; continue; }
+      if (st) return st;
+      p.done = true;
+    } else if (p.out->deg < p.I.deg_bound || p.out->nlimbs < p.I.out_nlimbs || !p.out->limbs) {
+      p.out->deg = p.I.deg_bound;
+      p.out->nlimbs = p.I.out_nlimbs;
+      short_out = true;
+    }
+  }
+  if (short_out) { ctx->err = "output buffer too small"; return SNC_ERANGE; }
+  int active = 0;
+  for (auto& p : P) active += !p.done;
+  if (!active) return SNC_OK;
+
+  GcdBatchLayout L;
+  layout_batch(P, L);
+  if (!d_ws || ws_bytes < L.total * 4) {
+    ctx->err = "workspace of " + std::to_string(ws_bytes) + " bytes, need " + std::to_string(L.total * 4);
     return SNC_ENOMEM;
   }
   uint32_t* ws = (uint32_t*)d_ws;
-  const Tables& TB = tables();
-  const int T = I.da + I.db + 2, wl = std::min(I.da, I.db) + 1;
-  const int K = I.kmax;
-  if (ctx->stage_in((L.header_words + L.crt_header_words) * 4) ||
-      ctx->stage_out((size_t)std::max<size_t>(K, 3 * ((size_t)std::max(I.da, I.db) + 1) * L.lg) * 4)) {
+  if (ctx->stage_in(L.crt_end * 4) || ctx->stage_out((L.out_end - L.e_begin) * 4)) {
     ctx->err = "pinned staging allocation failed";
     return SNC_EDEVICE;
   }
-  // upload block: packed coefficients, then the slot tables (grown per round)
-  uint32_t* h = (uint32_t*)ctx->h_in;
-  for (int i = 0; i < T; ++i) {
-    const BigInt& x = i <= I.da ? A.c[i] : B.c[i - I.da - 1];
-    if (!x.to_twos(h + L.coef + (size_t)i * I.nl, I.nl)) { ctx->err = "input conversion"; return SNC_EINTERNAL; }
-  }
-  int32_t* slot_prime = (int32_t*)(h + L.slot_prime);
-  uint32_t* slot_scale = h + L.slot_scale;
-  GcdDesc G{};
-  G.da = I.da; G.db = I.db; G.nl = I.nl; G.wl = wl;
-  G.coef_off = (int64_t)L.coef; G.slot_prime_off = (int64_t)L.slot_prime; G.slot_scale_off = (int64_t)L.slot_scale;
-  G.res_off = (int64_t)L.res; G.e_off = (int64_t)L.e; G.w_off = (int64_t)L.w; G.u_off = (int64_t)L.u; G.v_off = (int64_t)L.v;
-
-  int next_prime = 0;  // next table index to try
-  int ns = 0;          // slots filled
-  std::vector<int32_t> e_host;
-  int target = std::min(K, std::max(3, primes_for_bits(bits_needed_opt(I)) + 2));
-  bool full_tried = false;
-  for (int round = 0; round < 64; ++round) {
-    const int first = ns;
-    while (ns < target && next_prime < KMAX) {
-      const uint32_t p = TB.p[next_prime];
-      const uint32_t cam = I.ca.mod_small(p), cbm = I.cb.mod_small(p);
-      const bool lc_ok = I.lca_bar.mod_small(p) != 0 || I.lcb_bar.mod_small(p) != 0;  // p does not divide beta
-      if (cam && cbm && lc_ok) {
-        slot_prime[ns] = next_prime;
-        slot_scale[3 * ns + 0] = cam == 1 ? 1u : powmod32(cam, p - 2, p);
-        slot_scale[3 * ns + 1] = cbm == 1 ? 1u : powmod32(cbm, p - 2, p);
-        slot_scale[3 * ns + 2] = 0;
-        ++ns;
-      }
-      ++next_prime;
+  uint32_t* h = (uint32_t*)ctx->h_in;                  // mirrors ws[0, crt_end)
+  const uint32_t* ho = (const uint32_t*)ctx->h_out;    // mirrors ws[e_begin, out_end)
+  GcdDesc* descs = (GcdDesc*)(h + L.descs);
+  for (int i = 0; i < n; ++i) {
+    GcdProb& p = P[i];
+    if (p.done) continue;
+    for (int t = 0; t < p.T; ++t) {
+      const BigInt& x = t <= p.I.da ? p.A.c[t] : p.B.c[t - p.I.da - 1];
+      if (!x.to_twos(h + p.coef + (size_t)t * p.I.nl, p.I.nl)) { ctx->err = "input conversion"; return SNC_EINTERNAL; }
     }
-    if (ns == first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
+    GcdDesc& G = p.G;
+    G.da = p.I.da; G.db = p.I.db; G.nl = p.I.nl; G.wl = p.wl;
+    G.coef_off = (int64_t)p.coef; G.slot_prime_off = (int64_t)p.slot_prime; G.slot_scale_off = (int64_t)p.slot_scale;
+    G.res_off = (int64_t)p.res; G.e_off = (int64_t)p.e; G.w_off = (int64_t)p.w; G.u_off = (int64_t)p.u;
+    G.v_off = (int64_t)p.v;
+    descs[i] = G;
+    p.target = std::min(p.K, std::max(3, primes_for_bits(bits_needed_opt(p.I)) + 2));
+  }
+  const Tables& TB = tables();
+  int32_t* items = (int32_t*)(h + L.items);
+  const GcdDesc* descs_d = (const GcdDesc*)(ws + L.descs);
+  const int32_t* items_d = (const int32_t*)(ws + L.items);
+
+  for (int round = 0; round < 64 && active; ++round) {
+    // 1. next primes of every unfinished problem
+    int maxT = 0;
+    for (auto& p : P) {
+      if (p.done) continue;
+      p.first = p.ns;
+      int32_t* slot_prime = (int32_t*)(h + p.slot_prime);
+      uint32_t* slot_scale = h + p.slot_scale;
+      while (p.ns < p.target && p.next_prime < KMAX) {
+        const uint32_t q = TB.p[p.next_prime];
+        const uint32_t cam = p.I.ca.mod_small(q), cbm = p.I.cb.mod_small(q);
+        const bool lc_ok = p.I.lca_bar.mod_small(q) != 0 || p.I.lcb_bar.mod_small(q) != 0;  // q does not divide beta
+        if (cam && cbm && lc_ok) {
+          slot_prime[p.ns] = p.next_prime;
+          slot_scale[3 * p.ns + 0] = cam == 1 ? 1u : powmod32(cam, q - 2, q);
+          slot_scale[3 * p.ns + 1] = cbm == 1 ? 1u : powmod32(cbm, q - 2, q);
+          slot_scale[3 * p.ns + 2] = 0;
+          ++p.ns;
+        }
+        ++p.next_prime;
+      }
+      if (p.ns == p.first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
+      maxT = std::max(maxT, p.T);
+    }
+    // work items grouped by register class, one launch per class
+    struct Range { int cls, off, cnt, maxd; };
+    std::vector<Range> ranges;
+    int nitems = 0;
+    for (int cls : {2, 4, 6, 9, 12, 16, 24, 32, 0}) {
+      Range r{cls, nitems, 0, 0};
+      for (int i = 0; i < n; ++i) {
+        GcdProb& p = P[i];
+        if (p.done || p.cls != cls) continue;
+        for (int s = p.first; s < p.ns; ++s) { items[2 * nitems] = i; items[2 * nitems + 1] = s; ++nitems; }
+        r.maxd = std::max(r.maxd, std::max(p.I.da, p.I.db));
+      }
+      r.cnt = nitems - r.off;
+      if (r.cnt) ranges.push_back(r);
+    }
     tm.host("gcd_select_primes");
-    HIPCHK(hipMemcpyAsync(ws, h, L.header_words * 4, hipMemcpyHostToDevice, stream));
-    G.slot0 = first;
+    HIPCHK(hipMemcpyAsync(ws, h, L.hdr_end * 4, hipMemcpyHostToDevice, stream));
     tm.dev_begin();
-    launch_gcd_reduce(G, ns - first, ws, stream);
-    tm.dev_end("gcd_reduce", ns - first);
+    launch_gcd_reduce(descs_d, items_d, nitems, maxT, ws, stream);
+    tm.dev_end("gcd_reduce", nitems);
     tm.dev_begin();
-    launch_gcd_euclid(G, ns - first, ws, stream);
+    for (const Range& r : ranges) launch_gcd_euclid(descs_d, items_d + 2 * r.off, r.cnt, r.cls, r.maxd, ws, stream);
     HIPCHK(hipGetLastError());
-    tm.dev_end("gcd_euclid", ns - first);
-    HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.e, (size_t)ns * 4, hipMemcpyDeviceToHost, stream));
+    tm.dev_end("gcd_euclid", nitems);
+    HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.e_begin, (L.e_end - L.e_begin) * 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     tm.host("gcd_d2h_sync");
-    e_host.assign((int32_t*)ctx->h_out, (int32_t*)ctx->h_out + ns);
-    for (int s = 0; s < ns; ++s) {
-      if (e_host[s] < 0 || e_host[s] > std::min(I.da, I.db)) {
-        ctx->err = "gcd: degree " + std::to_string(e_host[s]) + " out of range for prime slot " + std::to_string(s);
-        return SNC_EINTERNAL;
+
+    // 2. decide per problem: constant gcd, more primes, or lift
+    std::vector<int> lift;
+    std::vector<std::vector<int32_t>> sels(n);
+    std::vector<int> emins(n, -1);
+    std::vector<BigInt> Ms(n);
+    for (int i = 0; i < n; ++i) {
+      GcdProb& p = P[i];
+      if (p.done) continue;
+      const int32_t* e_host = (const int32_t*)(ho + (p.e - L.e_begin));
+      for (int s = 0; s < p.ns; ++s) {
+        if (e_host[s] < 0 || e_host[s] > std::min(p.I.da, p.I.db)) {
+          ctx->err = "gcd: degree " + std::to_string(e_host[s]) + " out of range for prime slot " + std::to_string(s);
+          return SNC_EINTERNAL;
+        }
       }
-    }
-    const int emin = *std::min_element(e_host.begin(), e_host.end());
-    if (emin == 0) {
-      UPoly R;
-      R.c = {I.c};
-      return write_upoly(R, out, ctx->err);
-    }
-    if (!I.have_beta) {
-      I.beta = BigInt::gcd(I.lca_bar, I.lcb_bar);
-      I.have_beta = true;
-    }
-    std::vector<int32_t> sel;
-    for (int s = 0; s < ns; ++s) if (e_host[s] == emin) sel.push_back(s);
-    const int ks = (int)sel.size();
-    if (ks < primes_for_bits(bits_needed_opt(I))) {  // too few lucky-looking primes yet
-      target = std::min(K, ns + primes_for_bits(bits_needed_opt(I)) - ks + 2);
-      if (target <= ns) { ctx->err = "gcd: prime budget exhausted"; return SNC_EINTERNAL; }
-      continue;
-    }
-    // CRT tables for the selected primes, staged after the slot tables
-    uint32_t* hc = (uint32_t*)ctx->h_in + L.header_words;
-    const size_t crt0 = L.primes;
-    auto at = [&](size_t word) { return hc + (word - crt0); };
-    PrimeC* pc = (PrimeC*)at(L.primes);
-    std::vector<uint32_t> q(ks);
-    for (int j = 0; j < ks; ++j) { q[j] = TB.p[slot_prime[sel[j]]]; pc[j] = TB.pc[slot_prime[sel[j]]]; }
-    uint32_t* garner = at(L.garner);
-    uint32_t* wtab = at(L.wtab);
-    for (int i = 0; i < ks; ++i) {
-      uint64_t run = 1;
-      for (int j = 0; j < i; ++j) {
-        wtab[(size_t)j * ks + i] = mont32(run, q[i]);
-        run = run * q[j] % q[i];
+      const int emin = *std::min_element(e_host, e_host + p.ns);
+      if (emin == 0) {
+        UPoly R;
+        R.c = {p.I.c};
+        const int st = write_upoly(R, p.out, ctx->err);
+        if (st) return st;
+        p.done = true;
+        --active;
+        continue;
       }
-      garner[i] = mont32(powmod32(run, q[i] - 2, q[i]), q[i]);
+      if (!p.I.have_beta) {
+        p.I.beta = BigInt::gcd(p.I.lca_bar, p.I.lcb_bar);
+        p.I.have_beta = true;
+      }
+      std::vector<int32_t> sel;
+      for (int s = 0; s < p.ns; ++s) if (e_host[s] == emin) sel.push_back(s);
+      const int ks = (int)sel.size();
+      const int need = primes_for_bits(bits_needed_opt(p.I));
+      if (ks < need) {  // too few lucky-looking primes yet
+        p.target = std::min(p.K, p.ns + need - ks + 2);
+        if (p.target <= p.ns) { ctx->err = "gcd: prime budget exhausted"; return SNC_EINTERNAL; }
+        continue;
+      }
+      Ms[i] = stage_crt(p, sel, emin, (const int32_t*)(h + p.slot_prime), h);
+      sels[i] = std::move(sel);
+      emins[i] = emin;
+      lift.push_back(i);
     }
-    uint32_t* ptab = at(L.ptab);
-    std::memset(ptab, 0, (size_t)(ks + 1) * L.lpg * 4);
-    BigInt Pr = BigInt::from_u64(1);
-    for (int j = 0; j <= ks; ++j) {
-      for (size_t l = 0; l < Pr.mag.size() && (int)l < L.lpg; ++l) ptab[(size_t)j * L.lpg + l] = Pr.mag[l];
-      if (j < ks) Pr = Pr.mul_small(q[j]);
+    if (lift.empty()) continue;
+
+    // 3. lift w, u, v of those problems and certify
+    HIPCHK(hipMemcpyAsync(ws + L.crt_begin, h + L.crt_begin, (L.crt_end - L.crt_begin) * 4, hipMemcpyHostToDevice,
+                          stream));
+    for (int i : lift) {
+      GcdProb& p = P[i];
+      const int ks = (int)sels[i].size();
+      launch_gcd_gather(p.G, (const int32_t*)(ws + p.sel), ws + p.betas, (const PrimeC*)(ws + p.primes), ks,
+                        emins[i], ws, (int64_t)p.wv, (int64_t)p.uv, (int64_t)p.vv, stream);
+      CrtTables tb{(const PrimeC*)(ws + p.primes), ws + p.garner, ws + p.wtab, ws + p.ptab, ks, p.lg};
+      const int64_t* pd = (const int64_t*)(h + p.prefd);
+      launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefd), 3, pd[3], ws, stream);
+      launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefc), 3, pd[3], ks, ws, stream);
     }
-    const BigInt M = Pr;
-    const int lens[3] = {emin + 1, I.da - emin + 1, I.db - emin + 1};
-    const size_t vals[3] = {L.wv, L.uv, L.vv};
-    ResJob* jb = (ResJob*)at(L.jobs);
-    int64_t* pd = (int64_t*)at(L.prefd);
-    int64_t* pcb = (int64_t*)at(L.prefc);
-    pd[0] = pcb[0] = 0;
-    const size_t nmax = (size_t)std::max(I.da, I.db) + 1;
-    for (int t = 0; t < 3; ++t) {
-      std::memset(&jb[t], 0, sizeof(ResJob));
-      jb[t].D = lens[t] - 1;
-      jb[t].k = ks;
-      jb[t].L = L.lg;
-      jb[t].val_off = (int64_t)vals[t];
-      jb[t].dig_off = (int64_t)(L.dig + t * nmax * ks);
-      jb[t].acc_off = 0;
-      jb[t].out_off = (int64_t)(L.out + t * nmax * L.lg);
-      pd[t + 1] = pd[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-      pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-    }
-    int32_t* hsel = (int32_t*)at(L.sel);
-    for (int j = 0; j < ks; ++j) hsel[j] = sel[j];
-    uint32_t* hbeta = at(L.betas);
-    for (int j = 0; j < ks; ++j) hbeta[j] = I.beta.mod_small(q[j]);
-    HIPCHK(hipMemcpyAsync(ws + crt0, hc, L.crt_header_words * 4, hipMemcpyHostToDevice, stream));
-    launch_gcd_gather(G, (const int32_t*)(ws + L.sel), ws + L.betas, (const PrimeC*)(ws + L.primes), ks, emin, ws,
-                      (int64_t)L.wv, (int64_t)L.uv, (int64_t)L.vv, stream);
-    CrtTables tb{(const PrimeC*)(ws + L.primes), ws + L.garner, ws + L.wtab, ws + L.ptab, ks, L.lpg};
-    launch_crt_digits(tb, (const ResJob*)(ws + L.jobs), (const int64_t*)(ws + L.prefd), 3, pd[3], ws, stream);
-    launch_crt_combine(tb, (const ResJob*)(ws + L.jobs), (const int64_t*)(ws + L.prefc), 3, pcb[3], ks, ws, stream);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.out, 3 * nmax * L.lg * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync((uint8_t*)ctx->h_out + (L.out_begin - L.e_begin) * 4, ws + L.out_begin,
+                          (L.out_end - L.out_begin) * 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    const uint32_t* ho = (const uint32_t*)ctx->h_out;
-    UPoly W, U, V;
-    UPoly* polys[3] = {&W, &U, &V};
-    BigInt n1[3];
-    for (int t = 0; t < 3; ++t) {
-      polys[t]->c.resize(lens[t]);
-      for (int i = 0; i < lens[t]; ++i) {
-        polys[t]->c[i] = BigInt::from_twos(ho + t * nmax * L.lg + (size_t)i * L.lg, L.lg);
-        n1[t] = n1[t] + abs_big(polys[t]->c[i]);
+    tm.host("gcd_lift");
+    for (int i : lift) {
+      GcdProb& p = P[i];
+      const int emin = emins[i];
+      const int ks = (int)sels[i].size();
+      const int lens[3] = {emin + 1, p.I.da - emin + 1, p.I.db - emin + 1};
+      const uint32_t* hq = ho + (p.outw - L.e_begin);
+      UPoly W, U, V;
+      UPoly* polys[3] = {&W, &U, &V};
+      BigInt n1[3];
+      for (int t = 0; t < 3; ++t) {
+        polys[t]->c.resize(lens[t]);
+        for (int j = 0; j < lens[t]; ++j) {
+          polys[t]->c[j] = BigInt::from_twos(hq + t * p.nmax * p.lg + (size_t)j * p.lg, p.lg);
+          n1[t] = n1[t] + abs_big(polys[t]->c[j]);
+        }
       }
-    }
-    const BigInt two = BigInt::from_u64(2);
-    const bool ok = BigInt::cmp_mag((two * n1[0] * n1[1]).mag, M.mag) < 0 &&
-                    BigInt::cmp_mag((two * n1[0] * n1[2]).mag, M.mag) < 0 &&
-                    !W.c.back().is_zero() && !W.c.back().neg;
-    if (ok) {
-      // result: c * pp(w)
-      BigInt cw = content(W);
-      UPoly R;
-      R.c.resize(W.c.size());
-      for (size_t i = 0; i < W.c.size(); ++i) {
-        BigInt qq, rr;
-        BigInt::divmod(W.c[i], cw, qq, rr);
-        R.c[i] = I.c * qq;
+      const BigInt two = BigInt::from_u64(2);
+      const BigInt& M = Ms[i];
+      const bool ok = BigInt::cmp_mag((two * n1[0] * n1[1]).mag, M.mag) < 0 &&
+                      BigInt::cmp_mag((two * n1[0] * n1[2]).mag, M.mag) < 0 &&
+                      !W.c.back().is_zero() && !W.c.back().neg;
+      if (ok) {  // result: c * pp(w)
+        const BigInt cw = content(W);
+        UPoly R;
+        R.c.resize(W.c.size());
+        for (size_t j = 0; j < W.c.size(); ++j) {
+          BigInt qq, rr;
+          BigInt::divmod(W.c[j], cw, qq, rr);
+          R.c[j] = p.I.c * qq;
+        }
+        const int st = write_upoly(normalise_sign(R), p.out, ctx->err);
+        if (st) return st;
+        p.done = true;
+        --active;
+        continue;
       }
-      return write_upoly(normalise_sign(R), out, ctx->err);
+      // not certified: too few primes for the true sizes, or all unlucky
+      const int want = primes_for_bits(bits_needed_full(p.I, emin));
+      if (!p.full_tried && want > ks) {
+        p.target = std::min(p.K, p.ns + (want - ks) + 2);
+        p.full_tried = true;
+      } else {
+        p.target = std::min(p.K, p.ns + std::max(4, ks / 2));
+      }
+      if (p.target <= p.ns) { ctx->err = "gcd: prime budget exhausted before the result certified"; return SNC_EINTERNAL; }
     }
-    // not certified: either too few primes for the true sizes, or all unlucky
-    int want = primes_for_bits(bits_needed_full(I, emin));
-    if (!full_tried && want > ks) {
-      target = std::min(K, ns + (want - ks) + 2);
-      full_tried = true;
-    } else {
-      target = std::min(K, ns + std::max(4, ks / 2));
-    }
-    if (target <= ns) { ctx->err = "gcd: prime budget exhausted before the result certified"; return SNC_EINTERNAL; }
+    tm.host("gcd_certify");
   }
-  ctx->err = "gcd: too many rounds";
-  return SNC_EINTERNAL;
+  if (active) { ctx->err = "gcd: too many rounds"; return SNC_EINTERNAL; }
+  return SNC_OK;
+}
+
+static int gcd_run(snc_ctx* ctx, int n, const snc_upoly* a, const snc_upoly* b, bool deriv, void* d_ws,
+                   size_t ws_bytes, hipStream_t stream, snc_upoly* out) {
+  HIPCHK(hipSetDevice(ctx->device));
+  GcdTimer tm(ctx, stream);
+  std::vector<GcdProb> P(n);
+  for (int i = 0; i < n; ++i) {
+    const int st = parse_problem(&a[i], deriv ? nullptr : &b[i], deriv, P[i], ctx->err);
+    if (st) return st;
+    P[i].out = &out[i];
+  }
+  tm.host("gcd_parse");
+  return gcd_batch(ctx, tm, P, d_ws, ws_bytes, stream);
+}
+
+static int gcd_plan(int n, const snc_upoly* a, const snc_upoly* b, bool deriv, snc_plan* each, snc_plan* total) {
+  std::string err;
+  std::vector<GcdProb> P(n);
+  for (int i = 0; i < n; ++i) {
+    int st = parse_problem(&a[i], deriv ? nullptr : &b[i], deriv, P[i], err);
+    if (!st) st = analyse(P[i].A, P[i].B, P[i].nla, P[i].nlb, P[i].I);
+    if (st) return st;
+  }
+  GcdBatchLayout L;
+  layout_batch(P, L);
+  int needs_device = 0;
+  if (total) *total = snc_plan{};
+  for (int i = 0; i < n; ++i) {
+    const GcdInfo& I = P[i].I;
+    snc_plan pl{};
+    pl.deg_bound = I.deg_bound;
+    pl.out_nlimbs = I.out_nlimbs;
+    pl.nprimes = I.trivial ? 0 : I.kmax;
+    pl.workspace_bytes = 0;
+    if (!I.trivial) {
+      std::vector<GcdProb> one(1);
+      one[0].I = I;
+      GcdBatchLayout L1;
+      layout_batch(one, L1);
+      pl.workspace_bytes = L1.total * 4;
+      needs_device = 1;
+    }
+    if (each) each[i] = pl;
+    if (total) {
+      total->deg_bound = std::max(total->deg_bound, pl.deg_bound);
+      total->out_nlimbs = std::max(total->out_nlimbs, pl.out_nlimbs);
+      total->nprimes += pl.nprimes;
+    }
+  }
+  if (total) total->workspace_bytes = needs_device ? L.total * 4 : 0;
+  return SNC_OK;
 }
 
 }  // namespace snc
 
 using namespace snc;
 
-static int gcd_plan(const UPoly& A, const UPoly& B, int nla, int nlb, snc_plan* out) {
-  GcdInfo I;
-  const int st = analyse(A, B, nla, nlb, I);
-  if (st) return st;
-  out->deg_bound = I.deg_bound;
-  out->out_nlimbs = I.out_nlimbs;
-  out->nprimes = I.trivial ? 0 : I.kmax;
-  out->reserved = 0;
-  if (I.trivial) {
-    out->workspace_bytes = 0;
-  } else {
-    GcdLayout L;
-    layout_gcd(I, L);
-    out->workspace_bytes = L.total_words * 4;
-  }
-  return SNC_OK;
-}
-
 extern "C" {
 
 int snc_gcd_z_plan(const snc_upoly* a, const snc_upoly* b, snc_plan* out) {
-  if (!out) return SNC_EINVAL;
-  std::string err;
-  UPoly A, B;
-  int nla = 1, nlb = 1;
-  int st = parse_upoly(a, A, nla, err);
-  if (!st) st = parse_upoly(b, B, nlb, err);
-  if (st) return st;
-  return gcd_plan(A, B, nla, nlb, out);
-}
-
-int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
-  if (!out) return SNC_EINVAL;
-  std::string err;
-  UPoly A, B;
-  int nla = 1, nlb = 1;
-  int st = parse_upoly(a, A, nla, err);
-  if (st) return st;
-  derivative(A, B, nlb);
-  return gcd_plan(A, B, nla, nlb, out);
-}
-
-int snc_gcd_z_deriv(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {
-  if (!ctx || !out) return SNC_EINVAL;
-  return gcd_deriv_impl(ctx, a, d_ws, ws_bytes, (hipStream_t)stream, out);
+  if (!out || !a || !b) return SNC_EINVAL;
+  return gcd_plan(1, a, b, false, nullptr, out);
 }
 
 int snc_gcd_z(snc_ctx* ctx, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
               void* stream, snc_upoly* out) {
-  if (!ctx || !out) return SNC_EINVAL;
-  return gcd_impl(ctx, a, b, d_ws, ws_bytes, (hipStream_t)stream, out);
+  if (!ctx || !out || !a || !b) return SNC_EINVAL;
+  return gcd_run(ctx, 1, a, b, false, d_ws, ws_bytes, (hipStream_t)stream, out);
+}
+
+int snc_gcd_z_batch_plan(int32_t n, const snc_upoly* a, const snc_upoly* b, snc_plan* out_each,
+                         snc_plan* out_total) {
+  if (n < 0 || (n > 0 && (!a || !b)) || !out_total) return SNC_EINVAL;
+  return gcd_plan(n, a, b, false, out_each, out_total);
+}
+
+int snc_gcd_z_batch(snc_ctx* ctx, int32_t n, const snc_upoly* a, const snc_upoly* b, void* d_ws, size_t ws_bytes,
+                    void* stream, snc_upoly* out) {
+  if (!ctx || n < 0 || (n > 0 && (!a || !b || !out))) return SNC_EINVAL;
+  if (n == 0) return SNC_OK;
+  return gcd_run(ctx, n, a, b, false, d_ws, ws_bytes, (hipStream_t)stream, out);
+}
+
+int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
+  if (!out || !a) return SNC_EINVAL;
+  return gcd_plan(1, a, nullptr, true, nullptr, out);
+}
+
+int snc_gcd_z_deriv(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {
+  if (!ctx || !out || !a) return SNC_EINVAL;
+  return gcd_run(ctx, 1, a, nullptr, true, d_ws, ws_bytes, (hipStream_t)stream, out);
 }
 
 }  // extern "C"

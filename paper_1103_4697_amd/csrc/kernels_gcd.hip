@@ -27,20 +27,26 @@ __device__ __forceinline__ uint32_t reduce_coef(const uint32_t* limbs, int nl, c
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_gcd_reduce(GcdDesc G, const PrimeC* primes, uint32_t* ws) {
+// Work items are (problem, slot) pairs: items[2w] indexes descs, items[2w+1]
+// is the slot (prime) of that problem.
+__global__ __launch_bounds__(256) void k_gcd_reduce(const GcdDesc* descs, const int32_t* items,
+                                                    const PrimeC* primes, uint32_t* ws) {
+  const GcdDesc G = descs[items[2 * blockIdx.y]];
+  const int slot = items[2 * blockIdx.y + 1];
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int T = G.da + G.db + 2;
   if (t >= T) return;
-  const int slot = G.slot0 + blockIdx.y;
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   ws[G.res_off + (int64_t)slot * T + t] = reduce_coef(ws + G.coef_off + (int64_t)t * G.nl, G.nl, c);
 }
 
-__global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(GcdDesc G, const PrimeC* primes, uint32_t* ws) {
+__global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, const int32_t* items,
+                                                           const PrimeC* primes, uint32_t* ws) {
   extern __shared__ uint32_t sm[];
   const int tid = threadIdx.x;
-  const int slot = G.slot0 + blockIdx.x;
+  const GcdDesc G = descs[items[2 * blockIdx.x]];
+  const int slot = items[2 * blockIdx.x + 1];
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
@@ -333,9 +339,11 @@ __device__ __forceinline__ void reg_cofactor(uint32_t (&R)[E], const uint32_t (&
 }
 
 template <int E>
-__global__ __launch_bounds__(64) void k_gcd_modp_reg(GcdDesc G, const PrimeC* primes, uint32_t* ws) {
+__global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const int32_t* items,
+                                                      const PrimeC* primes, uint32_t* ws) {
   const int lane = threadIdx.x;
-  const int slot = G.slot0 + blockIdx.x;
+  const GcdDesc G = descs[items[2 * blockIdx.x]];
+  const int slot = items[2 * blockIdx.x + 1];
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
@@ -393,32 +401,34 @@ __global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* beta
   (void)ks;
 }
 
-void launch_gcd_reduce(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s) {
-  if (nslots <= 0) return;
-  const int T = G.da + G.db + 2;
-  hipLaunchKernelGGL(k_gcd_reduce, dim3((T + 255) / 256, nslots), dim3(256), 0, s, G, global_crt_tables().primes, ws);
+void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int maxT, uint32_t* ws,
+                       hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_gcd_reduce, dim3((maxT + 255) / 256, nitems), dim3(256), 0, s, descs, items,
+                     global_crt_tables().primes, ws);
 }
 
-void launch_gcd_euclid(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s) {
-  if (nslots <= 0) return;
-  const PrimeC* primes = global_crt_tables().primes;
-  const int maxd = G.da > G.db ? G.da : G.db;
-  int E = 0;
+int gcd_reg_slots(int maxd) {
   for (int e : kGcdE)
-    if (64 * e >= maxd + 1) { E = e; break; }
-  switch (E) {
-    case 2: hipLaunchKernelGGL(k_gcd_modp_reg<2>, dim3(nslots), dim3(64), 2 * 64 * 2 * 4, s, G, primes, ws); return;
-    case 4: hipLaunchKernelGGL(k_gcd_modp_reg<4>, dim3(nslots), dim3(64), 2 * 64 * 4 * 4, s, G, primes, ws); return;
-    case 6: hipLaunchKernelGGL(k_gcd_modp_reg<6>, dim3(nslots), dim3(64), 2 * 64 * 6 * 4, s, G, primes, ws); return;
-    case 9: hipLaunchKernelGGL(k_gcd_modp_reg<9>, dim3(nslots), dim3(64), 2 * 64 * 9 * 4, s, G, primes, ws); return;
-    case 12: hipLaunchKernelGGL(k_gcd_modp_reg<12>, dim3(nslots), dim3(64), 2 * 64 * 12 * 4, s, G, primes, ws); return;
-    case 16: hipLaunchKernelGGL(k_gcd_modp_reg<16>, dim3(nslots), dim3(64), 2 * 64 * 16 * 4, s, G, primes, ws); return;
-    case 24: hipLaunchKernelGGL(k_gcd_modp_reg<24>, dim3(nslots), dim3(64), 2 * 64 * 24 * 4, s, G, primes, ws); return;
-    case 32: hipLaunchKernelGGL(k_gcd_modp_reg<32>, dim3(nslots), dim3(64), 2 * 64 * 32 * 4, s, G, primes, ws); return;
+    if (64 * e >= maxd + 1) return e;
+  return 0;
+}
+
+void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, int slots, int maxd, uint32_t* ws,
+                       hipStream_t s) {
+  if (nitems <= 0) return;
+  const PrimeC* primes = global_crt_tables().primes;
+  const dim3 grid(nitems), blk(64);
+  switch (slots) {
+#define SNC_GCD_REG(E) \
+    case E: hipLaunchKernelGGL(k_gcd_modp_reg<E>, grid, blk, 2 * 64 * E * 4, s, descs, items, primes, ws); return;
+    SNC_GCD_REG(2) SNC_GCD_REG(4) SNC_GCD_REG(6) SNC_GCD_REG(9)
+    SNC_GCD_REG(12) SNC_GCD_REG(16) SNC_GCD_REG(24) SNC_GCD_REG(32)
+#undef SNC_GCD_REG
     default: break;
   }
   const size_t shmem = (size_t)(3 * (maxd + 1)) * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_gcd_modp, dim3(nslots), dim3(GCD_THREADS), shmem, s, G, primes, ws);
+  hipLaunchKernelGGL(k_gcd_modp, grid, dim3(GCD_THREADS), shmem, s, descs, items, primes, ws);
 }
 
 void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,

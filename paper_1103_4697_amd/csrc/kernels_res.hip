@@ -202,7 +202,7 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
                                                         const RowDesc* rows, uint32_t* ws,
                                                         uint32_t* abn_count, AbnEntry* abn_list,
                                                         uint32_t abn_cap) {
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const int jid = job_list[jj];
   const ResJob J = jobs[jid];
@@ -570,7 +570,7 @@ constexpr int CRT_SLOTS = KMAX / 64;
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTables tb, const ResJob* jobs,
                                                                         const int64_t* prefix,
                                                                         int njobs, uint32_t* ws) {
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

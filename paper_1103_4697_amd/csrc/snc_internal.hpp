@@ -47,6 +47,16 @@ struct RowDesc {
   int32_t off;  // first residue of the group within a prime's block of T
   int32_t len;  // coefficients per row of the group (0 for an all-zero group)
 };
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// block index.  Renumbering so that XCD x runs a contiguous range of logical
+// blocks keeps neighbouring work, which reads the same data (the residues of
+// one prime, adjacent coefficients), in one L2.  A bijection on [0, nb).
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / NXCD, r = nb % NXCD, x = b % NXCD;
+  return x * q + (x < r ? x : r) + b / NXCD;
+}
+
 constexpr int ROWGRP = 4;
 constexpr int HCHUNK = 4;   // Horner steps per 64-byte scalar load; group lengths are padded to a multiple
 __host__ __device__ inline int padded_group_len(int ml) { return (ml + HCHUNK - 1) / HCHUNK * HCHUNK; }
@@ -68,9 +78,7 @@ struct CrtTables {
 struct GcdDesc {
   int32_t da, db;          // degrees of a and b
   int32_t nl;              // limbs per input coefficient
-  int32_t slot0;           // first slot of this round
   int32_t wl;              // row length of w: min(da, db) + 1
-  int32_t pad;
   int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl] (uint32 index)
   int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
   int64_t slot_scale_off;  // 3 uint32 per slot: cont(a)^-1, cont(b)^-1 mod p (plain), unused
@@ -115,8 +123,12 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t
                         int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
 
-void launch_gcd_reduce(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);   // residues of a, b per slot
-void launch_gcd_euclid(const GcdDesc& G, int nslots, uint32_t* ws, hipStream_t s);   // monic gcd and cofactors per slot
+// gcd work items are (problem, slot) pairs indexing a device array of GcdDesc
+void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int maxT, uint32_t* ws,
+                       hipStream_t s);   // residues of a, b per item
+int gcd_reg_slots(int maxd);             // register class of a degree (slots per lane), 0: LDS kernel
+void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, int slots, int maxd, uint32_t* ws,
+                       hipStream_t s);   // monic gcd and cofactors per item; one register class per launch
 void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();

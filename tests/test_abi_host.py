@@ -173,3 +173,33 @@ def test_gcd_plan(snc):
     p = plan(a, b)
     norm = min(sum(c * c for c in a), sum(c * c for c in b)) ** 0.5
     assert 32 * p.out_nlimbs - 1 >= 24 + np.log2(norm)
+
+
+def test_gcd_batch_plan(snc):
+    """The batch plan covers every problem: per-problem plans equal the single
+    plans, and the total workspace holds all of them (trivial ones need none)."""
+    import ctypes as C
+    keep = []
+    rng = np.random.default_rng(3)
+    pairs = [([1, 2, 3, 4], [5, 6, 7]), ([], [3]), ([0, 0, 5], [0, 2]),
+             ([int(v) for v in rng.integers(-99, 99, 300)] + [1], [int(v) for v in rng.integers(-99, 99, 40)] + [7])]
+    n = len(pairs)
+    A = (snc.Upoly * n)()
+    B = (snc.Upoly * n)()
+    for i, (a, b) in enumerate(pairs):
+        A[i] = snc._as_upoly(a, keep)
+        B[i] = snc._as_upoly(b, keep)
+    each = (snc.Plan * n)()
+    total = snc.Plan()
+    assert snc.lib().snc_gcd_z_batch_plan(n, A, B, each, C.byref(total)) == 0
+    ws_sum = 0
+    for i in range(n):
+        one = snc.Plan()
+        assert snc.lib().snc_gcd_z_plan(C.byref(A[i]), C.byref(B[i]), C.byref(one)) == 0
+        assert (each[i].deg_bound, each[i].out_nlimbs, each[i].nprimes) == (one.deg_bound, one.out_nlimbs, one.nprimes)
+        ws_sum += one.workspace_bytes
+    assert each[1].workspace_bytes == 0
+    assert max(e.workspace_bytes for e in each) <= total.workspace_bytes <= ws_sum
+    assert snc.lib().snc_gcd_z_batch_plan(0, None, None, None, C.byref(total)) == 0
+    assert total.workspace_bytes == 0
+    assert snc.lib().snc_gcd_z_batch_plan(-1, None, None, None, C.byref(total)) == snc.SNC_EINVAL

@@ -143,3 +143,59 @@ def test_gcd_with_derivative_of_curve_resultant(snc):
     limbs = snc.ints_to_limbs(r, max(1, max(c.bit_length() for c in r) // 32 + 2))
     got = snc.limbs_to_ints(snc.gcd_z_deriv_limbs(limbs))
     assert got == [int(c) for c in ref["gcd_r_rprime"]]
+
+
+def test_batch_equals_single_and_oracle(snc):
+    """snc_gcd_z_batch on a mix: shared factors of several degrees (register
+    classes 2..9 and degrees above 64 E), square-free pairs, contents,
+    derivative pairs, trivial entries and a repeated problem; every result
+    equals the single call and the oracle (Euclid over Q where fast, else
+    the divisibility certificate)."""
+    rng = random.Random(77)
+    pairs = []
+    for deg_h, deg_u in ((3, 20), (12, 60), (30, 200), (8, 500), (2, 2), (40, 40)):
+        h = rpoly(rng, deg_h, 10)
+        pairs.append((zx.mul(h, rpoly(rng, deg_u, 12)), zx.mul(h, rpoly(rng, deg_u + 3, 12))))
+    pairs.append(([c * 4 for c in rpoly(rng, 30, 20)], [c * 6 for c in rpoly(rng, 25, 20)]))
+    a = zx.mul(zx.mul([1, 1], [1, 1]), rpoly(rng, 15, 8))
+    pairs.append((a, zx.deriv(a)))
+    pairs += [([], []), ([5], []), ([0, 3], [6]), pairs[0]]
+    got = snc.gcd_z_batch(pairs)
+    assert len(got) == len(pairs)
+    for (a, b), g in zip(pairs, got):
+        assert g == snc.gcd_z(a, b)
+        if max(len(a), len(b)) <= 80:
+            assert g == G.gcd_zx(a, b)
+        elif g:
+            assert zx.divides(g, a) and zx.divides(g, b)
+    assert got[-1] == got[0]
+    assert snc.gcd_z_batch([]) == []
+
+
+def test_batch_output_too_small(snc):
+    """SNC_ERANGE: the entries that are too small receive the sizes they need."""
+    import ctypes as C
+    keep = []
+    pairs = [([1, 2, 1], [1, 1]), ([3, 0, 0, 1], [2, 5])]
+    n = len(pairs)
+    A = (snc.Upoly * n)()
+    B = (snc.Upoly * n)()
+    for i, (a, b) in enumerate(pairs):
+        A[i] = snc._as_upoly(a, keep)
+        B[i] = snc._as_upoly(b, keep)
+    each = (snc.Plan * n)()
+    total = snc.Plan()
+    assert snc.lib().snc_gcd_z_batch_plan(n, A, B, each, C.byref(total)) == 0
+    out = (snc.Upoly * n)()
+    bufs = []
+    for i in range(n):
+        u, buf = snc._out_upoly(each[i].deg_bound, each[i].out_nlimbs, keep)
+        out[i] = u
+        bufs.append(buf)
+    out[0].deg = -1  # too small on purpose (host-side check, no device work started)
+    ctx = snc.default_context()
+    ws = ctx.workspace(total.workspace_bytes)
+    st = snc.lib().snc_gcd_z_batch(ctx.h, n, A, B, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()),
+                                   ctx.stream_handle(), out)
+    assert st == snc.SNC_ERANGE
+    assert out[0].deg == each[0].deg_bound and out[0].nlimbs >= 1
