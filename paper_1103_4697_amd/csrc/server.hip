@@ -4,9 +4,10 @@
 // The caller hands the server one device pool.  Requests are copied at
 // submission and planned on the host (their device footprint is the plan's
 // workspace size).  Worker threads, each with its own context and HIP stream,
-// take work from the queue: a free worker collects the waiting resultant
-// requests that fit into the free pool bytes and slots and runs them as one
-// batch (every stage launched once over all of them), or runs one gcd.  A
+// take work from the queue: a free worker collects the waiting requests of
+// the kind at the head of the queue that fit into the free pool bytes and
+// slots and runs them as one batch (resultants: every stage launched once
+// over all of them; gcds: one batched gcd submission).  A
 // request that arrives while others are on the GPU is admitted as soon as
 // pool bytes and a slot free up, and its work overlaps with the in-flight
 // work on the other streams.  Results are kept until the caller polls them.
@@ -110,25 +111,17 @@ struct snc_server {
 namespace snc {
 namespace {
 
-// Take work for one worker: a batch of admitted resultant requests, or one gcd.
+// Take work for one worker: a batch of admitted requests of one kind.
 // Called with the lock held; returns false if nothing could be admitted.
 bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t& bytes) {
   batch.clear();
   if (s->queue.empty() || s->slots_used >= s->max_slots) return false;
-  Request* first = s->reqs[s->queue.front()];
-  if (first->kind == 1) {
-    if (!s->alloc.alloc(std::max<size_t>(first->footprint, 256), off)) return false;
-    bytes = std::max<size_t>(first->footprint, 256);
-    s->queue.pop_front();
-    batch.push_back(first);
-    s->slots_used++;
-    return true;
-  }
-  // resultants: grow the batch while the summed footprint and the slots allow
+  const int kind = s->reqs[s->queue.front()]->kind;
+  // grow a batch of the first request's kind while the summed footprint and the slots allow
   size_t total = 0;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
     Request* r = s->reqs[*it];
-    if (r->kind != 0) { ++it; continue; }
+    if (r->kind != kind) { ++it; continue; }
     if (s->slots_used + (int)batch.size() >= s->max_slots) break;
     size_t probe = 0;
     const size_t want = total + r->footprint + 65536;  // headroom for the batch header
@@ -140,17 +133,25 @@ bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t&
   }
   if (batch.empty()) return false;
   // the batch's real workspace is computed from its joint layout
-  std::vector<ResPlan> plans(batch.size());
-  std::string err;
-  for (size_t i = 0; i < batch.size(); ++i) {
-    Operand F, G;
-    parse_bipoly(&batch[i]->f, F, err);
-    parse_bipoly(&batch[i]->g, G, err);
-    plan_resultant(F, G, plans[i], err);
+  if (kind == 1) {
+    std::vector<snc_upoly> as(batch.size()), bs(batch.size());
+    for (size_t i = 0; i < batch.size(); ++i) { as[i] = batch[i]->a; bs[i] = batch[i]->b; }
+    snc_plan tot{};
+    if (snc_gcd_z_batch_plan((int32_t)batch.size(), as.data(), bs.data(), nullptr, &tot) != SNC_OK) tot.workspace_bytes = total;
+    bytes = std::max<size_t>(tot.workspace_bytes, 256);
+  } else {
+    std::vector<ResPlan> plans(batch.size());
+    std::string err;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      Operand F, G;
+      parse_bipoly(&batch[i]->f, F, err);
+      parse_bipoly(&batch[i]->g, G, err);
+      plan_resultant(F, G, plans[i], err);
+    }
+    BatchLayout lay;
+    layout_batch(plans, lay);
+    bytes = std::max<size_t>(lay.total_bytes, 256);
   }
-  BatchLayout lay;
-  layout_batch(plans, lay);
-  bytes = std::max<size_t>(lay.total_bytes, 256);
   if (!s->alloc.alloc(bytes, off)) {
     for (auto it = batch.rbegin(); it != batch.rend(); ++it) s->queue.push_front((*it)->ticket);
     batch.clear();
@@ -180,13 +181,31 @@ void worker_main(snc_server* s) {
     // results are written before the status is published under the lock
     std::vector<int> status(batch.size(), SNC_EINTERNAL);
     if (batch[0]->kind == 1) {
-      Request* r = batch[0];
-      std::vector<uint32_t> buf((size_t)(r->out_deg + 1) * r->out_nl);
-      snc_upoly o{buf.data(), r->out_deg, r->out_nl};
-      const int stt = snc_gcd_z(c, &r->a, &r->b, ws, bytes, st, &o);
-      status[0] = stt;
-      if (stt == SNC_OK) { r->res.swap(buf); r->res_deg = o.deg; r->res_nl = o.nlimbs; }
-      else r->err = snc_last_error(c);
+      const int n = (int)batch.size();
+      std::vector<snc_upoly> as(n), bs(n), os(n);
+      std::vector<std::vector<uint32_t>> bufs(n);
+      for (int i = 0; i < n; ++i) {
+        as[i] = batch[i]->a; bs[i] = batch[i]->b;
+        bufs[i].assign((size_t)(batch[i]->out_deg + 1) * batch[i]->out_nl, 0u);
+        os[i] = snc_upoly{bufs[i].data(), batch[i]->out_deg, batch[i]->out_nl};
+      }
+      int stt = snc_gcd_z_batch(c, n, as.data(), bs.data(), ws, bytes, st, os.data());
+      if (stt == SNC_OK) {
+        for (int i = 0; i < n; ++i) status[i] = SNC_OK;
+      } else {
+        // isolate the failing request: each alone in the same workspace
+        for (int i = 0; i < n; ++i) {
+          os[i] = snc_upoly{bufs[i].data(), batch[i]->out_deg, batch[i]->out_nl};
+          status[i] = snc_gcd_z(c, &as[i], &bs[i], ws, bytes, st, &os[i]);
+          if (status[i] != SNC_OK) batch[i]->err = snc_last_error(c);
+        }
+      }
+      for (int i = 0; i < n; ++i)
+        if (status[i] == SNC_OK) {
+          batch[i]->res.swap(bufs[i]);
+          batch[i]->res_deg = os[i].deg;
+          batch[i]->res_nl = os[i].nlimbs;
+        }
     } else {
       const int n = (int)batch.size();
       fs.resize(n); gs.resize(n); outs.resize(n);
