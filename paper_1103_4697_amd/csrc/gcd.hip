@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -489,12 +490,13 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       uint32_t* slot_scale = h + p.slot_scale;
       while (p.ns < p.target && p.next_prime < KMAX) {
         const uint32_t q = TB.p[p.next_prime];
+        // q must not divide a content; a q dividing both leading coefficients (hence beta)
+        // is detected by the Euclid kernel, which marks the slot unusable
         const uint32_t cam = p.I.ca.mod_small(q), cbm = p.I.cb.mod_small(q);
-        const bool lc_ok = p.I.lca_bar.mod_small(q) != 0 || p.I.lcb_bar.mod_small(q) != 0;  // q does not divide beta
-        if (cam && cbm && lc_ok) {
+        if (cam && cbm) {
           slot_prime[p.ns] = p.next_prime;
-          slot_scale[3 * p.ns + 0] = cam == 1 ? 1u : powmod32(cam, q - 2, q);
-          slot_scale[3 * p.ns + 1] = cbm == 1 ? 1u : powmod32(cbm, q - 2, q);
+          slot_scale[3 * p.ns + 0] = cam;
+          slot_scale[3 * p.ns + 1] = cbm;
           slot_scale[3 * p.ns + 2] = 0;
           ++p.ns;
         }
@@ -540,13 +542,20 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       GcdProb& p = P[i];
       if (p.done) continue;
       const int32_t* e_host = (const int32_t*)(ho + (p.e - L.e_begin));
+      int emin = INT32_MAX;
       for (int s = 0; s < p.ns; ++s) {
+        if (e_host[s] == GCD_SLOT_UNUSABLE) continue;
         if (e_host[s] < 0 || e_host[s] > std::min(p.I.da, p.I.db)) {
           ctx->err = "gcd: degree " + std::to_string(e_host[s]) + " out of range for prime slot " + std::to_string(s);
           return SNC_EINTERNAL;
         }
+        emin = std::min(emin, (int)e_host[s]);
       }
-      const int emin = *std::min_element(e_host, e_host + p.ns);
+      if (emin == INT32_MAX) {  // every prime so far divides both leading coefficients
+        p.target = std::min(p.K, p.ns + 4);
+        if (p.target <= p.ns) { ctx->err = "gcd: prime budget exhausted"; return SNC_EINTERNAL; }
+        continue;
+      }
       if (emin == 0) {
         UPoly R;
         R.c = {p.I.c};

@@ -41,6 +41,11 @@ __global__ __launch_bounds__(256) void k_gcd_reduce(const GcdDesc* descs, const 
   ws[G.res_off + (int64_t)slot * T + t] = reduce_coef(ws + G.coef_off + (int64_t)t * G.nl, G.nl, c);
 }
 
+// Montgomery form of 1 / (cont mod p); cont mod p is given plain and non-zero
+__device__ __forceinline__ uint32_t content_inverse(uint32_t r, const PrimeC& c) {
+  return r == 1u ? c.r1 : minv(to_mont(r, c), c);
+}
+
 __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, const int32_t* items,
                                                            const PrimeC* primes, uint32_t* ws) {
   extern __shared__ uint32_t sm[];
@@ -50,7 +55,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
-  const uint32_t ia = to_mont(sc[0], c), ib = to_mont(sc[1], c);
+  const uint32_t ia = content_inverse(sc[0], c), ib = content_inverse(sc[1], c);
   const int maxd = G.da > G.db ? G.da : G.db;
   uint32_t* P0 = sm;
   uint32_t* P1 = sm + (maxd + 1);
@@ -69,6 +74,10 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   while (dA >= 0 && A[dA] == 0) --dA;
   int dB = G.db;
   while (dB >= 0 && B[dB] == 0) --dB;
+  if (dA < G.da && dB < G.db) {
+    if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = GCD_SLOT_UNUSABLE;
+    return;
+  }
   // Euclid, division-free: A <- lc(B) A - lc(A) x^(dA-dB) B cancels the top term
   while (true) {
     if (dA < dB) {
@@ -347,7 +356,7 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
   const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
-  const uint32_t ia = to_mont(sc[0], c), ib = to_mont(sc[1], c);
+  const uint32_t ia = content_inverse(sc[0], c), ib = content_inverse(sc[1], c);
   const int T = G.da + G.db + 2;
   const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
   const uint32_t* rb = ra + G.da + 1;
@@ -357,6 +366,10 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   reg_load<E>(Y, rb, G.db, ib, lane, c);
   const int dX = reg_trim<E>(X, G.da, c);
   const int dY = reg_trim<E>(Y, G.db, c);
+  if (dX < G.da && dY < G.db) {
+    if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = GCD_SLOT_UNUSABLE;
+    return;
+  }
   const int e = euclid_levels<E>(X, dX, Y, dY, sm, lane, c);
   __syncthreads();
   reg_fetch<E>(Gm, sm, e, lane);

@@ -471,6 +471,8 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
   uint32_t* P1 = Fb + Dp;        // [IPAD + Dp]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+  // w_j = (-1)^j / j! behind IPAD zeros; u_i = v_i / i! staged in P1 (free until the expansion)
+  uint32_t* U = P1;
   for (int t = tid; t < IPAD + Dp; t += INTERP_THREADS) {
     const int j = t - IPAD;
     uint32_t w = 0;
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
       w = (j & 1) ? mneg(f, c.p) : f;
     }
     Wp[t] = w;
-    P1[t] = 0;
+    if (t < Dp) U[t] = t < n1 ? mmulc(canon(V[t], c.p), IF[t], c.p, c.pinv) : 0u;
   }
   __syncthreads();
 
@@ -488,11 +490,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
     // a_k for k = b0 + lane
     const uint32_t* wk = Wp + IPAD + b0 + lane;
     uint32_t a = 0;
-    for (int ib = 0; ib <= ob; ++ib) {
-      const int i = ib * IB + lane;
-      const uint32_t u = i < n1 ? mmulc(canon(V[i], c.p), IF[i], c.p, c.pinv) : 0u;
-      a = toeplitz64(a, u, wk - ib * IB, c);
-    }
+    for (int ib = 0; ib <= ob; ++ib) a = toeplitz64(a, U[ib * IB + lane], wk - ib * IB, c);
     // Q_ob and F_ob, coefficient of x^lane in lane
     const int len = min(IB, n1 - b0);
     const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
@@ -522,6 +520,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
   for (int t = tid; t < IPAD + Dp; t += INTERP_THREADS) {
     const int x = t - IPAD;
     Pa[t] = (x >= 0 && x < lastlen) ? Qb[lastb + x] : 0u;
+    Pb[t] = 0u;
   }
   __syncthreads();
   int dP = lastlen - 1;

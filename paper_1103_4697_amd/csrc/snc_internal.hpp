@@ -81,13 +81,16 @@ struct GcdDesc {
   int32_t wl;              // row length of w: min(da, db) + 1
   int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl] (uint32 index)
   int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
-  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a)^-1, cont(b)^-1 mod p (plain), unused
+  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a) mod p, cont(b) mod p (plain, non-zero), unused
   int64_t res_off;         // residues [slot][da+db+2] (Montgomery)
-  int64_t e_off;           // int32 per slot: degree of the gcd mod p
+  int64_t e_off;           // int32 per slot: degree of the gcd mod p, -2 if p divides both leading coefficients
   int64_t w_off;           // [slot][wl]   monic gcd mod p (plain)
   int64_t u_off;           // [slot][da+1] cofactor of a mod p (plain)
   int64_t v_off;           // [slot][db+1] cofactor of b mod p (plain)
 };
+
+// gcd degree written for a prime dividing both leading coefficients (the prime is not used)
+constexpr int32_t GCD_SLOT_UNUSABLE = -2;
 
 // abnormal (prime, point) instance queued for the general elimination
 struct AbnEntry {
