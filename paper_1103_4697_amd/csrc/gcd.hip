@@ -181,7 +181,10 @@ double bits_needed_opt(const GcdInfo& I) {
 
 int primes_for_bits(double bits) { return (int)std::ceil(bits / 29.99) + 1; }
 
-int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I) {
+// raw2, raw1: log2 of the 2- and 1-norms of a and b when already known from
+// their limbs (NULL: computed here)
+int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I, const double* raw2 = nullptr,
+            const double* raw1 = nullptr) {
   I = GcdInfo();
   I.nl = std::max(nla, nlb);
   if (A.c.empty() && B.c.empty()) { I.trivial = 1; I.deg_bound = 0; I.out_nlimbs = 1; return SNC_OK; }
@@ -213,8 +216,13 @@ int analyse(const UPoly& A, const UPoly& B, int nla, int nlb, GcdInfo& I) {
   I.lcb_bar = abs_big(q);
   // beta divides both leading coefficients: bound its size by the smaller
   I.lbeta = std::min(I.lca_bar.log2_abs(), I.lcb_bar.log2_abs());
-  log2_norms(A, I.l2a, I.l1a);
-  log2_norms(B, I.l2b, I.l1b);
+  if (raw2 && raw1) {
+    I.l2a = raw2[0]; I.l1a = raw1[0];
+    I.l2b = raw2[1]; I.l1b = raw1[1];
+  } else {
+    log2_norms(A, I.l2a, I.l1a);
+    log2_norms(B, I.l2b, I.l1b);
+  }
   const double lca = I.ca.log2_abs(), lcb = I.cb.log2_abs();
   I.l2a -= lca; I.l1a -= lca;
   I.l2b -= lcb; I.l1b -= lcb;
@@ -244,39 +252,152 @@ int write_upoly(const UPoly& G, snc_upoly* out, std::string& err) {
   return SNC_OK;
 }
 
-// b = a' (formal derivative), with the limb count its coefficients need
-void derivative(const UPoly& A, UPoly& B, int& nlb) {
+// b = a' (formal derivative)
+void derivative(const UPoly& A, UPoly& B) {
   B.c.clear();
-  nlb = 1;
   if (A.c.size() <= 1) return;
   B.c.resize(A.c.size() - 1);
-  for (size_t i = 0; i + 1 < A.c.size(); ++i) {
-    B.c[i] = A.c[i + 1].mul_small((uint32_t)(i + 1));
-    nlb = std::max(nlb, B.c[i].twos_limbs());
+  for (size_t i = 0; i + 1 < A.c.size(); ++i) B.c[i] = A.c[i + 1].mul_small((uint32_t)(i + 1));
+}
+
+// ---------------------------------------------------------------------------
+// Sizes read from the limbs alone, without big-integer arithmetic: trimmed
+// degrees and log2 of the norms and leading coefficients, each coefficient
+// taken from its top three magnitude limbs.  They are the sizes of a and b
+// themselves, not of their primitive parts, so every bound derived from them
+// is at least the one the contents would give.  The plan and the run both
+// size the work from these, and the first round of primes is launched on
+// them before the host has parsed the inputs or computed any content.
+// ---------------------------------------------------------------------------
+struct Quick {
+  int da = -1, db = -1, nla = 1, nlb = 1, nl = 1;
+  bool deriv = false, trivial = false;
+  double l2[2] = {0, 0}, l1[2] = {0, 0}, llc[2] = {0, 0};
+  int deg_bound = 0, out_nlimbs = 1, kmax = 0, target0 = 0;
+};
+
+// |x| ~ m 2^ex for a two's-complement coefficient (m from the top three limbs of |x|); m = 0 for x = 0
+void coef_size(const uint32_t* c, int nl, double& m, int& ex) {
+  const bool neg = c[nl - 1] >> 31;
+  int z = 0;  // lowest non-zero limb: |x| = ~x + 1 carries up to it
+  if (neg) while (z < nl && c[z] == 0) ++z;
+  auto mag = [&](int i) -> uint32_t { return !neg ? c[i] : i < z ? 0u : i == z ? 0u - c[i] : ~c[i]; };
+  int t = nl - 1;
+  while (t >= 0 && mag(t) == 0) --t;
+  if (t < 0) { m = 0.0; ex = 0; return; }
+  double v = (double)mag(t);
+  int used = 1;
+  for (int k = 1; k <= 2 && t - k >= 0; ++k, ++used) v = v * 4294967296.0 + (double)mag(t - k);
+  m = v;
+  ex = 32 * (t + 1 - used);
+}
+
+bool zero_coef(const uint32_t* c, int nl) {
+  for (int l = 0; l < nl; ++l) if (c[l]) return false;
+  return true;
+}
+
+int trimmed_degree(const snc_upoly* a) {
+  int d = a->deg;
+  while (d >= 0 && zero_coef(a->limbs + (size_t)d * a->nlimbs, a->nlimbs)) --d;
+  return d;
+}
+
+// log2 of the 2-norm, 1-norm and leading coefficient of the first deg+1
+// coefficients (times j+1 for coefficient j when mult: the derivative's)
+void limb_norms(const uint32_t* limbs, int nl, int deg, bool mult, double& l2, double& l1, double& llc) {
+  std::vector<double> m(deg + 1);
+  std::vector<int> ex(deg + 1);
+  int emax = INT_MIN;
+  for (int j = 0; j <= deg; ++j) {
+    coef_size(limbs + (size_t)(mult ? j + 1 : j) * nl, nl, m[j], ex[j]);
+    if (mult) m[j] *= (double)(j + 1);
+    if (m[j] > 0.0) emax = std::max(emax, ex[j]);
   }
+  const int E = emax + 128;  // m < 2^111, so every scaled term is below 1
+  double s2 = 0.0, s1 = 0.0;
+  for (int j = 0; j <= deg; ++j) {
+    if (m[j] == 0.0) continue;
+    const double r = std::ldexp(m[j], ex[j] - E);
+    s2 += r * r;
+    s1 += r;
+  }
+  l2 = E + 0.5 * std::log2(s2);
+  l1 = E + std::log2(s1);
+  llc = std::log2(m[deg]) + ex[deg];
+}
+
+int check_upoly(const snc_upoly* a, std::string& err) {
+  if (!a) { err = "null polynomial"; return SNC_EINVAL; }
+  if (a->deg >= 0 && (a->nlimbs < 1 || !a->limbs)) {
+    err = "invalid univariate polynomial (nlimbs < 1 or NULL limbs)";
+    return SNC_EINVAL;
+  }
+  return SNC_OK;
+}
+
+int quick_scan(const snc_upoly* a, const snc_upoly* b, bool deriv, Quick& Q, std::string& err) {
+  Q = Quick();
+  Q.deriv = deriv;
+  int st = check_upoly(a, err);
+  if (!st && !deriv) st = check_upoly(b, err);
+  if (st) return st;
+  Q.nla = a->deg >= 0 ? a->nlimbs : 1;
+  Q.da = trimmed_degree(a);
+  if (deriv) {
+    Q.nlb = Q.nla;
+    Q.db = Q.da >= 1 ? Q.da - 1 : -1;
+  } else {
+    Q.nlb = b->deg >= 0 ? b->nlimbs : 1;
+    Q.db = trimmed_degree(b);
+  }
+  Q.nl = deriv ? Q.nla : std::max(Q.nla, Q.nlb);
+  Q.trivial = Q.da <= 0 || Q.db <= 0;
+  if (Q.trivial) return SNC_OK;
+  limb_norms(a->limbs, a->nlimbs, Q.da, false, Q.l2[0], Q.l1[0], Q.llc[0]);
+  if (deriv) limb_norms(a->limbs, a->nlimbs, Q.db, true, Q.l2[1], Q.l1[1], Q.llc[1]);
+  else limb_norms(b->limbs, b->nlimbs, Q.db, false, Q.l2[1], Q.l1[1], Q.llc[1]);
+  GcdInfo sz;  // the size fields only
+  sz.da = Q.da; sz.db = Q.db;
+  sz.l2a = Q.l2[0]; sz.l1a = Q.l1[0]; sz.l2b = Q.l2[1]; sz.l1b = Q.l1[1];
+  sz.lbeta = std::min(Q.llc[0], Q.llc[1]);
+  // Mignotte: a factor of degree e of a has coefficients <= 2^e ||a||_2
+  Q.deg_bound = std::min(Q.da, Q.db);
+  Q.out_nlimbs = (int)std::ceil((Q.deg_bound + std::min(Q.l2[0], Q.l2[1]) + 3.0) / 32.0) + 1;
+  double worst = 0.0;
+  for (int e : {0, Q.deg_bound}) worst = std::max(worst, bits_needed_full(sz, e));
+  Q.kmax = std::min(KMAX, std::max(primes_for_bits(worst), primes_for_bits(bits_needed_opt(sz))) + 12);
+  Q.target0 = std::min(Q.kmax, std::max(3, primes_for_bits(bits_needed_opt(sz)) + 2));
+  return SNC_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Batched driver.  n problems share one workspace and advance in rounds.  In a
 // round every unfinished problem draws its next primes; one upload, one
 // reduction launch, one Euclid launch per register class and one download
-// serve all of them.  Problems whose minimal-degree primes suffice are then
-// lifted (gather, CRT digits and combination per problem, one upload and one
-// download in all) and certified; the others draw more primes next round.
+// serve all of them.  The first round starts from the limbs as given, and
+// the host parses the inputs and computes contents while it runs; primes
+// dividing a content are then set aside.  Problems whose minimal-degree
+// primes suffice are lifted (gather, CRT digits and combination per problem,
+// one upload and one download in all) and certified; the others draw more
+// primes in the next round.
 // ---------------------------------------------------------------------------
 struct GcdProb {
+  const snc_upoly* a = nullptr;
+  const snc_upoly* b = nullptr;
+  Quick Q;
   UPoly A, B;
-  int nla = 1, nlb = 1;
   GcdInfo I;
   snc_upoly* out = nullptr;
-  bool done = false;
+  bool done = false, parsed = false;
   int K = 0, T = 0, wl = 0, lg = 0, cls = 0;
   size_t nmax = 0;
   GcdDesc G{};
+  std::vector<uint8_t> usable;  // per slot, known after the round that computed it
   // word offsets into the workspace
-  size_t coef = 0, slot_prime = 0, slot_scale = 0, e = 0;
+  size_t coef = 0, slot_prime = 0, e = 0;
   size_t res = 0, w = 0, u = 0, v = 0;
-  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0, betas = 0;
+  size_t primes = 0, garner = 0, wtab = 0, ptab = 0, jobs = 0, prefd = 0, prefc = 0, sel = 0, scales = 0;
   size_t wv = 0, uv = 0, vv = 0, dig = 0, outw = 0;
   // round state
   int ns = 0, next_prime = 0, target = 0, first = 0;
@@ -298,27 +419,26 @@ void layout_batch(std::vector<GcdProb>& P, GcdBatchLayout& L) {
   size_t w = 0;
   L.descs = w; w += align_words(sizeof(GcdDesc) / 4 * P.size());
   L.item_cap = 0;
-  for (const auto& p : P) if (!p.I.trivial) L.item_cap += (size_t)p.I.kmax;
+  for (const auto& p : P) if (!p.Q.trivial) L.item_cap += (size_t)p.Q.kmax;
   L.items = w; w += align_words(2 * L.item_cap);
   for (auto& p : P) {
-    if (p.I.trivial) continue;
-    p.K = p.I.kmax;
-    p.T = p.I.da + p.I.db + 2;
-    p.wl = std::min(p.I.da, p.I.db) + 1;
-    p.nmax = (size_t)std::max(p.I.da, p.I.db) + 1;
+    if (p.Q.trivial) continue;
+    p.K = p.Q.kmax;
+    p.T = p.Q.da + p.Q.db + 2;
+    p.wl = std::min(p.Q.da, p.Q.db) + 1;
+    p.nmax = (size_t)std::max(p.Q.da, p.Q.db) + 1;
     p.lg = lx_of(p.K);
-    p.cls = gcd_reg_slots(std::max(p.I.da, p.I.db));
-    p.coef = w; w += align_words((size_t)p.T * p.I.nl);
+    p.cls = gcd_reg_slots(std::max(p.Q.da, p.Q.db));
+    p.coef = w; w += align_words((size_t)(p.Q.deriv ? p.Q.da + 1 : p.T) * p.Q.nl);
     p.slot_prime = w; w += align_words(p.K);
-    p.slot_scale = w; w += align_words((size_t)3 * p.K);
   }
   L.hdr_end = w;
   L.e_begin = w;
-  for (auto& p : P) if (!p.I.trivial) { p.e = w; w += align_words(p.K); }
+  for (auto& p : P) if (!p.Q.trivial) { p.e = w; w += align_words(p.K); }
   L.e_end = w;
   L.crt_begin = w;
   for (auto& p : P) {
-    if (p.I.trivial) continue;
+    if (p.Q.trivial) continue;
     const size_t K = p.K;
     p.primes = w; w += align_words(sizeof(PrimeC) / 4 * K);
     p.garner = w; w += align_words(K);
@@ -328,33 +448,48 @@ void layout_batch(std::vector<GcdProb>& P, GcdBatchLayout& L) {
     p.prefd = w; w += align_words(8);
     p.prefc = w; w += align_words(8);
     p.sel = w; w += align_words(K);
-    p.betas = w; w += align_words(K);
+    p.scales = w; w += align_words(3 * K);
   }
   L.crt_end = w;
   L.out_begin = w;
-  for (auto& p : P) if (!p.I.trivial) { p.outw = w; w += align_words(3 * p.nmax * p.lg); }
+  for (auto& p : P) if (!p.Q.trivial) { p.outw = w; w += align_words(3 * p.nmax * p.lg); }
   L.out_end = w;
   for (auto& p : P) {
-    if (p.I.trivial) continue;
+    if (p.Q.trivial) continue;
     const size_t K = p.K;
     p.res = w; w += align_words(K * p.T);
     p.w = w; w += align_words(K * p.wl);
-    p.u = w; w += align_words(K * (p.I.da + 1));
-    p.v = w; w += align_words(K * (p.I.db + 1));
+    p.u = w; w += align_words(K * (p.Q.da + 1));
+    p.v = w; w += align_words(K * (p.Q.db + 1));
     p.wv = w; w += align_words(K * p.wl);
-    p.uv = w; w += align_words(K * (p.I.da + 1));
-    p.vv = w; w += align_words(K * (p.I.db + 1));
+    p.uv = w; w += align_words(K * (p.Q.da + 1));
+    p.vv = w; w += align_words(K * (p.Q.db + 1));
     p.dig = w; w += align_words(3 * p.nmax * K);
   }
   L.total = w;
 }
 
-int parse_problem(const snc_upoly* a, const snc_upoly* b, bool deriv, GcdProb& p, std::string& err) {
-  int st = parse_upoly(a, p.A, p.nla, err);
+// big-integer form of a and b (b = a' when deriv) and their contents
+int parse_analyse(GcdProb& p, std::string& err) {
+  int nla = 1, nlb = 1;
+  int st = parse_upoly(p.a, p.A, nla, err);
   if (st) return st;
-  if (deriv) derivative(p.A, p.B, p.nlb);
-  else st = parse_upoly(b, p.B, p.nlb, err);
+  if (p.Q.deriv) derivative(p.A, p.B);
+  else st = parse_upoly(p.b, p.B, nlb, err);
+  if (st) return st;
+  st = p.Q.trivial ? analyse(p.A, p.B, nla, nlb, p.I) : analyse(p.A, p.B, nla, nlb, p.I, p.Q.l2, p.Q.l1);
+  p.parsed = true;
   return st;
+}
+
+// rows 0..deg of a limb array into nl-limb rows (sign-extended)
+void pack_rows(const snc_upoly* a, int deg, int nl, uint32_t* dst) {
+  for (int i = 0; i <= deg; ++i) {
+    const uint32_t* src = a->limbs + (size_t)i * a->nlimbs;
+    const uint32_t ext = (src[a->nlimbs - 1] >> 31) ? 0xffffffffu : 0u;
+    uint32_t* d = dst + (size_t)i * nl;
+    for (int l = 0; l < nl; ++l) d[l] = l < a->nlimbs ? src[l] : ext;
+  }
 }
 
 }  // namespace
@@ -394,7 +529,7 @@ static BigInt stage_crt(GcdProb& p, const std::vector<int32_t>& sel, int emin, c
     for (size_t l = 0; l < Pr.mag.size() && (int)l < p.lg; ++l) ptab[(size_t)j * p.lg + l] = Pr.mag[l];
     if (j < ks) Pr = Pr.mul_small(q[j]);
   }
-  const int lens[3] = {emin + 1, p.I.da - emin + 1, p.I.db - emin + 1};
+  const int lens[3] = {emin + 1, p.Q.da - emin + 1, p.Q.db - emin + 1};
   const size_t vals[3] = {p.wv, p.uv, p.vv};
   ResJob* jb = (ResJob*)(h + p.jobs);
   int64_t* pd = (int64_t*)(h + p.prefd);
@@ -413,31 +548,33 @@ static BigInt stage_crt(GcdProb& p, const std::vector<int32_t>& sel, int emin, c
     pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
   }
   int32_t* hsel = (int32_t*)(h + p.sel);
-  for (int j = 0; j < ks; ++j) hsel[j] = sel[j];
-  uint32_t* hbeta = h + p.betas;
-  for (int j = 0; j < ks; ++j) hbeta[j] = p.I.beta.mod_small(q[j]);
+  uint32_t* hsc = h + p.scales;
+  for (int j = 0; j < ks; ++j) {
+    hsel[j] = sel[j];
+    hsc[3 * j + 0] = p.I.beta.mod_small(q[j]);
+    hsc[3 * j + 1] = powmod32(p.I.ca.mod_small(q[j]), q[j] - 2, q[j]);
+    hsc[3 * j + 2] = powmod32(p.I.cb.mod_small(q[j]), q[j] - 2, q[j]);
+  }
   return Pr;
 }
 
-// All problems are parsed; this analyses, checks capacities and runs them.
+// Quick scans are done; this runs every problem.
 static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* d_ws, size_t ws_bytes,
                      hipStream_t stream) {
   const int n = (int)P.size();
-  for (auto& p : P) {
-    const int st = analyse(p.A, p.B, p.nla, p.nlb, p.I);
-    if (st) return st;
-  }
-  tm.host("gcd_contents");
   bool short_out = false;
   for (auto& p : P) {
-    if (p.I.trivial) {
-      const int st = write_upoly(p.I.triv, p.out, ctx->err);
+    if (p.Q.trivial) {  // a zero or constant operand: on the host
+      int st = parse_analyse(p, ctx->err);
+      if (st) return st;
+      if (!p.I.trivial) { ctx->err = "gcd: size scan and analysis disagree"; return SNC_EINTERNAL; }
+      st = write_upoly(p.I.triv, p.out, ctx->err);
       if (st == SNC_ERANGE) { short_out = true; continue; }
       if (st) return st;
       p.done = true;
-    } else if (p.out->deg < p.I.deg_bound || p.out->nlimbs < p.I.out_nlimbs || !p.out->limbs) {
-      p.out->deg = p.I.deg_bound;
-      p.out->nlimbs = p.I.out_nlimbs;
+    } else if (p.out->deg < p.Q.deg_bound || p.out->nlimbs < p.Q.out_nlimbs || !p.out->limbs) {
+      p.out->deg = p.Q.deg_bound;
+      p.out->nlimbs = p.Q.out_nlimbs;
       short_out = true;
     }
   }
@@ -463,43 +600,35 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
   for (int i = 0; i < n; ++i) {
     GcdProb& p = P[i];
     if (p.done) continue;
-    for (int t = 0; t < p.T; ++t) {
-      const BigInt& x = t <= p.I.da ? p.A.c[t] : p.B.c[t - p.I.da - 1];
-      if (!x.to_twos(h + p.coef + (size_t)t * p.I.nl, p.I.nl)) { ctx->err = "input conversion"; return SNC_EINTERNAL; }
-    }
+    pack_rows(p.a, p.Q.da, p.Q.nl, h + p.coef);
+    if (!p.Q.deriv) pack_rows(p.b, p.Q.db, p.Q.nl, h + p.coef + (size_t)(p.Q.da + 1) * p.Q.nl);
     GcdDesc& G = p.G;
-    G.da = p.I.da; G.db = p.I.db; G.nl = p.I.nl; G.wl = p.wl;
-    G.coef_off = (int64_t)p.coef; G.slot_prime_off = (int64_t)p.slot_prime; G.slot_scale_off = (int64_t)p.slot_scale;
+    G.da = p.Q.da; G.db = p.Q.db; G.nl = p.Q.nl; G.wl = p.wl; G.deriv = p.Q.deriv ? 1 : 0; G.pad = 0;
+    G.coef_off = (int64_t)p.coef; G.slot_prime_off = (int64_t)p.slot_prime;
     G.res_off = (int64_t)p.res; G.e_off = (int64_t)p.e; G.w_off = (int64_t)p.w; G.u_off = (int64_t)p.u;
     G.v_off = (int64_t)p.v;
     descs[i] = G;
-    p.target = std::min(p.K, std::max(3, primes_for_bits(bits_needed_opt(p.I)) + 2));
+    p.target = p.Q.target0;
+    p.usable.assign(p.K, 0);
   }
+  tm.host("gcd_pack");
   const Tables& TB = tables();
   int32_t* items = (int32_t*)(h + L.items);
   const GcdDesc* descs_d = (const GcdDesc*)(ws + L.descs);
   const int32_t* items_d = (const int32_t*)(ws + L.items);
 
   for (int round = 0; round < 64 && active; ++round) {
-    // 1. next primes of every unfinished problem
+    // 1. next primes of every unfinished problem; before the contents are
+    //    known (first round) every table prime is drawn, later only primes
+    //    dividing neither content
     int maxT = 0;
     for (auto& p : P) {
       if (p.done) continue;
       p.first = p.ns;
       int32_t* slot_prime = (int32_t*)(h + p.slot_prime);
-      uint32_t* slot_scale = h + p.slot_scale;
       while (p.ns < p.target && p.next_prime < KMAX) {
         const uint32_t q = TB.p[p.next_prime];
-        // q must not divide a content; a q dividing both leading coefficients (hence beta)
-        // is detected by the Euclid kernel, which marks the slot unusable
-        const uint32_t cam = p.I.ca.mod_small(q), cbm = p.I.cb.mod_small(q);
-        if (cam && cbm) {
-          slot_prime[p.ns] = p.next_prime;
-          slot_scale[3 * p.ns + 0] = cam;
-          slot_scale[3 * p.ns + 1] = cbm;
-          slot_scale[3 * p.ns + 2] = 0;
-          ++p.ns;
-        }
+        if (!p.parsed || (p.I.ca.mod_small(q) && p.I.cb.mod_small(q))) slot_prime[p.ns++] = p.next_prime;
         ++p.next_prime;
       }
       if (p.ns == p.first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
@@ -515,7 +644,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         GcdProb& p = P[i];
         if (p.done || p.cls != cls) continue;
         for (int s = p.first; s < p.ns; ++s) { items[2 * nitems] = i; items[2 * nitems + 1] = s; ++nitems; }
-        r.maxd = std::max(r.maxd, std::max(p.I.da, p.I.db));
+        r.maxd = std::max(r.maxd, std::max(p.Q.da, p.Q.db));
       }
       r.cnt = nitems - r.off;
       if (r.cnt) ranges.push_back(r);
@@ -530,6 +659,18 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     HIPCHK(hipGetLastError());
     tm.dev_end("gcd_euclid", nitems);
     HIPCHK(hipMemcpyAsync(ctx->h_out, ws + L.e_begin, (L.e_end - L.e_begin) * 4, hipMemcpyDeviceToHost, stream));
+    if (round == 0) {  // while the device works: big integers and contents
+      for (auto& p : P) {
+        if (p.done) continue;
+        const int st = parse_analyse(p, ctx->err);
+        if (st) return st;
+        if (p.I.trivial || p.I.da != p.Q.da || p.I.db != p.Q.db) {
+          ctx->err = "gcd: size scan and analysis disagree";
+          return SNC_EINTERNAL;
+        }
+      }
+      tm.host("gcd_parse_contents");
+    }
     HIPCHK(hipStreamSynchronize(stream));
     tm.host("gcd_d2h_sync");
 
@@ -542,21 +683,26 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       GcdProb& p = P[i];
       if (p.done) continue;
       const int32_t* e_host = (const int32_t*)(ho + (p.e - L.e_begin));
+      const int32_t* slot_prime = (const int32_t*)(h + p.slot_prime);
       int emin = INT32_MAX;
       for (int s = 0; s < p.ns; ++s) {
-        if (e_host[s] == GCD_SLOT_UNUSABLE) continue;
-        if (e_host[s] < 0 || e_host[s] > std::min(p.I.da, p.I.db)) {
-          ctx->err = "gcd: degree " + std::to_string(e_host[s]) + " out of range for prime slot " + std::to_string(s);
-          return SNC_EINTERNAL;
+        if (s >= p.first) {
+          const int32_t es = e_host[s];
+          if (es != GCD_SLOT_UNUSABLE && (es < 0 || es > std::min(p.Q.da, p.Q.db))) {
+            ctx->err = "gcd: degree " + std::to_string(es) + " out of range for prime slot " + std::to_string(s);
+            return SNC_EINTERNAL;
+          }
+          const uint32_t q = TB.p[slot_prime[s]];
+          p.usable[s] = es != GCD_SLOT_UNUSABLE && p.I.ca.mod_small(q) && p.I.cb.mod_small(q);
         }
-        emin = std::min(emin, (int)e_host[s]);
+        if (p.usable[s]) emin = std::min(emin, (int)e_host[s]);
       }
-      if (emin == INT32_MAX) {  // every prime so far divides both leading coefficients
+      if (emin == INT32_MAX) {  // no usable prime yet
         p.target = std::min(p.K, p.ns + 4);
         if (p.target <= p.ns) { ctx->err = "gcd: prime budget exhausted"; return SNC_EINTERNAL; }
         continue;
       }
-      if (emin == 0) {
+      if (emin == 0) {  // a usable prime with a constant gcd: the gcd is the content
         UPoly R;
         R.c = {p.I.c};
         const int st = write_upoly(R, p.out, ctx->err);
@@ -570,7 +716,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         p.I.have_beta = true;
       }
       std::vector<int32_t> sel;
-      for (int s = 0; s < p.ns; ++s) if (e_host[s] == emin) sel.push_back(s);
+      for (int s = 0; s < p.ns; ++s) if (p.usable[s] && e_host[s] == emin) sel.push_back(s);
       const int ks = (int)sel.size();
       const int need = primes_for_bits(bits_needed_opt(p.I));
       if (ks < need) {  // too few lucky-looking primes yet
@@ -578,7 +724,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         if (p.target <= p.ns) { ctx->err = "gcd: prime budget exhausted"; return SNC_EINTERNAL; }
         continue;
       }
-      Ms[i] = stage_crt(p, sel, emin, (const int32_t*)(h + p.slot_prime), h);
+      Ms[i] = stage_crt(p, sel, emin, slot_prime, h);
       sels[i] = std::move(sel);
       emins[i] = emin;
       lift.push_back(i);
@@ -591,7 +737,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     for (int i : lift) {
       GcdProb& p = P[i];
       const int ks = (int)sels[i].size();
-      launch_gcd_gather(p.G, (const int32_t*)(ws + p.sel), ws + p.betas, (const PrimeC*)(ws + p.primes), ks,
+      launch_gcd_gather(p.G, (const int32_t*)(ws + p.sel), ws + p.scales, (const PrimeC*)(ws + p.primes), ks,
                         emins[i], ws, (int64_t)p.wv, (int64_t)p.uv, (int64_t)p.vv, stream);
       CrtTables tb{(const PrimeC*)(ws + p.primes), ws + p.garner, ws + p.wtab, ws + p.ptab, ks, p.lg};
       const int64_t* pd = (const int64_t*)(h + p.prefd);
@@ -607,7 +753,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       GcdProb& p = P[i];
       const int emin = emins[i];
       const int ks = (int)sels[i].size();
-      const int lens[3] = {emin + 1, p.I.da - emin + 1, p.I.db - emin + 1};
+      const int lens[3] = {emin + 1, p.Q.da - emin + 1, p.Q.db - emin + 1};
       const uint32_t* hq = ho + (p.outw - L.e_begin);
       UPoly W, U, V;
       UPoly* polys[3] = {&W, &U, &V};
@@ -661,11 +807,13 @@ static int gcd_run(snc_ctx* ctx, int n, const snc_upoly* a, const snc_upoly* b, 
   GcdTimer tm(ctx, stream);
   std::vector<GcdProb> P(n);
   for (int i = 0; i < n; ++i) {
-    const int st = parse_problem(&a[i], deriv ? nullptr : &b[i], deriv, P[i], ctx->err);
-    if (st) return st;
+    P[i].a = &a[i];
+    P[i].b = deriv ? nullptr : &b[i];
     P[i].out = &out[i];
+    const int st = quick_scan(P[i].a, P[i].b, deriv, P[i].Q, ctx->err);
+    if (st) return st;
   }
-  tm.host("gcd_parse");
+  tm.host("gcd_scan");
   return gcd_batch(ctx, tm, P, d_ws, ws_bytes, stream);
 }
 
@@ -673,8 +821,10 @@ static int gcd_plan(int n, const snc_upoly* a, const snc_upoly* b, bool deriv, s
   std::string err;
   std::vector<GcdProb> P(n);
   for (int i = 0; i < n; ++i) {
-    int st = parse_problem(&a[i], deriv ? nullptr : &b[i], deriv, P[i], err);
-    if (!st) st = analyse(P[i].A, P[i].B, P[i].nla, P[i].nlb, P[i].I);
+    P[i].a = &a[i];
+    P[i].b = deriv ? nullptr : &b[i];
+    int st = quick_scan(P[i].a, P[i].b, deriv, P[i].Q, err);
+    if (!st && P[i].Q.trivial) st = parse_analyse(P[i], err);  // exact size of a host result
     if (st) return st;
   }
   GcdBatchLayout L;
@@ -682,15 +832,17 @@ static int gcd_plan(int n, const snc_upoly* a, const snc_upoly* b, bool deriv, s
   int needs_device = 0;
   if (total) *total = snc_plan{};
   for (int i = 0; i < n; ++i) {
-    const GcdInfo& I = P[i].I;
+    const Quick& Q = P[i].Q;
     snc_plan pl{};
-    pl.deg_bound = I.deg_bound;
-    pl.out_nlimbs = I.out_nlimbs;
-    pl.nprimes = I.trivial ? 0 : I.kmax;
-    pl.workspace_bytes = 0;
-    if (!I.trivial) {
+    if (Q.trivial) {
+      pl.deg_bound = P[i].I.deg_bound;
+      pl.out_nlimbs = P[i].I.out_nlimbs;
+    } else {
+      pl.deg_bound = Q.deg_bound;
+      pl.out_nlimbs = Q.out_nlimbs;
+      pl.nprimes = Q.kmax;
       std::vector<GcdProb> one(1);
-      one[0].I = I;
+      one[0].Q = Q;
       GcdBatchLayout L1;
       layout_batch(one, L1);
       pl.workspace_bytes = L1.total * 4;

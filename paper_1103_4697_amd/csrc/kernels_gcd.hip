@@ -2,13 +2,15 @@
 // derivative in the square-free factorisation, and the content of f;
 // Section 4, "Symbolic Speedups": the gcd follows the same modular scheme).
 //
-// Per prime p (one workgroup each): the primitive parts a/cont(a) and
-// b/cont(b) reduced mod p, their monic gcd G_p by Euclid in LDS, the scaled
-// gcd w_p = beta * G_p (beta = gcd of the leading coefficients of the
-// primitive parts) and the cofactors u_p = a_p / G_p, v_p = b_p / G_p by
-// exact division mod p.  The host keeps the primes of minimal gcd degree,
-// lifts w, u, v by Chinese remaindering and certifies beta*a = w*u,
-// beta*b = w*v over Z from a norm bound.
+// Per (problem, prime p), one wavefront (or one workgroup above degree 2047):
+// a and b reduced mod p (b = a' formed from a's residues when asked), their
+// monic gcd G_p by Euclid, and a / G_p, b / G_p by exact division mod p.  A
+// prime dividing both leading coefficients is marked unusable.  The gather
+// kernel scales the selected primes' rows to w_p = beta G_p (beta = gcd of the
+// leading coefficients of the primitive parts), u_p = (a / cont a) / G_p and
+// v_p = (b / cont b) / G_p.  The host keeps the primes of minimal gcd degree,
+// lifts w, u, v by Chinese remaindering and certifies beta abar = w u,
+// beta bbar = w v over Z from a norm bound.
 #include <hip/hip_runtime.h>
 
 #include "snc_internal.hpp"
@@ -38,12 +40,15 @@ __global__ __launch_bounds__(256) void k_gcd_reduce(const GcdDesc* descs, const 
   if (t >= T) return;
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
-  ws[G.res_off + (int64_t)slot * T + t] = reduce_coef(ws + G.coef_off + (int64_t)t * G.nl, G.nl, c);
-}
-
-// Montgomery form of 1 / (cont mod p); cont mod p is given plain and non-zero
-__device__ __forceinline__ uint32_t content_inverse(uint32_t r, const PrimeC& c) {
-  return r == 1u ? c.r1 : minv(to_mont(r, c), c);
+  uint32_t r;
+  if (G.deriv && t > G.da) {  // b_j = (j + 1) a_{j+1}
+    const int j = t - G.da - 1;
+    r = mmulc(reduce_coef(ws + G.coef_off + (int64_t)(j + 1) * G.nl, G.nl, c), to_mont((uint32_t)(j + 1), c),
+              c.p, c.pinv);
+  } else {
+    r = reduce_coef(ws + G.coef_off + (int64_t)t * G.nl, G.nl, c);
+  }
+  ws[G.res_off + (int64_t)slot * T + t] = r;
 }
 
 __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, const int32_t* items,
@@ -54,8 +59,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   const int slot = items[2 * blockIdx.x + 1];
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
-  const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
-  const uint32_t ia = content_inverse(sc[0], c), ib = content_inverse(sc[1], c);
+
   const int maxd = G.da > G.db ? G.da : G.db;
   uint32_t* P0 = sm;
   uint32_t* P1 = sm + (maxd + 1);
@@ -64,8 +68,8 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
   const uint32_t* rb = ra + G.da + 1;
   for (int i = tid; i <= maxd; i += GCD_THREADS) {
-    P0[i] = i <= G.da ? mmulc(ra[i], ia, c.p, c.pinv) : 0u;
-    P1[i] = i <= G.db ? mmulc(rb[i], ib, c.p, c.pinv) : 0u;
+    P0[i] = i <= G.da ? ra[i] : 0u;
+    P1[i] = i <= G.db ? rb[i] : 0u;
   }
   __syncthreads();
   uint32_t* A = P0;
@@ -107,19 +111,18 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
     // constant gcd: the cofactors are the primitive parts themselves
     uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
     uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
-    for (int i = tid; i <= G.da; i += GCD_THREADS) u[i] = from_mont(mmulc(ra[i], ia, c.p, c.pinv), c);
-    for (int i = tid; i <= G.db; i += GCD_THREADS) v[i] = from_mont(mmulc(rb[i], ib, c.p, c.pinv), c);
+    for (int i = tid; i <= G.da; i += GCD_THREADS) u[i] = from_mont(ra[i], c);
+    for (int i = tid; i <= G.db; i += GCD_THREADS) v[i] = from_mont(rb[i], c);
     return;
   }
   // exact division of the primitive parts by the monic gcd, in LDS
   for (int pass = 0; pass < 2; ++pass) {
     const int dn = pass ? G.db : G.da;
     const uint32_t* rs = pass ? rb : ra;
-    const uint32_t sc2 = pass ? ib : ia;
     uint32_t* q = ws + (pass ? G.v_off : G.u_off) + (int64_t)slot * (dn + 1);
     uint32_t* Rr = P0;
     __syncthreads();
-    for (int i = tid; i <= dn; i += GCD_THREADS) Rr[i] = mmulc(rs[i], sc2, c.p, c.pinv);
+    for (int i = tid; i <= dn; i += GCD_THREADS) Rr[i] = rs[i];
     for (int i = tid; i <= dn; i += GCD_THREADS) q[i] = 0u;
     __syncthreads();
     int dr = dn;
@@ -325,19 +328,18 @@ __device__ __forceinline__ int euclid_levels(uint32_t (&X)[E], int dX, uint32_t 
 
 // load coefficients 0..deg of a residue row (scaled by sc) top-aligned
 template <int E>
-__device__ __forceinline__ void reg_load(uint32_t (&X)[E], const uint32_t* row, int deg, uint32_t sc, int lane,
-                                         const PrimeC& c) {
+__device__ __forceinline__ void reg_load(uint32_t (&X)[E], const uint32_t* row, int deg, int lane) {
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int i = lane * E + s;
-    X[s] = i <= deg ? mmul(row[deg - i], sc, c.p, c.pinv) : 0u;
+    X[s] = i <= deg ? row[deg - i] : 0u;
   }
 }
 
 template <int E>
 __device__ __forceinline__ void reg_cofactor(uint32_t (&R)[E], const uint32_t (&G)[E], int e, const uint32_t* row,
-                                             int deg, uint32_t sc, uint32_t* q, int lane, const PrimeC& c) {
-  reg_load<E>(R, row, deg, sc, lane, c);
+                                             int deg, uint32_t* q, int lane, const PrimeC& c) {
+  reg_load<E>(R, row, deg, lane);
   for (int i = lane; i <= deg; i += 64) q[i] = 0u;
   const int dR = reg_trim<E>(R, deg, c);
   for (int t = dR - e; t >= 0; --t) {
@@ -355,15 +357,14 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   const int slot = items[2 * blockIdx.x + 1];
   const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
   const PrimeC c = primes[pidx];
-  const uint32_t* sc = ws + G.slot_scale_off + 3 * (int64_t)slot;
-  const uint32_t ia = content_inverse(sc[0], c), ib = content_inverse(sc[1], c);
+
   const int T = G.da + G.db + 2;
   const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
   const uint32_t* rb = ra + G.da + 1;
   extern __shared__ uint32_t sm[];  // 2 * 64 * E words
   uint32_t X[E], Y[E], Gm[E];
-  reg_load<E>(X, ra, G.da, ia, lane, c);
-  reg_load<E>(Y, rb, G.db, ib, lane, c);
+  reg_load<E>(X, ra, G.da, lane);
+  reg_load<E>(Y, rb, G.db, lane);
   const int dX = reg_trim<E>(X, G.da, c);
   const int dY = reg_trim<E>(Y, G.db, c);
   if (dX < G.da && dY < G.db) {
@@ -387,29 +388,37 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
   uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
   if (e == 0) {
-    for (int i = lane; i <= G.da; i += 64) u[i] = from_mont(mmulc(ra[i], ia, c.p, c.pinv), c);
-    for (int i = lane; i <= G.db; i += 64) v[i] = from_mont(mmulc(rb[i], ib, c.p, c.pinv), c);
+    for (int i = lane; i <= G.da; i += 64) u[i] = from_mont(ra[i], c);
+    for (int i = lane; i <= G.db; i += 64) v[i] = from_mont(rb[i], c);
     return;
   }
-  reg_cofactor<E>(X, Gm, e, ra, G.da, ia, u, lane, c);
-  reg_cofactor<E>(X, Gm, e, rb, G.db, ib, v, lane, c);
+  reg_cofactor<E>(X, Gm, e, ra, G.da, u, lane, c);
+  reg_cofactor<E>(X, Gm, e, rb, G.db, v, lane, c);
 }
 
 static const int kGcdE[] = {2, 4, 6, 9, 12, 16, 24, 32};
 
 // copy the rows of the selected primes into compact [k][len] arrays; the
 // monic gcd is scaled by beta mod p on the way (w = beta * monic gcd)
-__global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* betas, const PrimeC* sprimes,
+__global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* scales, const PrimeC* sprimes,
                              int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv) {
   const int j = blockIdx.y;
   const int s = sel[j];
   const PrimeC c = sprimes[j];
-  const uint32_t bm = to_mont(betas[j], c);
+  const uint32_t bm = to_mont(scales[3 * j + 0], c);  // beta
+  const uint32_t ia = to_mont(scales[3 * j + 1], c);  // 1 / cont(a)
+  const uint32_t ib = to_mont(scales[3 * j + 2], c);  // 1 / cont(b)
   const int nw = e + 1, nu = G.da - e + 1, nv = G.db - e + 1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nw + nu + nv; i += gridDim.x * blockDim.x) {
-    if (i < nw) ws[wv + (int64_t)j * nw + i] = mmulc(bm, ws[G.w_off + (int64_t)s * G.wl + i], c.p, c.pinv);
-    else if (i < nw + nu) ws[uv + (int64_t)j * nu + (i - nw)] = ws[G.u_off + (int64_t)s * (G.da + 1) + (i - nw)];
-    else ws[vv + (int64_t)j * nv + (i - nw - nu)] = ws[G.v_off + (int64_t)s * (G.db + 1) + (i - nw - nu)];
+    if (i < nw) {
+      ws[wv + (int64_t)j * nw + i] = mmulc(bm, ws[G.w_off + (int64_t)s * G.wl + i], c.p, c.pinv);
+    } else if (i < nw + nu) {
+      const uint32_t x = ws[G.u_off + (int64_t)s * (G.da + 1) + (i - nw)];
+      ws[uv + (int64_t)j * nu + (i - nw)] = mmulc(ia, x, c.p, c.pinv);
+    } else {
+      const uint32_t x = ws[G.v_off + (int64_t)s * (G.db + 1) + (i - nw - nu)];
+      ws[vv + (int64_t)j * nv + (i - nw - nu)] = mmulc(ib, x, c.p, c.pinv);
+    }
   }
   (void)ks;
 }
@@ -444,10 +453,10 @@ void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, i
   hipLaunchKernelGGL(k_gcd_modp, grid, dim3(GCD_THREADS), shmem, s, descs, items, primes, ws);
 }
 
-void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
+void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* scales_d, const PrimeC* sprimes_d,
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s) {
   const int n = G.da + G.db + 3 - e;
-  hipLaunchKernelGGL(k_gcd_gather, dim3((n + 255) / 256, ks), dim3(256), 0, s, G, sel_d, betas_d, sprimes_d, ks, e,
+  hipLaunchKernelGGL(k_gcd_gather, dim3((n + 255) / 256, ks), dim3(256), 0, s, G, sel_d, scales_d, sprimes_d, ks, e,
                      ws, wv, uv, vv);
 }
 

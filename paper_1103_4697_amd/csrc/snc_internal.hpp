@@ -79,14 +79,15 @@ struct GcdDesc {
   int32_t da, db;          // degrees of a and b
   int32_t nl;              // limbs per input coefficient
   int32_t wl;              // row length of w: min(da, db) + 1
-  int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl] (uint32 index)
+  int32_t deriv;           // 1: b = a' (only a's limbs are stored; b's residues are formed from them)
+  int32_t pad;
+  int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl], or [da+1][nl] when deriv (uint32 index)
   int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
-  int64_t slot_scale_off;  // 3 uint32 per slot: cont(a) mod p, cont(b) mod p (plain, non-zero), unused
   int64_t res_off;         // residues [slot][da+db+2] (Montgomery)
   int64_t e_off;           // int32 per slot: degree of the gcd mod p, -2 if p divides both leading coefficients
   int64_t w_off;           // [slot][wl]   monic gcd mod p (plain)
-  int64_t u_off;           // [slot][da+1] cofactor of a mod p (plain)
-  int64_t v_off;           // [slot][db+1] cofactor of b mod p (plain)
+  int64_t u_off;           // [slot][da+1] a / monic gcd mod p (plain)
+  int64_t v_off;           // [slot][db+1] b / monic gcd mod p (plain)
 };
 
 // gcd degree written for a prime dividing both leading coefficients (the prime is not used)
@@ -132,7 +133,9 @@ void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, i
 int gcd_reg_slots(int maxd);             // register class of a degree (slots per lane), 0: LDS kernel
 void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, int slots, int maxd, uint32_t* ws,
                        hipStream_t s);   // monic gcd and cofactors per item; one register class per launch
-void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* betas_d, const PrimeC* sprimes_d,
+// selected slots sel_d[j] (primes sprimes_d[j]) into compact rows; scales_d[3j..3j+2] = beta,
+// cont(a)^-1, cont(b)^-1 mod q_j (plain) multiply w, u, v
+void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* scales_d, const PrimeC* sprimes_d,
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();
 
