@@ -566,47 +566,62 @@ void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 // ---------------------------------------------------------------------------
 constexpr int CRT_SLOTS = KMAX / 64;
 
+constexpr int CRT_WCH = 8192;  // words of W table rows staged in LDS at a time
+
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTables tb, const ResJob* jobs,
                                                                         const int64_t* prefix,
                                                                         int njobs, uint32_t* ws) {
+  __shared__ uint32_t wrows[CRT_WCH];  // rows j0..j0+ch-1 of W, columns 0..k-1
+  __shared__ uint2 lp[KMAX];           // (p, pinv) of the k primes
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = (int)(b - prefix[jj]) * CRT_COEF_PER_BLOCK + wave;
-  if (t > J.D) return;
+  const bool active = t <= J.D;  // the block's waves share one job; idle ones still meet the barriers
   const int k = J.k;
+  const int ch = min(64, max(1, CRT_WCH / k));
   const int n1 = J.D + 1;
   const uint32_t* V = ws + J.val_off;
-  uint32_t* dig = ws + J.dig_off + (int64_t)t * k;
+  uint32_t* dig = ws + J.dig_off + (int64_t)(active ? t : 0) * k;
+  for (int i = threadIdx.x; i < k; i += 64 * CRT_COEF_PER_BLOCK) lp[i] = make_uint2(tb.primes[i].p, tb.primes[i].pinv);
   uint32_t r[CRT_SLOTS], S[CRT_SLOTS];
 #pragma unroll
   for (int s = 0; s < CRT_SLOTS; ++s) {
     const int i = lane + 64 * s;
     r[s] = 0; S[s] = 0;
-    if (64 * s < k && i < k) r[s] = V[(int64_t)i * n1 + t];
+    if (active && 64 * s < k && i < k) r[s] = V[(int64_t)i * n1 + t];
   }
 #pragma unroll
   for (int s = 0; s < CRT_SLOTS; ++s) {
     if (64 * s >= k) break;
-    const int i0 = lane + 64 * s;
-    const PrimeC c0 = tb.primes[i0 < k ? i0 : 0];
-    const uint32_t g0 = tb.garner[i0 < k ? i0 : 0];
+    const PrimeC c0 = tb.primes[lane + 64 * s < k ? lane + 64 * s : 0];
+    const uint32_t g0 = tb.garner[lane + 64 * s < k ? lane + 64 * s : 0];
     for (int q = 0; q < 64; ++q) {
       const int j = 64 * s + q;
       if (j >= k) break;
+      const int jr = j % ch;
+      if (jr == 0) {  // stage rows j .. j+ch-1
+        __syncthreads();
+        const int nrow = min(ch, k - j);
+        for (int x = threadIdx.x; x < nrow * k; x += 64 * CRT_COEF_PER_BLOCK) {
+          const int row = x / k, col = x - row * k;
+          wrows[x] = tb.wtab[(int64_t)(j + row) * tb.wstride + col];
+        }
+        __syncthreads();
+      }
       const uint32_t cand = canon(redc((uint64_t)msub(r[s], S[s], c0.p) * g0, c0.p, c0.pinv), c0.p);
       const uint32_t y = __builtin_amdgcn_readlane(cand, q);
-      if (lane == q) dig[j] = y;
+      if (active && lane == q) dig[j] = y;
+      const uint32_t* wr = wrows + jr * k;
 #pragma unroll
       for (int s2 = 0; s2 < CRT_SLOTS; ++s2) {
         if (64 * s2 >= k) break;
         if (64 * s2 + 63 <= j) continue;
         const int i = lane + 64 * s2;
         if (i > j && i < k) {
-          const PrimeC ci = tb.primes[i];
-          const uint32_t w = tb.wtab[(int64_t)j * tb.wstride + i];
-          S[s2] = madd(S[s2], canon(redc((uint64_t)y * w, ci.p, ci.pinv), ci.p), ci.p);
+          const uint2 ci = lp[i];
+          S[s2] = madd(S[s2], canon(redc((uint64_t)y * wr[i], ci.x, ci.y), ci.x), ci.x);
         }
       }
     }
@@ -641,6 +656,7 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
     // P_j has at most 30 j / 32 + 1 limbs, so limbs >= l0 need j >= 32 l0 / 30 - 1
     int j0 = (32 * l0) / 30 - 1;
     if (j0 < 0) j0 = 0;
+#pragma unroll 8
     for (int j = j0; j < k; ++j) {
       const uint32_t pl = l < tb.pstride ? tb.ptab[(int64_t)j * tb.pstride + l] : 0u;
       const uint64_t pr = (uint64_t)d[j] * pl;
