@@ -621,7 +621,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     // 1. next primes of every unfinished problem; before the contents are
     //    known (first round) every table prime is drawn, later only primes
     //    dividing neither content
-    int maxT = 0;
+    int max_rows = 0, max_nl = 1;
     for (auto& p : P) {
       if (p.done) continue;
       p.first = p.ns;
@@ -632,7 +632,8 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         ++p.next_prime;
       }
       if (p.ns == p.first) { ctx->err = "gcd: ran out of primes before the result certified"; return SNC_EINTERNAL; }
-      maxT = std::max(maxT, p.T);
+      max_rows = std::max(max_rows, p.Q.deriv ? p.Q.da + 1 : p.T);
+      max_nl = std::max(max_nl, p.Q.nl);
     }
     // work items grouped by register class, one launch per class
     struct Range { int cls, off, cnt, maxd; };
@@ -652,7 +653,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     tm.host("gcd_select_primes");
     HIPCHK(hipMemcpyAsync(ws, h, L.hdr_end * 4, hipMemcpyHostToDevice, stream));
     tm.dev_begin();
-    launch_gcd_reduce(descs_d, items_d, nitems, maxT, ws, stream);
+    launch_gcd_reduce(descs_d, items_d, nitems, max_rows, max_nl, ws, stream);
     tm.dev_end("gcd_reduce", nitems);
     tm.dev_begin();
     for (const Range& r : ranges) launch_gcd_euclid(descs_d, items_d + 2 * r.off, r.cnt, r.cls, r.maxd, ws, stream);

@@ -13,6 +13,8 @@
 // beta bbar = w v over Z from a norm bound.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "snc_internal.hpp"
 
 namespace snc {
@@ -31,24 +33,40 @@ __device__ __forceinline__ uint32_t reduce_coef(const uint32_t* limbs, int nl, c
 
 // Work items are (problem, slot) pairs: items[2w] indexes descs, items[2w+1]
 // is the slot (prime) of that problem.
-__global__ __launch_bounds__(256) void k_gcd_reduce(const GcdDesc* descs, const int32_t* items,
+//
+// Residues of the stored rows (a's rows, then b's unless b = a'): a block
+// stages rpb consecutive rows in LDS with coalesced loads and reduces them for
+// up to GCD_RED_ITEMS work items; with b = a', row i also gives b_{i-1} = i a_i.
+constexpr int GCD_RED_ITEMS = 1;
+
+__global__ __launch_bounds__(256) void k_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int rpb,
                                                     const PrimeC* primes, uint32_t* ws) {
-  const GcdDesc G = descs[items[2 * blockIdx.y]];
-  const int slot = items[2 * blockIdx.y + 1];
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int T = G.da + G.db + 2;
-  if (t >= T) return;
-  const int pidx = ((const int32_t*)(ws + G.slot_prime_off))[slot];
-  const PrimeC c = primes[pidx];
-  uint32_t r;
-  if (G.deriv && t > G.da) {  // b_j = (j + 1) a_{j+1}
-    const int j = t - G.da - 1;
-    r = mmulc(reduce_coef(ws + G.coef_off + (int64_t)(j + 1) * G.nl, G.nl, c), to_mont((uint32_t)(j + 1), c),
-              c.p, c.pinv);
-  } else {
-    r = reduce_coef(ws + G.coef_off + (int64_t)t * G.nl, G.nl, c);
+  extern __shared__ uint32_t lm[];  // rpb rows of nl limbs
+  const int row0 = blockIdx.x * rpb;
+  const int w0 = blockIdx.y * GCD_RED_ITEMS;
+  const int w1 = min(w0 + GCD_RED_ITEMS, nitems);
+  int staged = -1;
+  for (int w = w0; w < w1; ++w) {
+    const int pb = items[2 * w], slot = items[2 * w + 1];
+    const GcdDesc G = descs[pb];
+    const int rows = G.deriv ? G.da + 1 : G.da + G.db + 2;
+    if (row0 >= rows) continue;  // uniform over the block
+    const int nr = min(rpb, rows - row0);
+    if (pb != staged) {
+      __syncthreads();
+      for (int x = threadIdx.x; x < nr * G.nl; x += 256) lm[x] = ws[G.coef_off + (int64_t)row0 * G.nl + x];
+      __syncthreads();
+      staged = pb;
+    }
+    if ((int)threadIdx.x < nr) {
+      const int i = row0 + threadIdx.x;
+      const PrimeC c = primes[((const int32_t*)(ws + G.slot_prime_off))[slot]];
+      uint32_t* res = ws + G.res_off + (int64_t)slot * (G.da + G.db + 2);
+      const uint32_t r = reduce_coef(lm + threadIdx.x * G.nl, G.nl, c);
+      res[i] = r;
+      if (G.deriv && i >= 1) res[G.da + i] = mmulc(r, to_mont((uint32_t)i, c), c.p, c.pinv);  // b_{i-1} = i a_i
+    }
   }
-  ws[G.res_off + (int64_t)slot * T + t] = r;
 }
 
 __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, const int32_t* items,
@@ -423,11 +441,13 @@ __global__ void k_gcd_gather(GcdDesc G, const int32_t* sel, const uint32_t* scal
   (void)ks;
 }
 
-void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int maxT, uint32_t* ws,
-                       hipStream_t s) {
-  if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_gcd_reduce, dim3((maxT + 255) / 256, nitems), dim3(256), 0, s, descs, items,
-                     global_crt_tables().primes, ws);
+void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int max_rows, int max_nl,
+                       uint32_t* ws, hipStream_t s) {
+  if (nitems <= 0 || max_rows <= 0) return;
+  const int rpb = std::max(1, std::min(256, 12288 / std::max(max_nl, 1)));
+  const dim3 grid((max_rows + rpb - 1) / rpb, (nitems + GCD_RED_ITEMS - 1) / GCD_RED_ITEMS);
+  hipLaunchKernelGGL(k_gcd_reduce, grid, dim3(256), (size_t)rpb * max_nl * sizeof(uint32_t), s, descs, items, nitems,
+                     rpb, global_crt_tables().primes, ws);
 }
 
 int gcd_reg_slots(int maxd) {

@@ -128,8 +128,8 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
 
 // gcd work items are (problem, slot) pairs indexing a device array of GcdDesc
-void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int maxT, uint32_t* ws,
-                       hipStream_t s);   // residues of a, b per item
+void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int max_rows, int max_nl,
+                       uint32_t* ws, hipStream_t s);   // residues of a, b per item (rows: stored coefficient rows)
 int gcd_reg_slots(int maxd);             // register class of a degree (slots per lane), 0: LDS kernel
 void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, int slots, int maxd, uint32_t* ws,
                        hipStream_t s);   // monic gcd and cofactors per item; one register class per launch
