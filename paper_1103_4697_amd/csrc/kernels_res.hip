@@ -164,10 +164,11 @@ __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* 
 
 // One remainder step X <- prem(X, Y) on the first C+1 entries of the
 // register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
-// above each degree zero).  Branch-free inside an elementary step.
+// above each degree zero).  Branch-free inside an elementary step.  Returns
+// lc(Y), canonical.
 template <int N, int C>
-__device__ __forceinline__ void rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, int b,
-                                      int s, bool& ok, uint32_t& den, const PrimeC& c) {
+__device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, bool& ok,
+                                          const PrimeC& c) {
   const uint32_t lcY = canon(Y[0], c.p);
 #pragma nounroll
   for (int e = 0; e < s; ++e) {
@@ -177,23 +178,35 @@ __device__ __forceinline__ void rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[
     X[C] = 0;
   }
   if (canon(X[0], c.p) == 0) ok = false;
-  den = mmulc(den, mpow(lcY, (uint32_t)(s * (b - 1)), c), c.p, c.pinv);
+  return lcY;
+}
+
+// Scale factors of the normal steps.  A normal step with divisor degree b
+// (s = 2) contributes y^{2(b-1)}, y = lc(divisor), and b drops by one per
+// step, so with prefix products P_j = y_0 ... y_j the whole product is
+// (P_0 P_1 ... P_J)^2 over the steps with b >= 2: two products per step, in
+// straight-line code, instead of a power per step.
+__device__ __forceinline__ void scale_step(uint32_t y, int b, uint32_t& P, uint32_t& Q, const PrimeC& c) {
+  const uint32_t Pn = mmulc(P, y, c.p, c.pinv);
+  const uint32_t Qn = mmulc(Q, Pn, c.p, c.pinv);
+  P = b >= 2 ? Pn : P;
+  Q = b >= 2 ? Qn : Q;
 }
 
 // Remainder pairs (dividend B, divisor A) while the divisor degree bb stays
 // >= C - 8, on arrays of width C; then the next narrower phase.
 template <int N, int C>
 __device__ __forceinline__ void elim_phases(uint32_t (&A)[N + 1], uint32_t (&B)[N + 1], int& a,
-                                            int& bb, bool& ok, uint32_t& den, int& sg,
+                                            int& bb, bool& ok, uint32_t& P, uint32_t& Q, int& sg,
                                             const PrimeC& c) {
 #pragma nounroll
   while (bb >= 2 && bb >= C - 8) {
-    rem_c<N, C>(B, A, a, bb, 2, ok, den, c);  // B <- prem(B, A), degree bb-1
+    scale_step(rem_c<N, C>(B, A, 2, ok, c), bb, P, Q, c);  // B <- prem(B, A), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
-    rem_c<N, C>(A, B, a, bb, 2, ok, den, c);  // A <- prem(A, B), degree bb-1
+    scale_step(rem_c<N, C>(A, B, 2, ok, c), bb, P, Q, c);  // A <- prem(A, B), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
   }
-  if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, ok, den, sg, c);
+  if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, ok, P, Q, sg, c);
 }
 
 template <int N>
@@ -230,13 +243,18 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   if (bb < 1) {
     res = mpow(B[0], (uint32_t)a, c);
   } else {
-    // first remainder: A <- prem(A, B) with s = m - n + 1 elementary steps
-    rem_c<N, N>(A, B, a, bb, a - bb + 1, ok, den, c);
+    // first remainder: A <- prem(A, B) with s = m - n + 1 elementary steps,
+    // scale lc(B)^{s (n - 1)}
+    const int s0 = a - bb + 1;
+    const uint32_t y0 = rem_c<N, N>(A, B, s0, ok, c);
+    den = mpow(y0, (uint32_t)(s0 * (bb - 1)), c);
     sg ^= (a & bb & 1); a = bb; bb -= 1;
     // from here on: dividend B (degree a), divisor A (degree bb)
-    elim_phases<N, N>(A, B, a, bb, ok, den, sg, c);
-    if (bb == 1) {
-      rem_c<N, 8>(B, A, a, bb, 2, ok, den, c);
+    uint32_t P = c.r1, Q = c.r1;
+    elim_phases<N, N>(A, B, a, bb, ok, P, Q, sg, c);
+    den = mmulc(den, mmulc(Q, Q, c.p, c.pinv), c.p, c.pinv);
+    if (bb == 1) {  // last step: divisor of degree 1, scale y^0
+      rem_c<N, 8>(B, A, 2, ok, c);
       sg ^= (a & bb & 1); a = bb; bb -= 1;
       res = mpow(B[0], (uint32_t)a, c);
     } else {
