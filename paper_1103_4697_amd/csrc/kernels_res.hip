@@ -209,7 +209,12 @@ __device__ __forceinline__ void elim_phases(uint32_t (&A)[N + 1], uint32_t (&B)[
   if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, ok, P, Q, sg, c);
 }
 
-template <int N>
+// LDSROWS: the wavefront first copies its prime's residues into LDS
+// (coalesced) and reads the row chunks from there, so the reads pipeline;
+// otherwise they are 64-byte scalar loads.
+constexpr int EE_LDS_MAX = 64 * 1024;
+
+template <int N, bool LDSROWS>
 __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, const int32_t* job_list,
                                                         const int64_t* prefix, int njobs,
                                                         const RowDesc* rows, uint32_t* ws,
@@ -222,10 +227,18 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   const int npb = (J.D + EE_BLOCK) / EE_BLOCK;
   const int64_t lb = b - prefix[jj];
   const int pi = (int)(lb / npb);
-  const int j = (int)(lb % npb) * EE_BLOCK + threadIdx.x;
-  if (j > J.D) return;
+  const int j0 = (int)(lb % npb) * EE_BLOCK + threadIdx.x;
+  const bool live = j0 <= J.D;  // lanes past the last point still help stage the rows
+  const int j = live ? j0 : J.D;
   const PrimeC c = g_primes[pi];
   const uint32_t* r = ws + J.res_off + (int64_t)pi * J.T;
+  if constexpr (LDSROWS) {
+    extern __shared__ uint4 er4[];  // J.T words
+    uint32_t* er = reinterpret_cast<uint32_t*>(er4);
+    for (int x = threadIdx.x; x < J.T; x += EE_BLOCK) er[x] = r[x];
+    __syncthreads();
+    r = er;
+  }
   const uint32_t X = to_mont((uint32_t)j, c);
   // rows are padded to N+1 per operand (length 0 above the degree): no branches
   const RowDesc* ra = rows + J.rows_off;
@@ -263,6 +276,7 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   }
   res = mmulc(res, minv(den, c), c.p, c.pinv);
   if (sg) res = mneg(res, c.p);
+  if (!live) return;
   ws[J.val_off + (int64_t)pi * (J.D + 1) + j] = ok ? res : 0u;
   if (!ok) {
     uint32_t idx = atomicAdd(abn_count, 1u);
@@ -280,18 +294,28 @@ int fast_class_of(int maxy) {
 int fast_class_cap(int cls) { return kClassCap[cls]; }
 
 void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
-                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, const RowDesc* rows_d,
+                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
                       hipStream_t s) {
   if (nblocks <= 0) return;
   dim3 g((unsigned)nblocks), blk(EE_BLOCK);
+  const size_t lds = (size_t)max_T * sizeof(uint32_t);
+  const bool in_lds = lds <= (size_t)EE_LDS_MAX;
+#define SNC_EE(NN)                                                                                        \
+  if (in_lds)                                                                                             \
+    hipLaunchKernelGGL((k_eval_elim<NN, true>), g, blk, lds, s, jobs_d, job_list_d, blk_prefix_d, njobs,   \
+                       rows_d, ws, abn_count, abn_list, abn_cap);                                          \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_eval_elim<NN, false>), g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs,    \
+                       rows_d, ws, abn_count, abn_list, abn_cap);
   switch (kClassCap[cls]) {
-    case 8: hipLaunchKernelGGL(k_eval_elim<8>, g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs, rows_d, ws, abn_count, abn_list, abn_cap); break;
-    case 16: hipLaunchKernelGGL(k_eval_elim<16>, g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs, rows_d, ws, abn_count, abn_list, abn_cap); break;
-    case 32: hipLaunchKernelGGL(k_eval_elim<32>, g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs, rows_d, ws, abn_count, abn_list, abn_cap); break;
-    case 48: hipLaunchKernelGGL(k_eval_elim<48>, g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs, rows_d, ws, abn_count, abn_list, abn_cap); break;
-    default: hipLaunchKernelGGL(k_eval_elim<64>, g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs, rows_d, ws, abn_count, abn_list, abn_cap); break;
+    case 8: SNC_EE(8) break;
+    case 16: SNC_EE(16) break;
+    case 32: SNC_EE(32) break;
+    case 48: SNC_EE(48) break;
+    default: SNC_EE(64) break;
   }
+#undef SNC_EE
 }
 
 // ---------------------------------------------------------------------------

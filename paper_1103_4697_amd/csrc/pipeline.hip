@@ -103,7 +103,10 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
     lay.nb_crtc += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
     lay.max_k = std::max(lay.max_k, P.k);
-    if (P.cls >= 0) lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
+    if (P.cls >= 0) {
+      lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
+      lay.max_T_ee[P.cls] = std::max(lay.max_T_ee[P.cls], P.T);
+    }
     else lay.n_gen_inst += (int64_t)P.k * n1;
     lay.total_inst += (int64_t)P.k * n1;
     lay.max_D = std::max(lay.max_D, P.D);
@@ -172,7 +175,8 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   for (int c = 0; c < NCLS; ++c) {
     if (!lay.n_ee_jobs[c]) continue;
     launch_eval_elim(c, jobs, (const int32_t*)(ws + lay.list_ee[c]), (const int64_t*)(ws + lay.pref_ee[c]),
-                     lay.n_ee_jobs[c], lay.nb_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap, s);
+                     lay.n_ee_jobs[c], lay.nb_ee[c], lay.max_T_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap,
+                     s);
     ++nee;
   }
   if (lay.n_gen_jobs) {
@@ -281,7 +285,9 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
   key.push_back(lay.nb_red); key.push_back(lay.nb_interp); key.push_back(lay.nb_crtd);
   key.push_back(lay.nb_crtc); key.push_back(lay.n_gen_inst); key.push_back(lay.max_D);
   key.push_back(lay.total_inst);
-  for (int c = 0; c < NCLS; ++c) { key.push_back(lay.nb_ee[c]); key.push_back(lay.n_ee_jobs[c]); }
+  for (int c = 0; c < NCLS; ++c) {
+    key.push_back(lay.nb_ee[c]); key.push_back(lay.n_ee_jobs[c]); key.push_back(lay.max_T_ee[c]);
+  }
   key.push_back(lay.n_gen_jobs);
   key.push_back((int64_t)lay.abn_count_off); key.push_back((int64_t)lay.abn_list_off);
   for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_crtd, lay.pref_crtc,

@@ -56,6 +56,7 @@ struct BatchLayout {
   int64_t nb_red = 0, nb_interp = 0, nb_crtd = 0, nb_crtc = 0, n_gen_inst = 0;
   int64_t nb_ee[NCLS] = {0};
   int n_ee_jobs[NCLS] = {0}, n_gen_jobs = 0, n_rows = 0, max_D = 0, max_k = 0;
+  int max_T_ee[NCLS] = {0};  // largest residue count per prime among a class's jobs
   int64_t total_inst = 0;
   size_t coef_words = 0;
 };

@@ -110,7 +110,7 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    const uint32_t* ws, uint32_t* res_base, hipStream_t s);
 void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
-                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, const RowDesc* rows_d,
+                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
                       hipStream_t s);
 void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,
