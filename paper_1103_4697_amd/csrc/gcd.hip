@@ -352,6 +352,11 @@ int quick_scan(const snc_upoly* a, const snc_upoly* b, bool deriv, Quick& Q, std
     Q.db = trimmed_degree(b);
   }
   Q.nl = deriv ? Q.nla : std::max(Q.nla, Q.nlb);
+  if (std::max(Q.da, Q.db) > GCD_MAX_DEG) {
+    err = "gcd: degree " + std::to_string(std::max(Q.da, Q.db)) + " exceeds the supported " +
+          std::to_string(GCD_MAX_DEG);
+    return SNC_EINVAL;
+  }
   Q.trivial = Q.da <= 0 || Q.db <= 0;
   if (Q.trivial) return SNC_OK;
   limb_norms(a->limbs, a->nlimbs, Q.da, false, Q.l2[0], Q.l1[0], Q.llc[0]);

@@ -119,20 +119,13 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
     while (dA >= 0 && A[dA] == 0) --dA;
   }
   const int e = dA;  // gcd degree mod p (>= 0: the inputs are non-zero mod p)
+  if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+  if (e == 0) return;  // a usable prime with a constant gcd ends the problem on the host: no rows needed
   const uint32_t inv = minv(A[e], c);
   for (int i = tid; i <= e; i += GCD_THREADS) Gm[i] = mmulc(A[i], inv, c.p, c.pinv);
   __syncthreads();
   uint32_t* w = ws + G.w_off + (int64_t)slot * G.wl;
   for (int i = tid; i < G.wl; i += GCD_THREADS) w[i] = i <= e ? from_mont(Gm[i], c) : 0u;
-  if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
-  if (e == 0) {
-    // constant gcd: the cofactors are the primitive parts themselves
-    uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
-    uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
-    for (int i = tid; i <= G.da; i += GCD_THREADS) u[i] = from_mont(ra[i], c);
-    for (int i = tid; i <= G.db; i += GCD_THREADS) v[i] = from_mont(rb[i], c);
-    return;
-  }
   // exact division of the primitive parts by the monic gcd, in LDS
   for (int pass = 0; pass < 2; ++pass) {
     const int dn = pass ? G.db : G.da;
@@ -390,6 +383,8 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
     return;
   }
   const int e = euclid_levels<E>(X, dX, Y, dY, sm, lane, c);
+  if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+  if (e == 0) return;  // a usable prime with a constant gcd ends the problem on the host: no rows needed
   __syncthreads();
   reg_fetch<E>(Gm, sm, e, lane);
   const uint32_t inv = minv(lead(Gm[0], c.p), c);
@@ -402,14 +397,8 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
     const int i = lane * E + s;
     if (i <= e) w[e - i] = from_mont(Gm[s], c);
   }
-  if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
   uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
   uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
-  if (e == 0) {
-    for (int i = lane; i <= G.da; i += 64) u[i] = from_mont(ra[i], c);
-    for (int i = lane; i <= G.db; i += 64) v[i] = from_mont(rb[i], c);
-    return;
-  }
   reg_cofactor<E>(X, Gm, e, ra, G.da, u, lane, c);
   reg_cofactor<E>(X, Gm, e, rb, G.db, v, lane, c);
 }

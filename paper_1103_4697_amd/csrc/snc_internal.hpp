@@ -131,6 +131,7 @@ CrtTables global_crt_tables();  // the resident tables of the modulus table (aft
 void launch_gcd_reduce(const GcdDesc* descs, const int32_t* items, int nitems, int max_rows, int max_nl,
                        uint32_t* ws, hipStream_t s);   // residues of a, b per item (rows: stored coefficient rows)
 int gcd_reg_slots(int maxd);             // register class of a degree (slots per lane), 0: LDS kernel
+constexpr int GCD_MAX_DEG = 13000;       // the LDS kernel keeps 3 (deg + 1) words
 void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, int slots, int maxd, uint32_t* ws,
                        hipStream_t s);   // monic gcd and cofactors per item; one register class per launch
 // selected slots sel_d[j] (primes sprimes_d[j]) into compact rows; scales_d[3j..3j+2] = beta,

@@ -203,3 +203,15 @@ def test_gcd_batch_plan(snc):
     assert snc.lib().snc_gcd_z_batch_plan(0, None, None, None, C.byref(total)) == 0
     assert total.workspace_bytes == 0
     assert snc.lib().snc_gcd_z_batch_plan(-1, None, None, None, C.byref(total)) == snc.SNC_EINVAL
+
+
+def test_gcd_degree_limit(snc):
+    """Degrees above the supported maximum (13000) are refused at planning."""
+    import ctypes as C
+    keep = []
+    ua = snc._as_upoly([1] * 13002, keep)       # degree 13001
+    ub = snc._as_upoly([1, 1], keep)
+    p = snc.Plan()
+    assert snc.lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)) == snc.SNC_EINVAL
+    ua = snc._as_upoly([1] * 13001, keep)       # degree 13000
+    assert snc.lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)) == 0
