@@ -141,6 +141,21 @@ int snc_resultant_y_prepare(snc_ctx* ctx, int32_t n, const snc_bipoly* f, const 
 int snc_prepared_run(snc_prepared* prep, void* stream, snc_upoly* out);
 int snc_prepared_destroy(snc_prepared* prep);
 
+/* Resultant and square-free gcd in one pass: the projection step of the
+ * curve analysis (Section 2.1) needs R = res_y(f, g) and gcd(R, R') (R / gcd
+ * is the square-free part).  One run of the prepared pipeline computes both:
+ * the modular Euclid of gcd(R, R') runs on R mod p for the resultant's own
+ * primes, on a second stream beside the Chinese remaindering, and a prime not
+ * dividing lc(R) with a constant gcd mod p proves gcd(R, R') = gcd(cont R,
+ * cont R'); otherwise the full modular gcd of R follows (as snc_gcd_z_deriv).
+ * R: the n resultants (conventions of snc_prepared_run).  G: the n gcds
+ * (conventions of snc_gcd_z), sized by snc_prepared_sqfree_plan (gcd_each:
+ * per pair, or NULL), which also sizes d_gws, a second device workspace
+ * (caller-owned, not retained) for the gcd work. */
+int snc_prepared_sqfree_plan(const snc_prepared* prep, snc_plan* gcd_each, snc_plan* gcd_total);
+int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, void* stream, snc_upoly* R,
+                            snc_upoly* G);
+
 /* ---- gcd in Z[x] ---------------------------------------------------------
  * Modular (small primes) gcd: contents on the host, monic gcd and cofactors
  * mod each prime on the device, primes of minimal gcd degree kept, CRT, and

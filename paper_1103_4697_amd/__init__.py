@@ -83,6 +83,8 @@ def lib():
                 "snc_gcd_z": (C.c_int, [VP, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv_plan": (C.c_int, [P(Upoly), P(Plan)]),
                 "snc_gcd_z_batch_plan": (C.c_int, [I32, P(Upoly), P(Upoly), P(Plan), P(Plan)]),
+                "snc_prepared_sqfree_plan": (C.c_int, [VP, P(Plan), P(Plan)]),
+                "snc_prepared_run_sqfree": (C.c_int, [VP, VP, SZ, VP, P(Upoly), P(Upoly)]),
                 "snc_gcd_z_batch": (C.c_int, [VP, I32, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
             }
@@ -338,6 +340,38 @@ class ResultantBatch:
             self.out[i].nlimbs = nl
         st = lib().snc_prepared_run(self.h, self.ctx.stream_handle(stream), self.out)
         self.ctx.check(st, "snc_prepared_run")
+
+    def run_sqfree(self, stream=None):
+        """Run the pipeline and gcd(R_i, R_i') in the same pass
+        (snc_prepared_run_sqfree): the resultants land in bufs/out as with
+        run(), the gcds in gbufs/gout (read them with sqfree_results)."""
+        import torch
+        if not hasattr(self, "gout"):
+            n = self.n
+            each = (Plan * n)()
+            total = Plan()
+            self.ctx.check(lib().snc_prepared_sqfree_plan(self.h, each, C.byref(total)), "snc_prepared_sqfree_plan")
+            self.gout = (Upoly * n)()
+            self.gbufs, self.gcaps = [], []
+            for i in range(n):
+                u, buf = _out_upoly(each[i].deg_bound, each[i].out_nlimbs, self.keep)
+                self.gout[i] = u
+                self.gbufs.append(buf)
+                self.gcaps.append((each[i].deg_bound, each[i].out_nlimbs))
+            self.gws = torch.empty(max(total.workspace_bytes, 256), dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        for i, (d, nl) in enumerate(self.caps):
+            self.out[i].deg = d
+            self.out[i].nlimbs = nl
+        for i, (d, nl) in enumerate(self.gcaps):
+            self.gout[i].deg = d
+            self.gout[i].nlimbs = nl
+        st = lib().snc_prepared_run_sqfree(self.h, C.c_void_p(self.gws.data_ptr()), C.c_size_t(self.gws.numel()),
+                                           self.ctx.stream_handle(stream), self.out, self.gout)
+        self.ctx.check(st, "snc_prepared_run_sqfree")
+
+    def sqfree_results(self):
+        return [_read_upoly(self.gout[i], self.gbufs[i]) for i in range(self.n)]
 
     def degrees(self):
         return [self.out[i].deg for i in range(self.n)]

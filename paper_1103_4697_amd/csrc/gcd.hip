@@ -608,7 +608,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     pack_rows(p.a, p.Q.da, p.Q.nl, h + p.coef);
     if (!p.Q.deriv) pack_rows(p.b, p.Q.db, p.Q.nl, h + p.coef + (size_t)(p.Q.da + 1) * p.Q.nl);
     GcdDesc& G = p.G;
-    G.da = p.Q.da; G.db = p.Q.db; G.nl = p.Q.nl; G.wl = p.wl; G.deriv = p.Q.deriv ? 1 : 0; G.pad = 0;
+    G.da = p.Q.da; G.db = p.Q.db; G.nl = p.Q.nl; G.wl = p.wl; G.deriv = p.Q.deriv ? 1 : 0; G.fused = 0; G.vals = nullptr; G.vstride = 0; G.d_off = 0;
     G.coef_off = (int64_t)p.coef; G.slot_prime_off = (int64_t)p.slot_prime;
     G.res_off = (int64_t)p.res; G.e_off = (int64_t)p.e; G.w_off = (int64_t)p.w; G.u_off = (int64_t)p.u;
     G.v_off = (int64_t)p.v;
@@ -865,6 +865,233 @@ static int gcd_plan(int n, const snc_upoly* a, const snc_upoly* b, bool deriv, s
   return SNC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Resultant and gcd(R, R') in one pass (the projection step, Section 2.1).
+// The interpolation leaves R mod p for the resultant's own primes; the
+// Euclid kernel runs on those residues (b = R' formed from them) on a second
+// stream while the Chinese remaindering runs, and reports e_p and the degree
+// d_p of R mod p.  A prime with d_p = deg R does not divide lc(R), so
+// e_p >= deg gcd(R, R'); e_p = 0 for one such prime proves that the gcd is
+// gcd(cont R, cont R').  The host computes the contents from R while the
+// Euclid runs.  Without such a prime the full modular gcd of R follows.
+// ---------------------------------------------------------------------------
+
+// sizes of the gcd(R, R') problem bounded by the resultant's bounds: |R_i| <= B, |R'_i| <= D B
+static void sqfree_bound(const ResPlan& P, Quick& Q) {
+  Q = Quick();
+  Q.deriv = true;
+  Q.da = P.trivial ? 0 : P.D;
+  Q.db = Q.da - 1;
+  Q.nla = Q.nlb = Q.nl = P.L;
+  Q.trivial = Q.da <= 0;
+  if (Q.trivial) { Q.deg_bound = 0; Q.out_nlimbs = P.L; return; }
+  const double lb = std::max(P.log2B, 0.0), ln = std::log2((double)P.D + 1.0), ld = std::log2((double)P.D);
+  Q.l2[0] = lb + 0.5 * ln; Q.l1[0] = lb + ln; Q.llc[0] = lb;
+  Q.l2[1] = Q.l2[0] + ld; Q.l1[1] = Q.l1[0] + ld; Q.llc[1] = lb + ld;
+  GcdInfo sz;
+  sz.da = Q.da; sz.db = Q.db;
+  sz.l2a = Q.l2[0]; sz.l1a = Q.l1[0]; sz.l2b = Q.l2[1]; sz.l1b = Q.l1[1];
+  sz.lbeta = std::min(Q.llc[0], Q.llc[1]);
+  Q.deg_bound = Q.db;
+  Q.out_nlimbs = std::max(P.L, (int)std::ceil((Q.deg_bound + std::min(Q.l2[0], Q.l2[1]) + 3.0) / 32.0) + 1);
+  double worst = 0.0;
+  for (int e : {0, Q.deg_bound}) worst = std::max(worst, bits_needed_full(sz, e));
+  Q.kmax = std::min(KMAX, std::max(primes_for_bits(worst), primes_for_bits(bits_needed_opt(sz))) + 12);
+  Q.target0 = std::min(Q.kmax, std::max(3, primes_for_bits(bits_needed_opt(sz)) + 2));
+}
+
+struct SqfreeLayout {
+  size_t descs = 0, items = 0, slotp = 0, e = 0, d = 0, fused = 0;  // words
+  size_t fallback_words = 0;                                         // full gcd of one R
+  std::vector<size_t> job_base;                                      // first e/d entry of each device job
+};
+
+static void sqfree_layout(const snc_prepared* pr, SqfreeLayout& S, std::vector<Quick>* bounds) {
+  const BatchLayout& lay = pr->lay;
+  size_t w = 0, nk = 0;
+  S.job_base.clear();
+  for (const ResJob& J : lay.jobs) { S.job_base.push_back(nk); nk += J.k; }
+  S.descs = w; w += align_words(sizeof(GcdDesc) / 4 * std::max<size_t>(lay.jobs.size(), 1));
+  S.items = w; w += align_words(2 * std::max<size_t>(nk, 1));
+  S.slotp = w; w += align_words(KMAX);
+  S.e = w; w += align_words(std::max<size_t>(nk, 1));
+  S.d = w; w += align_words(std::max<size_t>(nk, 1));
+  S.fused = w;
+  S.fallback_words = 0;
+  if (bounds) bounds->assign(pr->n, Quick());
+  for (int i = 0; i < pr->n; ++i) {
+    Quick Q;
+    sqfree_bound(pr->P[i], Q);
+    if (bounds) (*bounds)[i] = Q;
+    if (Q.trivial) continue;
+    std::vector<GcdProb> one(1);
+    one[0].Q = Q;
+    GcdBatchLayout L1;
+    layout_batch(one, L1);
+    S.fallback_words = std::max(S.fallback_words, L1.total);
+  }
+}
+
+int prepared_sqfree_plan(const snc_prepared* pr, snc_plan* each, snc_plan* total) {
+  SqfreeLayout S;
+  std::vector<Quick> B;
+  sqfree_layout(pr, S, &B);
+  for (int i = 0; i < pr->n; ++i) {
+    snc_plan pl{};
+    pl.deg_bound = std::max(B[i].deg_bound, 0);
+    pl.out_nlimbs = B[i].out_nlimbs;
+    pl.nprimes = B[i].trivial ? 0 : B[i].kmax;
+    if (each) each[i] = pl;
+    if (total) {
+      total->deg_bound = std::max(total->deg_bound, pl.deg_bound);
+      total->out_nlimbs = std::max(total->out_nlimbs, pl.out_nlimbs);
+    }
+  }
+  if (total) total->workspace_bytes = (S.fused + S.fallback_words) * 4;
+  return SNC_OK;
+}
+
+int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStream_t stream, snc_upoly* R,
+                        snc_upoly* Gout) {
+  snc_ctx* ctx = pr->c;
+  const int n = pr->n;
+  const BatchLayout& lay = pr->lay;
+  SqfreeLayout S;
+  std::vector<Quick> B;
+  sqfree_layout(pr, S, &B);
+  bool short_out = false;
+  for (int i = 0; i < n; ++i) {
+    const int need_deg = std::max(B[i].deg_bound, 0);
+    if (Gout[i].deg < need_deg || Gout[i].nlimbs < B[i].out_nlimbs || !Gout[i].limbs) {
+      Gout[i].deg = need_deg;
+      Gout[i].nlimbs = B[i].out_nlimbs;
+      short_out = true;
+    }
+  }
+  if (short_out) { ctx->err = "gcd output buffer too small"; return SNC_ERANGE; }
+  const size_t need = (S.fused + S.fallback_words) * 4;
+  if (!d_gws || gws_bytes < need) {
+    ctx->err = "gcd workspace of " + std::to_string(gws_bytes) + " bytes, need " + std::to_string(need);
+    return SNC_ENOMEM;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!ctx->side_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
+  uint32_t* gws = (uint32_t*)d_gws;
+  // host copy of the fused area: descriptors, work items by register class, slot -> prime
+  std::vector<uint32_t> hf(S.e, 0u);
+  GcdDesc* descs = (GcdDesc*)(hf.data() + S.descs);
+  int32_t* items = (int32_t*)(hf.data() + S.items);
+  int32_t* slotp = (int32_t*)(hf.data() + S.slotp);
+  for (int q = 0; q < KMAX; ++q) slotp[q] = q;
+  const int NJ = (int)lay.jobs.size();
+  for (int j = 0; j < NJ; ++j) {
+    const ResJob& J = lay.jobs[j];
+    GcdDesc& G = descs[j];
+    G = GcdDesc{};
+    G.da = J.D; G.db = J.D - 1; G.nl = 1; G.wl = J.D; G.deriv = 1; G.fused = 1;
+    G.vals = (const uint32_t*)pr->ws + J.val_off;
+    G.vstride = J.D + 1;
+    G.slot_prime_off = (int64_t)S.slotp;
+    G.e_off = (int64_t)(S.e + S.job_base[j]);
+    G.d_off = (int64_t)(S.d + S.job_base[j]);
+  }
+  struct Range { int cls, off, cnt, maxd; };
+  std::vector<Range> ranges;
+  int nitems = 0;
+  for (int cls : {2, 4, 6, 9, 12, 16, 24, 32, 0}) {
+    Range r{cls, nitems, 0, 0};
+    for (int j = 0; j < NJ; ++j) {
+      const ResJob& J = lay.jobs[j];
+      if (J.D < 1 || gcd_reg_slots(J.D) != cls) continue;
+      for (int q = 0; q < J.k; ++q) { items[2 * nitems] = j; items[2 * nitems + 1] = q; ++nitems; }
+      r.maxd = std::max(r.maxd, J.D);
+    }
+    r.cnt = nitems - r.off;
+    if (r.cnt) ranges.push_back(r);
+  }
+  const size_t e_words = S.fused - S.e;  // e and d arrays
+  if (ctx->stage_in(S.e * 4) || ctx->stage_out(e_words * 4)) {
+    ctx->err = "pinned staging allocation failed";
+    return SNC_EDEVICE;
+  }
+  std::memcpy(ctx->h_in, hf.data(), S.e * 4);
+  // with timing on: events around the Euclid launches on the side stream
+  const bool timing = ctx->timing;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (timing) {
+    ctx->stage_names.clear(); ctx->stage_ms.clear(); ctx->stage_launches.clear();
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+  }
+  auto mid = [&](hipStream_t side) -> int {
+    if (!side || !nitems) return SNC_OK;
+    HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, side));
+    const GcdDesc* descs_d = (const GcdDesc*)(gws + S.descs);
+    const int32_t* items_d = (const int32_t*)(gws + S.items);
+    if (timing) HIPCHK(hipEventRecord(t0, side));
+    for (const Range& r : ranges) launch_gcd_euclid(descs_d, items_d + 2 * r.off, r.cnt, r.cls, r.maxd, gws, side);
+    HIPCHK(hipGetLastError());
+    if (timing) HIPCHK(hipEventRecord(t1, side));
+    HIPCHK(hipMemcpyAsync(ctx->h_out, gws + S.e, e_words * 4, hipMemcpyDeviceToHost, side));
+    return SNC_OK;
+  };
+  int st = run_prepared_split(pr, stream, ctx->side_stream, mid, R);
+  if (st) return st;
+  // while the Euclid runs: big integers and contents of R and R'
+  std::vector<GcdProb> P(n);
+  for (int i = 0; i < n; ++i) {
+    int nla = 1;
+    st = parse_upoly(&R[i], P[i].A, nla, ctx->err);
+    if (st) return st;
+    derivative(P[i].A, P[i].B);
+    if (P[i].A.deg() >= 1) {
+      P[i].I.ca = content(P[i].A);
+      P[i].I.cb = content(P[i].B);
+      P[i].I.c = BigInt::gcd(P[i].I.ca, P[i].I.cb);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(ctx->side_stream));
+  if (timing) {
+    float ms = 0.f;
+    if (nitems) (void)hipEventElapsedTime(&ms, t0, t1);
+    ctx->stage_names.push_back("sqfree_euclid");
+    ctx->stage_ms.push_back(ms);
+    ctx->stage_launches.push_back(nitems);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+  }
+  std::vector<int32_t> ed((const int32_t*)ctx->h_out, (const int32_t*)ctx->h_out + e_words);
+  std::vector<int> job_of(n, -1);
+  for (int j = 0; j < NJ; ++j) job_of[lay.dev[j]] = j;
+  for (int i = 0; i < n; ++i) {
+    const int dR = P[i].A.deg();
+    const int j = job_of[i];
+    bool done = false;
+    if (j >= 0 && dR >= 1) {
+      const ResJob& J = lay.jobs[j];
+      const int32_t* e = ed.data() + S.job_base[j];
+      const int32_t* d = ed.data() + (S.d - S.e) + S.job_base[j];
+      for (int q = 0; q < J.k && !done; ++q) done = d[q] == dR && e[q] == 0;
+    }
+    if (done) {
+      UPoly G1;
+      G1.c = {P[i].I.c};
+      st = write_upoly(G1, &Gout[i], ctx->err);
+      if (st) return st;
+      continue;
+    }
+    // the full modular gcd of R (also the host-only cases: R zero or constant)
+    const int L = j >= 0 ? lay.jobs[j].L : 1;
+    std::vector<uint32_t> rl((size_t)std::max(dR + 1, 1) * L, 0u);
+    for (int t = 0; t <= dR; ++t)
+      if (!P[i].A.c[t].to_twos(rl.data() + (size_t)t * L, L)) { ctx->err = "resultant limbs"; return SNC_EINTERNAL; }
+    snc_upoly r1{rl.data(), dR, L};
+    st = gcd_run(ctx, 1, &r1, nullptr, true, gws + S.fused, gws_bytes - S.fused * 4, stream, &Gout[i]);
+    if (st) return st;
+  }
+  return SNC_OK;
+}
+
 }  // namespace snc
 
 using namespace snc;
@@ -893,6 +1120,18 @@ int snc_gcd_z_batch(snc_ctx* ctx, int32_t n, const snc_upoly* a, const snc_upoly
   if (!ctx || n < 0 || (n > 0 && (!a || !b || !out))) return SNC_EINVAL;
   if (n == 0) return SNC_OK;
   return gcd_run(ctx, n, a, b, false, d_ws, ws_bytes, (hipStream_t)stream, out);
+}
+
+int snc_prepared_sqfree_plan(const snc_prepared* prep, snc_plan* gcd_each, snc_plan* gcd_total) {
+  if (!prep || !gcd_total) return SNC_EINVAL;
+  *gcd_total = snc_plan{};
+  return prepared_sqfree_plan(prep, gcd_each, gcd_total);
+}
+
+int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, void* stream, snc_upoly* R,
+                            snc_upoly* G) {
+  if (!prep || !R || !G) return SNC_EINVAL;
+  return run_prepared_sqfree(prep, d_gws, gws_bytes, (hipStream_t)stream, R, G);
 }
 
 int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {

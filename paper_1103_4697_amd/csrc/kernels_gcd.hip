@@ -85,9 +85,16 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   const int T = G.da + G.db + 2;
   const uint32_t* ra = ws + G.res_off + (int64_t)slot * T;
   const uint32_t* rb = ra + G.da + 1;
-  for (int i = tid; i <= maxd; i += GCD_THREADS) {
-    P0[i] = i <= G.da ? ra[i] : 0u;
-    P1[i] = i <= G.db ? rb[i] : 0u;
+  if (G.fused) {  // given residues of a (plain), b = a'
+    const uint32_t* va = G.vals + (int64_t)slot * G.vstride;
+    for (int i = tid; i <= maxd; i += GCD_THREADS) P0[i] = i <= G.da ? to_mont(va[i], c) : 0u;
+    for (int i = tid; i <= maxd; i += GCD_THREADS)
+      P1[i] = i <= G.db ? mmulc(to_mont(va[i + 1], c), to_mont((uint32_t)(i + 1), c), c.p, c.pinv) : 0u;
+  } else {
+    for (int i = tid; i <= maxd; i += GCD_THREADS) {
+      P0[i] = i <= G.da ? ra[i] : 0u;
+      P1[i] = i <= G.db ? rb[i] : 0u;
+    }
   }
   __syncthreads();
   uint32_t* A = P0;
@@ -96,7 +103,8 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   while (dA >= 0 && A[dA] == 0) --dA;
   int dB = G.db;
   while (dB >= 0 && B[dB] == 0) --dB;
-  if (dA < G.da && dB < G.db) {
+  if (G.fused && tid == 0) ((int32_t*)(ws + G.d_off))[slot] = dA;
+  if (!G.fused && dA < G.da && dB < G.db) {
     if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = GCD_SLOT_UNUSABLE;
     return;
   }
@@ -118,9 +126,9 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
     --dA;
     while (dA >= 0 && A[dA] == 0) --dA;
   }
-  const int e = dA;  // gcd degree mod p (>= 0: the inputs are non-zero mod p)
+  const int e = dA;  // gcd degree mod p (>= 0 unless both operands vanish mod p)
   if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
-  if (e == 0) return;  // a usable prime with a constant gcd ends the problem on the host: no rows needed
+  if (e <= 0 || G.fused) return;  // a usable prime with a constant gcd ends the problem on the host: no rows needed
   const uint32_t inv = minv(A[e], c);
   for (int i = tid; i <= e; i += GCD_THREADS) Gm[i] = mmulc(A[i], inv, c.p, c.pinv);
   __syncthreads();
@@ -374,10 +382,26 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   const uint32_t* rb = ra + G.da + 1;
   extern __shared__ uint32_t sm[];  // 2 * 64 * E words
   uint32_t X[E], Y[E], Gm[E];
-  reg_load<E>(X, ra, G.da, lane);
-  reg_load<E>(Y, rb, G.db, lane);
+  if (G.fused) {  // given residues of a (plain), b = a': element i of b is (da - i) times element i of a
+    const uint32_t* va = G.vals + (int64_t)slot * G.vstride;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int i = lane * E + s;
+      X[s] = i <= G.da ? to_mont(va[G.da - i], c) : 0u;
+      Y[s] = i <= G.db ? mmulc(X[s], to_mont((uint32_t)(G.da - i), c), c.p, c.pinv) : 0u;
+    }
+  } else {
+    reg_load<E>(X, ra, G.da, lane);
+    reg_load<E>(Y, rb, G.db, lane);
+  }
   const int dX = reg_trim<E>(X, G.da, c);
   const int dY = reg_trim<E>(Y, G.db, c);
+  if (G.fused) {
+    if (lane == 0) ((int32_t*)(ws + G.d_off))[slot] = dX;
+    const int e = dX < 0 ? -1 : euclid_levels<E>(X, dX, Y, dY, sm, lane, c);
+    if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+    return;
+  }
   if (dX < G.da && dY < G.db) {
     if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = GCD_SLOT_UNUSABLE;
     return;

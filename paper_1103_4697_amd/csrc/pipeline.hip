@@ -3,6 +3,8 @@
 // the batched call (one captured HIP graph per batch shape, replayed).
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -35,6 +37,10 @@ void snc_ctx::release() {
   gexec = nullptr;
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   cap_stream = nullptr;
+  if (side_stream) (void)hipStreamDestroy(side_stream);
+  side_stream = nullptr;
+  if (ev_mid) (void)hipEventDestroy(ev_mid);
+  ev_mid = nullptr;
   for (auto e : events) (void)hipEventDestroy(e);
   events.clear();
   if (h_in) (void)hipHostFree(h_in);
@@ -161,13 +167,15 @@ struct StageTimer {
 };
 
 // Device launch sequence for a laid-out batch (everything after the upload).
-void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm) {
+// part: PIPE_ALL, PIPE_TO_INTERP (reduction .. interpolation) or PIPE_CRT
+void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part) {
   uint32_t* wsw = (uint32_t*)ws;
   const ResJob* jobs = (const ResJob*)(ws + lay.jobs_off);
   const RowDesc* rows = (const RowDesc*)(ws + lay.rows_off);
   const int NJ = (int)lay.jobs.size();
   uint32_t* abn_count = (uint32_t*)(ws + lay.abn_count_off);
   AbnEntry* abn_list = (AbnEntry*)(ws + lay.abn_list_off);
+  if (part != PIPE_CRT) {
   launch_zero_u32(abn_count, 1, s);
   launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, s);
   if (tm) tm->mark("reduce", 1);
@@ -190,6 +198,8 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   if (tm) tm->mark("elim_general", 1);
   launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, s);
   if (tm) tm->mark("interp", 1);
+  }
+  if (part == PIPE_TO_INTERP) return;
   const CrtTables tb = global_crt_tables();
   launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
   if (tm) tm->mark("crt_digits", 1);
@@ -350,13 +360,11 @@ int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly*
   return SNC_OK;
 }
 
-int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
-  snc_ctx* c = pr->c;
-  const int n = pr->n;
+// output sizes and the host-only (trivial) results; false with SNC_ERANGE sizes written back
+static bool prepared_outputs(snc_prepared* pr, snc_upoly* out) {
   const std::vector<ResPlan>& P = pr->P;
-  const BatchLayout& lay = pr->lay;
   bool range_err = false;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < pr->n; ++i) {
     const int need_deg = P[i].trivial ? (P[i].trivial_value ? 0 : -1) : P[i].D;
     const int need_nl = P[i].trivial ? 1 : P[i].L;
     if (out[i].deg < need_deg || out[i].nlimbs < need_nl || (need_deg >= 0 && !out[i].limbs)) {
@@ -365,8 +373,8 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
       range_err = true;
     }
   }
-  if (range_err) { c->err = "output buffer too small"; return SNC_ERANGE; }
-  for (int i = 0; i < n; ++i) {
+  if (range_err) { pr->c->err = "output buffer too small"; return false; }
+  for (int i = 0; i < pr->n; ++i) {
     if (!P[i].trivial) continue;
     if (P[i].trivial_value) {
       for (int l = 0; l < out[i].nlimbs; ++l) out[i].limbs[l] = l == 0 ? 1u : 0u;
@@ -375,32 +383,36 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
       out[i].deg = -1;
     }
   }
-  if (lay.dev.empty()) return SNC_OK;
-  HIPCHK(hipSetDevice(c->device));
-  uint8_t* ws = pr->ws;
-  StageTimer tm{c, stream, c->timing && !pr->use_graph};
-  tm.start();
-  if (pr->use_graph) {
-    if (!pr->gexec) {
-      if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-      hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      launch_pipeline(lay, ws, c->cap_stream, nullptr);
-      HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
-      hipError_t e = hipGraphInstantiate(&pr->gexec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) { pr->gexec = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
-    }
-    HIPCHK(hipGraphLaunch(pr->gexec, stream));
-    if (tm.on) tm.mark("pipeline", 1);
-  } else {
-    launch_pipeline(lay, ws, stream, tm.on ? &tm : nullptr);
+  return true;
+}
+
+// one part of the pipeline on `stream`, as a HIP graph captured on first use
+static int launch_prepared_part(snc_prepared* pr, hipStream_t stream, int part, StageTimer& tm) {
+  snc_ctx* c = pr->c;
+  if (!pr->use_graph) {
+    launch_pipeline(pr->lay, pr->ws, stream, tm.on ? &tm : nullptr, part);
+    HIPCHK(hipGetLastError());
+    return SNC_OK;
   }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(pr->h_out, ws + lay.out_off, lay.out_words * 4, hipMemcpyDeviceToHost, stream));
-  tm.mark("d2h", 1);
-  HIPCHK(hipStreamSynchronize(stream));
-  tm.finish();
+  hipGraphExec_t& gx = part == PIPE_ALL ? pr->gexec : part == PIPE_TO_INTERP ? pr->gexec_a : pr->gexec_b;
+  if (!gx) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    launch_pipeline(pr->lay, pr->ws, c->cap_stream, nullptr, part);
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { gx = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
+  }
+  HIPCHK(hipGraphLaunch(gx, stream));
+  if (tm.on) tm.mark(part == PIPE_CRT ? "pipeline_crt" : "pipeline", 1);
+  return SNC_OK;
+}
+
+// results from the staged output block into out
+static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
+  const BatchLayout& lay = pr->lay;
   const uint32_t* ho = (const uint32_t*)pr->h_out;
   const size_t base = lay.out_off / 4;
   for (int j = 0; j < (int)lay.dev.size(); ++j) {
@@ -420,6 +432,44 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
     }
     out[i].deg = deg;
   }
+}
+
+int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  if (!prepared_outputs(pr, out)) return SNC_ERANGE;
+  if (pr->lay.dev.empty()) return SNC_OK;
+  HIPCHK(hipSetDevice(c->device));
+  StageTimer tm{c, stream, c->timing && !pr->use_graph};
+  tm.start();
+  int st = launch_prepared_part(pr, stream, PIPE_ALL, tm);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, stream));
+  tm.mark("d2h", 1);
+  HIPCHK(hipStreamSynchronize(stream));
+  tm.finish();
+  prepared_collect(pr, out);
+  return SNC_OK;
+}
+
+int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
+                       const std::function<int(hipStream_t)>& mid, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  if (!prepared_outputs(pr, out)) return SNC_ERANGE;
+  HIPCHK(hipSetDevice(c->device));
+  if (pr->lay.dev.empty()) return mid(nullptr);
+  StageTimer tm{c, stream, false};
+  int st = launch_prepared_part(pr, stream, PIPE_TO_INTERP, tm);
+  if (st) return st;
+  if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->ev_mid, stream));
+  HIPCHK(hipStreamWaitEvent(side, c->ev_mid, 0));
+  st = mid(side);
+  if (st) return st;
+  st = launch_prepared_part(pr, stream, PIPE_CRT, tm);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  prepared_collect(pr, out);
   return SNC_OK;
 }
 
@@ -436,6 +486,8 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
 void destroy_prepared(snc_prepared* pr) {
   if (!pr) return;
   if (pr->gexec) (void)hipGraphExecDestroy(pr->gexec);
+  if (pr->gexec_a) (void)hipGraphExecDestroy(pr->gexec_a);
+  if (pr->gexec_b) (void)hipGraphExecDestroy(pr->gexec_b);
   if (pr->h_out) (void)hipHostFree(pr->h_out);
   delete pr;
 }

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,9 @@ struct snc_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<int64_t> gkey;
+  // second stream (default priority) and event for work beside the pipeline
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_mid = nullptr;
 
   int stage_in(size_t bytes);
   int stage_out(size_t bytes);
@@ -101,13 +105,20 @@ struct snc_prepared {
   snc::BatchLayout lay;
   uint8_t* ws = nullptr;
   void* h_out = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;    // whole pipeline
+  hipGraphExec_t gexec_a = nullptr;  // reduction .. interpolation
+  hipGraphExec_t gexec_b = nullptr;  // Chinese remaindering
 };
 
 namespace snc {
+enum { PIPE_ALL = 0, PIPE_TO_INTERP = 1, PIPE_CRT = 2 };
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
+// the pipeline with a hook after the interpolation: `side` waits for it and mid(side) enqueues work
+// there; returns with the results in out while the side stream may still run
+int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
+                       const std::function<int(hipStream_t)>& mid, snc_upoly* out);
 void destroy_prepared(snc_prepared* pr);
 int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                    size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph);

@@ -80,7 +80,11 @@ struct GcdDesc {
   int32_t nl;              // limbs per input coefficient
   int32_t wl;              // row length of w: min(da, db) + 1
   int32_t deriv;           // 1: b = a' (only a's limbs are stored; b's residues are formed from them)
-  int32_t pad;
+  int32_t fused;           // 1: a's residues are given (plain, vals[slot * vstride + i]), b = a'; only
+                           //    e and the degree of a mod p are written
+  const uint32_t* vals;    // fused: residues of a, coefficient i of slot s at vals[s * vstride + i]
+  int64_t vstride;
+  int64_t d_off;           // fused: int32 per slot, degree of a mod p
   int64_t coef_off;        // input limbs [(da+1)+(db+1)][nl], or [da+1][nl] when deriv (uint32 index)
   int64_t slot_prime_off;  // int32 per slot: index of its prime in the modulus table
   int64_t res_off;         // residues [slot][da+db+2] (Montgomery)

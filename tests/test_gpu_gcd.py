@@ -16,6 +16,7 @@ from oracle import zx
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+Q61 = (1 << 61) - 1
 
 
 @pytest.fixture(scope="module")
@@ -199,3 +200,49 @@ def test_batch_output_too_small(snc):
                                    ctx.stream_handle(), out)
     assert st == snc.SNC_ERANGE
     assert out[0].deg == each[0].deg_bound and out[0].nlimbs >= 1
+
+
+def _sq_pair(a, b):
+    """f = y - a(x), g = y - b(x): res_y(f, g) = a(x) - b(x) (formal degrees 1, 1)."""
+    n = max(len(a), len(b))
+    return ([[-c for c in a] + [0] * (n - len(a)), [1] + [0] * (n - 1)],
+            [[-c for c in b] + [0] * (n - len(b)), [1] + [0] * (n - 1)])
+
+
+def test_resultant_with_sqfree_gcd(snc):
+    """One pass for R = res_y(f, g) and gcd(R, R'): the fused check on the
+    resultant's primes (square-free R), the full gcd when R has a repeated
+    root, zero and constant resultants, and random pairs; R equal to the plain
+    run and G to the oracle."""
+    rng = random.Random(5)
+    pairs = []
+    for _ in range(4):
+        f = synth.dense_bivariate(np.random.default_rng(rng.randrange(1 << 30)), rng.randint(2, 6), bits=10)
+        g = synth.dense_bivariate(np.random.default_rng(rng.randrange(1 << 30)), rng.randint(2, 6), bits=10)
+        pairs.append((f, g))
+    d = zx.mul(zx.mul([-1, 1], [-1, 1]), [2, 1])            # (x - 1)^2 (x + 2): a repeated root
+    pairs.append(_sq_pair(zx.add([3, 0, 5], [c * 7 for c in d]), [3, 0, 5]))
+    h = [[1, 2], [3], [1]]                                     # common factor in y: R = 0
+    pairs.append((synth.bivariate_product(h, [[1, 1], [1]]), synth.bivariate_product(h, [[2], [1]])))
+    pairs.append(([[5]], [[7]]))                               # constants in y: R = 1
+    pairs.append(_sq_pair([4, 0, 0, 1], [4]))                  # R = -x^3 (a triple root at 0)
+    batch = snc.ResultantBatch(pairs)
+    for _ in range(2):                                         # graph capture, then replay
+        batch.run_sqfree()
+        R_all = batch.results()
+        G_all = batch.sqfree_results()
+        for (f, g), r, gg in zip(pairs, R_all, G_all):
+            assert r == snc.resultant_y(f, g)
+            assert gg == G.gcd_zx(r, zx.deriv(r))
+    assert R_all[5] == [] and G_all[5] == []
+
+
+def test_resultant_with_sqfree_gcd_curve_workload(snc):
+    ref = json.load(open(os.path.join(GOLDEN, "config1.json")))
+    f, g = synth.config1()
+    batch = snc.ResultantBatch([(f, g)])
+    batch.run_sqfree()
+    r = batch.results()[0]
+    assert len(r) - 1 == ref["degree"]
+    assert [c % Q61 for c in r] == ref["mod_2_61_minus_1"]
+    assert batch.sqfree_results()[0] == [int(c) for c in ref["gcd_r_rprime"]]
