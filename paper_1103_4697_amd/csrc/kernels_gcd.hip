@@ -168,7 +168,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
 // lc(Y) = 1 and the quotient coefficient as lc(X).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {  // lane l gets lane l+1 (0 for lane 63)
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
 }
 __device__ __forceinline__ uint32_t lead(uint32_t v0, uint32_t p) {
   return canon((uint32_t)__builtin_amdgcn_readfirstlane((int)v0), p);
@@ -251,10 +251,11 @@ __device__ __forceinline__ int reg_reduce(uint32_t (&X)[E], int dX, const uint32
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
-// Multipliers of the fused step from the canonical top pairs (p0, p1) of the
-// dividend and (q0, q1) of the divisor, computed on the vector unit with
-// lane 0's values (other lanes compute garbage that is never read) and then
-// made uniform: cheaper than the same Montgomery products on the scalar unit.
+// Multipliers of the fused step from the top pairs (p0, p1) of the dividend
+// and (q0, q1) of the divisor (p0, q0 canonical, p1, q1 below 4p), computed
+// on the vector unit with lane 0's values (other lanes compute garbage that
+// is never read) and then made uniform: cheaper than the same Montgomery
+// products on the scalar unit.
 __device__ __forceinline__ void step2_coefs(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1, uint32_t& a,
                                             uint32_t& b, uint32_t& cc, const PrimeC& c) {
   a = uni(mmulc(q0, q0, c.p, c.pinv));
@@ -272,8 +273,10 @@ template <int E>
 __device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (&Y)[E], int& dY, int dstop,
                                            const PrimeC& c) {
   if (dX != dY + 1 || dY < 1) return;
-  uint32_t x0 = canon(X[0], c.p), x1 = canon(X[1], c.p);
-  uint32_t y0 = canon(Y[0], c.p), y1 = canon(Y[1], c.p);
+  // leading coefficients canonical, second coefficients lazy: every product
+  // below pairs a canonical factor with one below 4p
+  uint32_t x0 = canon(X[0], c.p), x1 = X[1];
+  uint32_t y0 = canon(Y[0], c.p), y1 = Y[1];
   uint32_t a, b, cc;
   while (true) {
     step2_coefs(x0, x1, y0, y1, a, b, cc, c);
@@ -282,14 +285,14 @@ __device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (
     x0 = canon(X[0], c.p);
     if (uni(x0) == 0) { dX = reg_trim<E>(X, dX, c); return; }
     if (dX < 1 || dY < dstop) return;
-    x1 = canon(X[1], c.p);
+    x1 = X[1];
     step2_coefs(y0, y1, x0, x1, a, b, cc, c);
     reg_step2<E>(Y, X, a, b, cc, c);
     dY -= 2;
     y0 = canon(Y[0], c.p);
     if (uni(y0) == 0) { dY = reg_trim<E>(Y, dY, c); return; }
     if (dY < 1 || dX < dstop) return;
-    y1 = canon(Y[1], c.p);
+    y1 = Y[1];
   }
 }
 

@@ -474,7 +474,7 @@ void launch_ifact_init(hipStream_t s) {
 
 // lane L receives lane L-1 of v, lane 0 receives 0
 __device__ __forceinline__ uint32_t lane_shr1(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
 }
 
 __device__ __forceinline__ uint32_t bcast(uint32_t v, int lane) {
