@@ -1023,9 +1023,11 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
   }
+  // the work area goes up before the side stream starts waiting for the interpolation
+  if (nitems && !lay.dev.empty())
+    HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, ctx->side_stream));
   auto mid = [&](hipStream_t side) -> int {
     if (!side || !nitems) return SNC_OK;
-    HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, side));
     const GcdDesc* descs_d = (const GcdDesc*)(gws + S.descs);
     const int32_t* items_d = (const int32_t*)(gws + S.items);
     if (timing) HIPCHK(hipEventRecord(t0, side));
