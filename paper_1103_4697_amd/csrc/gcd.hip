@@ -122,6 +122,35 @@ BigInt content(const UPoly& P) {
   return BigInt::from_u64(gg);
 }
 
+// content of a polynomial given as two's-complement limbs: big-integer gcds
+// only while the running gcd exceeds one word, then each coefficient is
+// reduced straight from its limbs (x = U - 2^(32 n) when negative)
+BigInt content_limbs(const snc_upoly& a) {
+  const int nl = a.nlimbs;
+  BigInt g;
+  int i = 0;
+  for (; i <= a.deg; ++i) {
+    g = BigInt::gcd(g, BigInt::from_twos(a.limbs + (size_t)i * nl, nl));
+    if (g.mag.size() == 1) break;
+  }
+  if (g.mag.size() != 1) return g;
+  const uint32_t m = g.mag[0];
+  uint64_t gg = m;
+  std::vector<uint64_t> pw(nl + 1);
+  uint64_t v = 1;
+  for (int l = 0; l <= nl; ++l) { pw[l] = v; v = (v << 32) % m; }
+  for (++i; i <= a.deg && gg > 1; ++i) {
+    const uint32_t* c = a.limbs + (size_t)i * nl;
+    unsigned __int128 acc = 0;
+    for (int l = 0; l < nl; ++l) acc += (unsigned __int128)c[l] * pw[l];
+    uint64_t r = (uint64_t)(acc % m);
+    if (c[nl - 1] >> 31) r = (r + m - pw[nl]) % m;
+    r %= gg;  // gg divides m
+    while (r) { uint64_t t = gg % r; gg = r; r = t; }
+  }
+  return BigInt::from_u64(gg);
+}
+
 // log2 of the 2-norm and of the 1-norm (approximate, used only for sizing)
 void log2_norms(const UPoly& P, double& l2, double& l1) {
   double mx = -1e300;
@@ -868,8 +897,9 @@ static int gcd_plan(int n, const snc_upoly* a, const snc_upoly* b, bool deriv, s
 // ---------------------------------------------------------------------------
 // Resultant and gcd(R, R') in one pass (the projection step, Section 2.1).
 // The interpolation leaves R mod p for the resultant's own primes; the
-// Euclid kernel runs on those residues (b = R' formed from them) on a second
-// stream while the Chinese remaindering runs, and reports e_p and the degree
+// Euclid kernel runs on those residues (b = R' formed from them) right after
+// the interpolation while the Chinese remaindering runs on a second stream,
+// and reports e_p and the degree
 // d_p of R mod p.  A prime with d_p = deg R does not divide lc(R), so
 // e_p >= deg gcd(R, R'); e_p = 0 for one such prime proves that the gcd is
 // gcd(cont R, cont R').  The host computes the contents from R while the
@@ -1023,11 +1053,12 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
   }
-  // the work area goes up before the side stream starts waiting for the interpolation
-  if (nitems && !lay.dev.empty())
-    HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, ctx->side_stream));
-  auto mid = [&](hipStream_t side) -> int {
-    if (!side || !nitems) return SNC_OK;
+  // the work area goes up ahead of the pipeline
+  if (nitems && !lay.dev.empty()) HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, stream));
+  bool launched = false;
+  auto mid = [&](hipStream_t side, bool has_jobs) -> int {  // on the pipeline's stream, after the interpolation
+    if (!has_jobs || !nitems) return SNC_OK;
+    launched = true;
     const GcdDesc* descs_d = (const GcdDesc*)(gws + S.descs);
     const int32_t* items_d = (const int32_t*)(gws + S.items);
     if (timing) HIPCHK(hipEventRecord(t0, side));
@@ -1039,34 +1070,27 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
   };
   int st = run_prepared_split(pr, stream, ctx->side_stream, mid, R);
   if (st) return st;
-  // while the Euclid runs: big integers and contents of R and R'
-  std::vector<GcdProb> P(n);
-  for (int i = 0; i < n; ++i) {
-    int nla = 1;
-    st = parse_upoly(&R[i], P[i].A, nla, ctx->err);
-    if (st) return st;
-    derivative(P[i].A, P[i].B);
-    if (P[i].A.deg() >= 1) {
-      P[i].I.ca = content(P[i].A);
-      P[i].I.cb = content(P[i].B);
-      P[i].I.c = BigInt::gcd(P[i].I.ca, P[i].I.cb);
-    }
-  }
-  HIPCHK(hipStreamSynchronize(ctx->side_stream));
+  // while the Euclid runs: cont R, which is also gcd(cont R, cont R') since
+  // cont R divides every i R_i
+  std::vector<BigInt> cont(n);
+  for (int i = 0; i < n; ++i)
+    if (R[i].deg >= 1) cont[i] = content_limbs(R[i]);
+  HIPCHK(hipStreamSynchronize(stream));
   if (timing) {
     float ms = 0.f;
-    if (nitems) (void)hipEventElapsedTime(&ms, t0, t1);
+    if (launched) HIPCHK(hipEventElapsedTime(&ms, t0, t1));
     ctx->stage_names.push_back("sqfree_euclid");
     ctx->stage_ms.push_back(ms);
     ctx->stage_launches.push_back(nitems);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
   }
-  std::vector<int32_t> ed((const int32_t*)ctx->h_out, (const int32_t*)ctx->h_out + e_words);
+  std::vector<int32_t> ed(e_words, -1);
+  if (launched) ed.assign((const int32_t*)ctx->h_out, (const int32_t*)ctx->h_out + e_words);
   std::vector<int> job_of(n, -1);
   for (int j = 0; j < NJ; ++j) job_of[lay.dev[j]] = j;
   for (int i = 0; i < n; ++i) {
-    const int dR = P[i].A.deg();
+    const int dR = R[i].deg;
     const int j = job_of[i];
     bool done = false;
     if (j >= 0 && dR >= 1) {
@@ -1077,18 +1101,13 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     }
     if (done) {
       UPoly G1;
-      G1.c = {P[i].I.c};
+      G1.c = {cont[i]};
       st = write_upoly(G1, &Gout[i], ctx->err);
       if (st) return st;
       continue;
     }
     // the full modular gcd of R (also the host-only cases: R zero or constant)
-    const int L = j >= 0 ? lay.jobs[j].L : 1;
-    std::vector<uint32_t> rl((size_t)std::max(dR + 1, 1) * L, 0u);
-    for (int t = 0; t <= dR; ++t)
-      if (!P[i].A.c[t].to_twos(rl.data() + (size_t)t * L, L)) { ctx->err = "resultant limbs"; return SNC_EINTERNAL; }
-    snc_upoly r1{rl.data(), dR, L};
-    st = gcd_run(ctx, 1, &r1, nullptr, true, gws + S.fused, gws_bytes - S.fused * 4, stream, &Gout[i]);
+    st = gcd_run(ctx, 1, &R[i], nullptr, true, gws + S.fused, gws_bytes - S.fused * 4, stream, &Gout[i]);
     if (st) return st;
   }
   return SNC_OK;

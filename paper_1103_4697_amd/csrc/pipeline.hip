@@ -452,23 +452,26 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
 }
 
 int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
-                       const std::function<int(hipStream_t)>& mid, snc_upoly* out) {
+                       const std::function<int(hipStream_t, bool)>& mid, snc_upoly* out) {
   snc_ctx* c = pr->c;
   if (!prepared_outputs(pr, out)) return SNC_ERANGE;
   HIPCHK(hipSetDevice(c->device));
-  if (pr->lay.dev.empty()) return mid(nullptr);
+  if (pr->lay.dev.empty()) return mid(stream, false);
   StageTimer tm{c, stream, false};
   int st = launch_prepared_part(pr, stream, PIPE_TO_INTERP, tm);
   if (st) return st;
+  // the hook's work is queued on this stream right behind the interpolation,
+  // so it starts without a cross-stream wait; the Chinese remaindering and
+  // the download of the results go to the side stream
   if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming));
   HIPCHK(hipEventRecord(c->ev_mid, stream));
+  st = mid(stream, true);
+  if (st) return st;
   HIPCHK(hipStreamWaitEvent(side, c->ev_mid, 0));
-  st = mid(side);
+  st = launch_prepared_part(pr, side, PIPE_CRT, tm);
   if (st) return st;
-  st = launch_prepared_part(pr, stream, PIPE_CRT, tm);
-  if (st) return st;
-  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, side));
+  HIPCHK(hipStreamSynchronize(side));
   prepared_collect(pr, out);
   return SNC_OK;
 }

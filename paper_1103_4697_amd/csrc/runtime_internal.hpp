@@ -115,10 +115,12 @@ enum { PIPE_ALL = 0, PIPE_TO_INTERP = 1, PIPE_CRT = 2 };
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
-// the pipeline with a hook after the interpolation: `side` waits for it and mid(side) enqueues work
-// there; returns with the results in out while the side stream may still run
+// the pipeline with a hook after the interpolation: mid(stream, true) enqueues work that follows
+// the interpolation on `stream` while the Chinese remaindering and the download run on `side`
+// (mid(stream, false) when no pair needs device work); returns with the results in out while
+// `stream` may still run
 int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
-                       const std::function<int(hipStream_t)>& mid, snc_upoly* out);
+                       const std::function<int(hipStream_t, bool)>& mid, snc_upoly* out);
 void destroy_prepared(snc_prepared* pr);
 int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                    size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph);

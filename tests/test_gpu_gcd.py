@@ -226,6 +226,11 @@ def test_resultant_with_sqfree_gcd(snc):
     pairs.append((synth.bivariate_product(h, [[1, 1], [1]]), synth.bivariate_product(h, [[2], [1]])))
     pairs.append(([[5]], [[7]]))                               # constants in y: R = 1
     pairs.append(_sq_pair([4, 0, 0, 1], [4]))                  # R = -x^3 (a triple root at 0)
+    # contents: R scaled by 3^3 (one-word running gcd reduced from the limbs),
+    # and by 6^6 10^6 > 2^32 (a two-word content)
+    rg = np.random.default_rng(11)
+    pairs.append((3 * synth.dense_bivariate(rg, 4, bits=10), synth.dense_bivariate(rg, 3, bits=10)))
+    pairs.append((6 * synth.dense_bivariate(rg, 6, bits=8), 10 * synth.dense_bivariate(rg, 6, bits=8)))
     batch = snc.ResultantBatch(pairs)
     for _ in range(2):                                         # graph capture, then replay
         batch.run_sqfree()
