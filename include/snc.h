@@ -145,13 +145,16 @@ int snc_prepared_destroy(snc_prepared* prep);
  * curve analysis (Section 2.1) needs R = res_y(f, g) and gcd(R, R') (R / gcd
  * is the square-free part).  One run of the prepared pipeline computes both:
  * the modular Euclid of gcd(R, R') runs on R mod p for the resultant's own
- * primes, on a second stream beside the Chinese remaindering, and a prime not
+ * primes right after the interpolation, beside the Chinese remaindering
+ * (a second stream), and a prime not
  * dividing lc(R) with a constant gcd mod p proves gcd(R, R') = gcd(cont R,
- * cont R'); otherwise the full modular gcd of R follows (as snc_gcd_z_deriv).
+ * cont R') = cont R; otherwise the full modular gcd of R follows (as
+ * snc_gcd_z_deriv).  The Euclid's descriptors and outputs live in the
+ * prepared workspace (its size from snc_resultant_y_batch_plan includes them).
  * R: the n resultants (conventions of snc_prepared_run).  G: the n gcds
  * (conventions of snc_gcd_z), sized by snc_prepared_sqfree_plan (gcd_each:
  * per pair, or NULL), which also sizes d_gws, a second device workspace
- * (caller-owned, not retained) for the gcd work. */
+ * (caller-owned, not retained) for the full gcd when it is needed. */
 int snc_prepared_sqfree_plan(const snc_prepared* prep, snc_plan* gcd_each, snc_plan* gcd_total);
 int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, void* stream, snc_upoly* R,
                             snc_upoly* G);

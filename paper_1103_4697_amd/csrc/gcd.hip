@@ -977,7 +977,59 @@ int prepared_sqfree_plan(const snc_prepared* pr, snc_plan* each, snc_plan* total
       total->out_nlimbs = std::max(total->out_nlimbs, pl.out_nlimbs);
     }
   }
-  if (total) total->workspace_bytes = (S.fused + S.fallback_words) * 4;
+  if (total) total->workspace_bytes = std::max<size_t>(S.fallback_words * 4, 256);
+  return SNC_OK;
+}
+
+// descriptors, work items by register class and slot -> prime of the Euclid
+// on the resultant's primes, uploaded once into the prepared workspace (its
+// projection-step region), and the pinned buffer for e and d
+static int sqfree_setup(snc_prepared* pr, const SqfreeLayout& S, hipStream_t stream) {
+  snc_ctx* ctx = pr->c;
+  const BatchLayout& lay = pr->lay;
+  if (S.fused > lay.sq_words) { ctx->err = "projection-step region too small"; return SNC_EINTERNAL; }
+  const int64_t base = (int64_t)(lay.sq_off / 4);
+  std::vector<uint32_t> hf(S.e, 0u);
+  GcdDesc* descs = (GcdDesc*)(hf.data() + S.descs);
+  int32_t* items = (int32_t*)(hf.data() + S.items);
+  int32_t* slotp = (int32_t*)(hf.data() + S.slotp);
+  for (int q = 0; q < KMAX; ++q) slotp[q] = q;
+  const int NJ = (int)lay.jobs.size();
+  for (int j = 0; j < NJ; ++j) {
+    const ResJob& J = lay.jobs[j];
+    GcdDesc& G = descs[j];
+    G = GcdDesc{};
+    G.da = J.D; G.db = J.D - 1; G.nl = 1; G.wl = J.D; G.deriv = 1; G.fused = 1;
+    G.vals = (const uint32_t*)pr->ws + J.val_off;
+    G.vstride = J.D + 1;
+    G.slot_prime_off = base + (int64_t)S.slotp;
+    G.e_off = base + (int64_t)(S.e + S.job_base[j]);
+    G.d_off = base + (int64_t)(S.d + S.job_base[j]);
+  }
+  pr->sq_ranges.clear();
+  int nitems = 0;
+  for (int cls : {2, 4, 6, 9, 12, 16, 24, 32, 0}) {
+    const int off = nitems;
+    int maxd = 0;
+    for (int j = 0; j < NJ; ++j) {
+      const ResJob& J = lay.jobs[j];
+      if (J.D < 1 || gcd_reg_slots(J.D) != cls) continue;
+      for (int q = 0; q < J.k; ++q) { items[2 * nitems] = j; items[2 * nitems + 1] = q; ++nitems; }
+      maxd = std::max(maxd, J.D);
+    }
+    if (nitems > off) pr->sq_ranges.insert(pr->sq_ranges.end(), {cls, off, nitems - off, maxd});
+  }
+  const size_t e_words = S.fused - S.e;
+  if (!pr->h_ed && hipHostMalloc(&pr->h_ed, std::max<size_t>(e_words * 4, 4), hipHostMallocDefault) != hipSuccess) {
+    pr->h_ed = nullptr;
+    ctx->err = "pinned staging allocation failed";
+    return SNC_EDEVICE;
+  }
+  if (ctx->stage_in(S.e * 4)) { ctx->err = "pinned staging allocation failed"; return SNC_EDEVICE; }
+  std::memcpy(ctx->h_in, hf.data(), S.e * 4);
+  HIPCHK(hipMemcpyAsync(pr->ws + lay.sq_off, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  pr->sq_ready = true;
   return SNC_OK;
 }
 
@@ -999,53 +1051,23 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     }
   }
   if (short_out) { ctx->err = "gcd output buffer too small"; return SNC_ERANGE; }
-  const size_t need = (S.fused + S.fallback_words) * 4;
+  const size_t need = std::max<size_t>(S.fallback_words * 4, 256);
   if (!d_gws || gws_bytes < need) {
     ctx->err = "gcd workspace of " + std::to_string(gws_bytes) + " bytes, need " + std::to_string(need);
     return SNC_ENOMEM;
   }
   HIPCHK(hipSetDevice(ctx->device));
-  if (!ctx->side_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
   uint32_t* gws = (uint32_t*)d_gws;
-  // host copy of the fused area: descriptors, work items by register class, slot -> prime
-  std::vector<uint32_t> hf(S.e, 0u);
-  GcdDesc* descs = (GcdDesc*)(hf.data() + S.descs);
-  int32_t* items = (int32_t*)(hf.data() + S.items);
-  int32_t* slotp = (int32_t*)(hf.data() + S.slotp);
-  for (int q = 0; q < KMAX; ++q) slotp[q] = q;
-  const int NJ = (int)lay.jobs.size();
-  for (int j = 0; j < NJ; ++j) {
-    const ResJob& J = lay.jobs[j];
-    GcdDesc& G = descs[j];
-    G = GcdDesc{};
-    G.da = J.D; G.db = J.D - 1; G.nl = 1; G.wl = J.D; G.deriv = 1; G.fused = 1;
-    G.vals = (const uint32_t*)pr->ws + J.val_off;
-    G.vstride = J.D + 1;
-    G.slot_prime_off = (int64_t)S.slotp;
-    G.e_off = (int64_t)(S.e + S.job_base[j]);
-    G.d_off = (int64_t)(S.d + S.job_base[j]);
-  }
-  struct Range { int cls, off, cnt, maxd; };
-  std::vector<Range> ranges;
-  int nitems = 0;
-  for (int cls : {2, 4, 6, 9, 12, 16, 24, 32, 0}) {
-    Range r{cls, nitems, 0, 0};
-    for (int j = 0; j < NJ; ++j) {
-      const ResJob& J = lay.jobs[j];
-      if (J.D < 1 || gcd_reg_slots(J.D) != cls) continue;
-      for (int q = 0; q < J.k; ++q) { items[2 * nitems] = j; items[2 * nitems + 1] = q; ++nitems; }
-      r.maxd = std::max(r.maxd, J.D);
-    }
-    r.cnt = nitems - r.off;
-    if (r.cnt) ranges.push_back(r);
+  if (!lay.dev.empty() && !pr->sq_ready) {
+    const int st = sqfree_setup(pr, S, stream);
+    if (st) return st;
   }
   const size_t e_words = S.fused - S.e;  // e and d arrays
-  if (ctx->stage_in(S.e * 4) || ctx->stage_out(e_words * 4)) {
-    ctx->err = "pinned staging allocation failed";
-    return SNC_EDEVICE;
-  }
-  std::memcpy(ctx->h_in, hf.data(), S.e * 4);
-  // with timing on: events around the Euclid launches on the side stream
+  uint32_t* ws = (uint32_t*)pr->ws;
+  const int64_t base = (int64_t)(lay.sq_off / 4);
+  int nitems = 0;
+  for (size_t r = 0; r < pr->sq_ranges.size(); r += 4) nitems += pr->sq_ranges[r + 2];
+  // with timing on: events around the Euclid launches
   const bool timing = ctx->timing;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
@@ -1053,50 +1075,50 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
   }
-  // the work area goes up ahead of the pipeline
-  if (nitems && !lay.dev.empty()) HIPCHK(hipMemcpyAsync(gws, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, stream));
-  bool launched = false;
-  auto mid = [&](hipStream_t side, bool has_jobs) -> int {  // on the pipeline's stream, after the interpolation
-    if (!has_jobs || !nitems) return SNC_OK;
-    launched = true;
-    const GcdDesc* descs_d = (const GcdDesc*)(gws + S.descs);
-    const int32_t* items_d = (const int32_t*)(gws + S.items);
-    if (timing) HIPCHK(hipEventRecord(t0, side));
-    for (const Range& r : ranges) launch_gcd_euclid(descs_d, items_d + 2 * r.off, r.cnt, r.cls, r.maxd, gws, side);
+  // the Euclid and the download of e and d, following the interpolation
+  auto euclid = [&](hipStream_t s) -> int {
+    if (!nitems) return SNC_OK;
+    const GcdDesc* descs_d = (const GcdDesc*)(ws + base + S.descs);
+    const int32_t* items_d = (const int32_t*)(ws + base + S.items);
+    if (timing) HIPCHK(hipEventRecord(t0, s));
+    for (size_t r = 0; r < pr->sq_ranges.size(); r += 4) {
+      const int* q = &pr->sq_ranges[r];
+      launch_gcd_euclid(descs_d, items_d + 2 * q[1], q[2], q[0], q[3], ws, s);
+    }
     HIPCHK(hipGetLastError());
-    if (timing) HIPCHK(hipEventRecord(t1, side));
-    HIPCHK(hipMemcpyAsync(ctx->h_out, gws + S.e, e_words * 4, hipMemcpyDeviceToHost, side));
+    if (timing) HIPCHK(hipEventRecord(t1, s));
+    HIPCHK(hipMemcpyAsync(pr->h_ed, ws + base + S.e, e_words * 4, hipMemcpyDeviceToHost, s));
     return SNC_OK;
   };
-  int st = run_prepared_split(pr, stream, ctx->side_stream, mid, R);
-  if (st) return st;
   // while the Euclid runs: cont R, which is also gcd(cont R, cont R') since
   // cont R divides every i R_i
   std::vector<BigInt> cont(n);
-  for (int i = 0; i < n; ++i)
-    if (R[i].deg >= 1) cont[i] = content_limbs(R[i]);
-  HIPCHK(hipStreamSynchronize(stream));
+  auto contents = [&]() {
+    for (int i = 0; i < n; ++i)
+      if (R[i].deg >= 1) cont[i] = content_limbs(R[i]);
+  };
+  int st = run_prepared_fork(pr, stream, euclid, contents, R);
+  if (st) return st;
   if (timing) {
     float ms = 0.f;
-    if (launched) HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    if (nitems && !lay.dev.empty()) HIPCHK(hipEventElapsedTime(&ms, t0, t1));
     ctx->stage_names.push_back("sqfree_euclid");
     ctx->stage_ms.push_back(ms);
     ctx->stage_launches.push_back(nitems);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
   }
-  std::vector<int32_t> ed(e_words, -1);
-  if (launched) ed.assign((const int32_t*)ctx->h_out, (const int32_t*)ctx->h_out + e_words);
+  const int32_t* ed = (const int32_t*)pr->h_ed;
   std::vector<int> job_of(n, -1);
-  for (int j = 0; j < NJ; ++j) job_of[lay.dev[j]] = j;
+  for (int j = 0; j < (int)lay.dev.size(); ++j) job_of[lay.dev[j]] = j;
   for (int i = 0; i < n; ++i) {
     const int dR = R[i].deg;
     const int j = job_of[i];
     bool done = false;
-    if (j >= 0 && dR >= 1) {
+    if (j >= 0 && dR >= 1 && nitems) {
       const ResJob& J = lay.jobs[j];
-      const int32_t* e = ed.data() + S.job_base[j];
-      const int32_t* d = ed.data() + (S.d - S.e) + S.job_base[j];
+      const int32_t* e = ed + S.job_base[j];
+      const int32_t* d = ed + (S.d - S.e) + S.job_base[j];
       for (int q = 0; q < J.k && !done; ++q) done = d[q] == dR && e[q] == 0;
     }
     if (done) {
@@ -1107,7 +1129,7 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
       continue;
     }
     // the full modular gcd of R (also the host-only cases: R zero or constant)
-    st = gcd_run(ctx, 1, &R[i], nullptr, true, gws + S.fused, gws_bytes - S.fused * 4, stream, &Gout[i]);
+    st = gcd_run(ctx, 1, &R[i], nullptr, true, gws, gws_bytes, stream, &Gout[i]);
     if (st) return st;
   }
   return SNC_OK;

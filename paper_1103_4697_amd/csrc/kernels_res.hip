@@ -66,8 +66,9 @@ constexpr int RED_THREADS = 256;
 
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const ResJob* jobs, const int64_t* prefix,
                                                         int njobs, const uint32_t* ws,
-                                                        uint32_t* wsw) {
+                                                        uint32_t* wsw, uint32_t* zero_word) {
   const int64_t b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0 && zero_word) *zero_word = 0u;  // the abnormal-instance counter
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
   const int nb = (J.T + RED_THREADS - 1) / RED_THREADS;
@@ -89,10 +90,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const ResJob* jobs, cons
 }
 
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
-                   const uint32_t* ws, uint32_t* res_base, hipStream_t s) {
-  if (nblocks <= 0) return;
+                   const uint32_t* ws, uint32_t* res_base, uint32_t* zero_word, hipStream_t s) {
+  if (nblocks <= 0) {
+    if (zero_word) launch_zero_u32(zero_word, 1, s);
+    return;
+  }
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)nblocks), dim3(RED_THREADS), 0, s, jobs_d,
-                     blk_prefix_d, njobs, ws, res_base);
+                     blk_prefix_d, njobs, ws, res_base, zero_word);
 }
 
 // ---------------------------------------------------------------------------

@@ -130,6 +130,12 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   }
   lay.out_words = ow;
   w += align_words(ow);
+  size_t nk = 0;
+  for (const ResJob& J : lay.jobs) nk += J.k;
+  lay.sq_off = w * 4;
+  lay.sq_words = align_words(sizeof(GcdDesc) / 4 * std::max<size_t>(NJ, 1)) + align_words(2 * std::max<size_t>(nk, 1)) +
+                 align_words(KMAX) + 2 * align_words(std::max<size_t>(nk, 1));
+  w += lay.sq_words;
   lay.total_bytes = w * 4;
 }
 
@@ -176,8 +182,7 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   uint32_t* abn_count = (uint32_t*)(ws + lay.abn_count_off);
   AbnEntry* abn_list = (AbnEntry*)(ws + lay.abn_list_off);
   if (part != PIPE_CRT) {
-  launch_zero_u32(abn_count, 1, s);
-  launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, s);
+  launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, abn_count, s);
   if (tm) tm->mark("reduce", 1);
   int nee = 0;
   for (int c = 0; c < NCLS; ++c) {
@@ -451,28 +456,32 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   return SNC_OK;
 }
 
-int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
-                       const std::function<int(hipStream_t, bool)>& mid, snc_upoly* out) {
+int run_prepared_fork(snc_prepared* pr, hipStream_t stream, const std::function<int(hipStream_t)>& branch,
+                      const std::function<void()>& on_results, snc_upoly* out) {
   snc_ctx* c = pr->c;
   if (!prepared_outputs(pr, out)) return SNC_ERANGE;
+  if (pr->lay.dev.empty()) { on_results(); return SNC_OK; }
   HIPCHK(hipSetDevice(c->device));
-  if (pr->lay.dev.empty()) return mid(stream, false);
+  if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+  if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming));
   StageTimer tm{c, stream, false};
   int st = launch_prepared_part(pr, stream, PIPE_TO_INTERP, tm);
   if (st) return st;
-  // the hook's work is queued on this stream right behind the interpolation,
-  // so it starts without a cross-stream wait; the Chinese remaindering and
-  // the download of the results go to the side stream
-  if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming));
+  // the branch is queued on this stream right behind the interpolation, so
+  // it starts without a cross-stream wait; the Chinese remaindering and the
+  // download of the results go to the side stream
   HIPCHK(hipEventRecord(c->ev_mid, stream));
-  st = mid(stream, true);
+  st = branch(stream);
   if (st) return st;
-  HIPCHK(hipStreamWaitEvent(side, c->ev_mid, 0));
-  st = launch_prepared_part(pr, side, PIPE_CRT, tm);
+  HIPCHK(hipStreamWaitEvent(c->side_stream, c->ev_mid, 0));
+  st = launch_prepared_part(pr, c->side_stream, PIPE_CRT, tm);
   if (st) return st;
-  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, side));
-  HIPCHK(hipStreamSynchronize(side));
+  HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost,
+                        c->side_stream));
+  HIPCHK(hipStreamSynchronize(c->side_stream));
   prepared_collect(pr, out);
+  on_results();
+  HIPCHK(hipStreamSynchronize(stream));
   return SNC_OK;
 }
 
@@ -492,6 +501,7 @@ void destroy_prepared(snc_prepared* pr) {
   if (pr->gexec_a) (void)hipGraphExecDestroy(pr->gexec_a);
   if (pr->gexec_b) (void)hipGraphExecDestroy(pr->gexec_b);
   if (pr->h_out) (void)hipHostFree(pr->h_out);
+  if (pr->h_ed) (void)hipHostFree(pr->h_ed);
   delete pr;
 }
 

@@ -53,6 +53,7 @@ struct BatchLayout {
   size_t abn_count_off = 0, abn_list_off = 0;              // bytes
   uint32_t abn_cap = 0;
   size_t out_off = 0, out_words = 0;                       // bytes / words
+  size_t sq_off = 0, sq_words = 0;  // bytes / words: gcd(R, R') descriptors, work items, e and d
   size_t total_bytes = 0;
   int64_t nb_red = 0, nb_interp = 0, nb_crtd = 0, nb_crtc = 0, n_gen_inst = 0;
   int64_t nb_ee[NCLS] = {0};
@@ -108,6 +109,11 @@ struct snc_prepared {
   hipGraphExec_t gexec = nullptr;    // whole pipeline
   hipGraphExec_t gexec_a = nullptr;  // reduction .. interpolation
   hipGraphExec_t gexec_b = nullptr;  // Chinese remaindering
+  // projection step (resultant and gcd(R, R')): the Euclid descriptors are
+  // uploaded into the workspace on the first run
+  void* h_ed = nullptr;              // pinned download of e and d
+  bool sq_ready = false;
+  std::vector<int> sq_ranges;        // (register class, first item, items, largest degree) per launch
 };
 
 namespace snc {
@@ -115,12 +121,13 @@ enum { PIPE_ALL = 0, PIPE_TO_INTERP = 1, PIPE_CRT = 2 };
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
-// the pipeline with a hook after the interpolation: mid(stream, true) enqueues work that follows
-// the interpolation on `stream` while the Chinese remaindering and the download run on `side`
-// (mid(stream, false) when no pair needs device work); returns with the results in out while
-// `stream` may still run
-int run_prepared_split(snc_prepared* pr, hipStream_t stream, hipStream_t side,
-                       const std::function<int(hipStream_t, bool)>& mid, snc_upoly* out);
+// the pipeline with a second branch after the interpolation: branch(stream)
+// enqueues work that follows the interpolation on `stream` while the Chinese
+// remaindering and the download of the results run on the side stream;
+// on_results() runs on the host once the results are in out, while the
+// branch may still run; returns with all work complete.
+int run_prepared_fork(snc_prepared* pr, hipStream_t stream, const std::function<int(hipStream_t)>& branch,
+                      const std::function<void()>& on_results, snc_upoly* out);
 void destroy_prepared(snc_prepared* pr);
 int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                    size_t ws_bytes, hipStream_t stream, snc_upoly* out, bool use_graph);

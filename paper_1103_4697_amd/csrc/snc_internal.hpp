@@ -111,8 +111,9 @@ hipError_t configure_kernels();
 void launch_ifact_init(hipStream_t s);
 size_t interp_lds_bytes(int max_D);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+// zero_word (may be null) is set to zero by the same launch
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
-                   const uint32_t* ws, uint32_t* res_base, hipStream_t s);
+                   const uint32_t* ws, uint32_t* res_base, uint32_t* zero_word, hipStream_t s);
 void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
                       const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
