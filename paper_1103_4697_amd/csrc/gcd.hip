@@ -1099,18 +1099,16 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
   };
   int st = run_prepared_fork(pr, stream, euclid, contents, R);
   if (st) return st;
+  float euclid_ms = 0.f;
   if (timing) {
-    float ms = 0.f;
-    if (nitems && !lay.dev.empty()) HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    ctx->stage_names.push_back("sqfree_euclid");
-    ctx->stage_ms.push_back(ms);
-    ctx->stage_launches.push_back(nitems);
+    if (nitems && !lay.dev.empty()) HIPCHK(hipEventElapsedTime(&euclid_ms, t0, t1));
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
   }
   const int32_t* ed = (const int32_t*)pr->h_ed;
   std::vector<int> job_of(n, -1);
   for (int j = 0; j < (int)lay.dev.size(); ++j) job_of[lay.dev[j]] = j;
+  int full = 0;
   for (int i = 0; i < n; ++i) {
     const int dR = R[i].deg;
     const int j = job_of[i];
@@ -1131,6 +1129,16 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     // the full modular gcd of R (also the host-only cases: R zero or constant)
     st = gcd_run(ctx, 1, &R[i], nullptr, true, gws, gws_bytes, stream, &Gout[i]);
     if (st) return st;
+    if (dR >= 1) ++full;
+  }
+  if (timing) {  // the Euclid on the resultant's primes, and the pairs that needed the full gcd
+    if (!full) { ctx->stage_names.clear(); ctx->stage_ms.clear(); ctx->stage_launches.clear(); }
+    ctx->stage_names.push_back("sqfree_euclid");
+    ctx->stage_ms.push_back(euclid_ms);
+    ctx->stage_launches.push_back(nitems);
+    ctx->stage_names.push_back("sqfree_full_gcd");
+    ctx->stage_ms.push_back(0.f);
+    ctx->stage_launches.push_back(full);
   }
   return SNC_OK;
 }

@@ -259,8 +259,9 @@ __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin
 __device__ __forceinline__ void step2_coefs(uint32_t p0, uint32_t p1, uint32_t q0, uint32_t q1, uint32_t& a,
                                             uint32_t& b, uint32_t& cc, const PrimeC& c) {
   a = uni(mmulc(q0, q0, c.p, c.pinv));
-  b = uni(c.p - mmulc(q0, p0, c.p, c.pinv));  // -q0 p0, in (0, p]
-  cc = uni(msub(mmulc(p0, q1, c.p, c.pinv), mmulc(q0, p1, c.p, c.pinv), c.p));
+  b = uni(mmulc(q0, c.p - p0, c.p, c.pinv));  // -q0 p0 (p - p0 in (0, p])
+  // p0 q1 - q0 p1 with one reduction: the sum stays below 8 p^2, its reduction below 3p
+  cc = uni(canon(redc((uint64_t)p0 * q1 + (uint64_t)(c.p - q0) * p1, c.p, c.pinv), c.p));
 }
 
 // Runs of normal remainder steps (each remainder one degree below its

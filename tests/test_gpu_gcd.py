@@ -251,3 +251,60 @@ def test_resultant_with_sqfree_gcd_curve_workload(snc):
     assert len(r) - 1 == ref["degree"]
     assert [c % Q61 for c in r] == ref["mod_2_61_minus_1"]
     assert batch.sqfree_results()[0] == [int(c) for c in ref["gcd_r_rprime"]]
+
+
+def _gcd_mod_p(a, b, p):
+    """Monic gcd of two integer polynomials (coefficient lists, constant
+    first) reduced mod p, by the plain Euclidean algorithm."""
+    def trim(v):
+        v = [c % p for c in v]
+        while v and v[-1] == 0:
+            v.pop()
+        return v
+    a, b = trim(a), trim(b)
+    while b:
+        inv = pow(b[-1], p - 2, p)
+        while len(a) >= len(b):
+            q = a[-1] * inv % p
+            s = len(a) - len(b)
+            for i, c in enumerate(b):
+                a[s + i] = (a[s + i] - q * c) % p
+            a = trim(a)
+        a, b = b, a
+    inv = pow(a[-1], p - 2, p)
+    return [c * inv % p for c in a]
+
+
+def test_sqfree_check_large_degree(snc):
+    """The fused check at degree 420 and above: R = w (square-free,
+    primitive), 6 w (content 6), u^2 w (repeated factor u) for a random w of
+    degree 420: gcd(R, R') is 1, 6 and u by construction once w is square-free
+    and coprime to u, which is checked mod a prime.  The fast path must settle
+    the two square-free cases (no full gcd), and the gcds must equal the plain
+    modular gcd of R and R'."""
+    rng = random.Random(23)
+    p = 1000003
+    u = [-7, 3, 1]
+    while True:
+        w = [rng.randint(-60, 60) for _ in range(420)] + [1]
+        if _gcd_mod_p(w, zx.deriv(w), p) == [1] and _gcd_mod_p(w, u, p) == [1]:
+            break
+    cases = [(w, [1]), ([6 * c for c in w], [6]), (zx.mul(zx.mul(u, u), w), u)]
+    pairs = [_sq_pair(r, [0]) for r, _ in cases]
+    batch = snc.ResultantBatch(pairs)
+    ctx = batch.ctx
+    ctx.set_timing(True)
+    try:
+        batch.run_sqfree()
+        stages = {name: launches for name, _, launches in ctx.timing()}
+    finally:
+        ctx.set_timing(False)
+    R_all, G_all = batch.results(), batch.sqfree_results()
+    for (r, g), rr, gg in zip(cases, R_all, G_all):
+        assert rr in (r, [-c for c in r])
+        assert gg == g
+        assert gg == snc.gcd_z_deriv(rr)
+    assert stages["sqfree_full_gcd"] == 1          # only u^2 w needs the full gcd
+    assert stages["sqfree_euclid"] > 0              # (pair, prime) items of the fused check
+    batch.run_sqfree()                             # replay of the captured pipeline
+    assert batch.sqfree_results() == G_all
