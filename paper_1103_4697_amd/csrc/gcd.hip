@@ -577,6 +577,8 @@ static BigInt stage_crt(GcdProb& p, const std::vector<int32_t>& sel, int emin, c
     jb[t].val_off = (int64_t)vals[t];
     jb[t].dig_off = (int64_t)(p.dig + t * p.nmax * ks);
     jb[t].acc_off = 0;
+    jb[t].pts_off = 0;
+    jb[t].nq_off = 0;
     jb[t].out_off = (int64_t)(p.outw + t * p.nmax * p.lg);
     pd[t + 1] = pd[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;

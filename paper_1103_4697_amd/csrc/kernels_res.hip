@@ -281,7 +281,7 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   res = mmulc(res, minv(den, c), c.p, c.pinv);
   if (sg) res = mneg(res, c.p);
   if (!live) return;
-  ws[J.val_off + (int64_t)pi * (J.D + 1) + j] = ok ? res : 0u;
+  ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] = ok ? res : 0u;
   if (!ok) {
     uint32_t idx = atomicAdd(abn_count, 1u);
     if (idx < abn_cap) abn_list[idx] = AbnEntry{jid, pi, j, 0};
@@ -389,7 +389,7 @@ __device__ void general_instance(const ResJob& J, const RowDesc* rows, uint32_t*
   for (int t = 0; t <= J.n; ++t) G[J.n - t] = canon(horner_grouped(r, rb[t / ROWGRP], t % ROWGRP, X, c), c.p);
   uint32_t res = res_general(F, J.m, G, J.n, c);
   if (J.sign) res = mneg(res, c.p);
-  ws[J.val_off + (int64_t)pi * (J.D + 1) + j] = res;
+  ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] = res;
 }
 
 __global__ void k_elim_general(const ResJob* jobs, const RowDesc* rows, uint32_t* ws,
@@ -472,8 +472,11 @@ __global__ void k_ifact_init() {
   row[0] = inv;
 }
 
+void launch_ffact_init(hipStream_t s);
+
 void launch_ifact_init(hipStream_t s) {
   hipLaunchKernelGGL(k_ifact_init, dim3(KMAX / 64), dim3(64), 0, s);
+  launch_ffact_init(s);
 }
 
 // lane L receives lane L-1 of v, lane 0 receives 0
@@ -509,7 +512,8 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
   const int n1 = J.D + 1;
   const int nblk = (n1 + IB - 1) / IB;
   const int Dp = nblk * IB;
-  uint32_t* V = ws + J.val_off + (int64_t)pi * n1;
+  const uint32_t* V = ws + J.pts_off + (int64_t)pi * n1;  // values at the points
+  uint32_t* C = ws + J.val_off + (int64_t)pi * n1;        // coefficients
   const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
   uint32_t* Wp = sm;             // [IPAD + Dp]: zeros, then w_j = (-1)^j / j!; later a P buffer
   uint32_t* Qb = Wp + IPAD + Dp; // [Dp]: Q_j at 64j
@@ -585,7 +589,144 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
     uint32_t* tmp = Pa; Pa = Pb; Pb = tmp;
     dP = dN;
   }
-  for (int t = tid; t < n1; t += INTERP_THREADS) V[t] = from_mont(Pa[IPAD + t], c);
+  for (int t = tid; t < n1; t += INTERP_THREADS) C[t] = from_mont(Pa[IPAD + t], c);
+}
+
+// ---------------------------------------------------------------------------
+// Block-parallel interpolation (degree bounds below 64 IFF_J).
+//   With G_j = x (x-1) ... (x - 64j + 1) the Newton form is P = sum_j G_j Q_j
+//   (Q_j as above), so the blocks of 64 coefficients of P are independent
+//   sums of Toeplitz products.  Two launches, each with one workgroup per
+//   (resultant, prime, block):
+//   k_interp_q:   Newton coefficients a_{64j..64j+63} (the convolution units
+//                 over input blocks spread over the wavefronts, summed in LDS)
+//                 and Q_j, stored in the workspace;
+//   k_interp_out: coefficients 64 ob .. 64 ob + 63 of P as sum_{j >= ob} of
+//                 G_j Q_j (one wavefront per j).
+//   The G_j come from a table filled once per device.
+// ---------------------------------------------------------------------------
+constexpr int IFF_W = 32 * IFF_J * (IFF_J - 1) + IFF_J;  // words per prime: rows j < IFF_J of degree 64 j
+__host__ __device__ constexpr int iff_off(int j) { return 32 * j * (j - 1) + j; }
+constexpr int IBT = IFF_J;  // wavefronts per workgroup (one per input block or Newton block)
+
+// Montgomery form of the coefficients of G_j for the first IFF_K primes
+__device__ uint32_t g_ffact[(int64_t)IFF_K * IFF_W];
+
+__global__ __launch_bounds__(256) void k_ffact_init() {
+  __shared__ uint32_t buf[2][64 * IFF_J + 1];
+  const int pi = blockIdx.x;
+  const PrimeC c = g_primes[pi];
+  uint32_t* out = g_ffact + (int64_t)pi * IFF_W;
+  for (int m = threadIdx.x; m <= 64 * IFF_J; m += 256) buf[0][m] = m == 0 ? c.r1 : 0u;
+  if (threadIdx.x == 0) out[iff_off(0)] = c.r1;
+  __syncthreads();
+  int cur = 0;
+  for (int t = 0; t < 64 * (IFF_J - 1); ++t) {  // multiply by (x - t): degree t -> t + 1
+    const uint32_t nt = to_mont(t == 0 ? 0u : c.p - (uint32_t)t, c);
+    for (int m = threadIdx.x; m <= t + 1; m += 256) {
+      const uint32_t lo = m >= 1 ? buf[cur][m - 1] : 0u;
+      const uint32_t hi = m <= t ? buf[cur][m] : 0u;
+      buf[cur ^ 1][m] = madd(lo, mmulc(nt, hi, c.p, c.pinv), c.p);
+    }
+    __syncthreads();
+    cur ^= 1;
+    if ((t + 1) % 64 == 0) {  // G_j complete, j = (t + 1) / 64
+      const int j = (t + 1) / 64;
+      for (int m = threadIdx.x; m <= t + 1; m += 256) out[iff_off(j) + m] = buf[cur][m];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64 * IBT) void k_interp_q(const ResJob* jobs, const int64_t* prefix, int njobs,
+                                                       uint32_t* ws) {
+  __shared__ uint32_t U[64 * IFF_J];          // v_i / i!
+  __shared__ uint32_t Wp[IPAD + 64 * IFF_J];  // zeros, then (-1)^j / j!
+  __shared__ uint32_t part[IFF_J][64];        // convolution units of this Newton block
+  const int64_t b = blockIdx.x;
+  const int jj = find_job(prefix, njobs, b);
+  const ResJob J = jobs[jj];
+  const int n1 = J.D + 1;
+  const int nblk = (n1 + 63) / 64;
+  const int64_t lb = b - prefix[jj];
+  const int pi = (int)(lb / nblk);
+  const int j = (int)(lb % nblk);             // Newton block
+  const PrimeC c = g_primes[pi];
+  const uint32_t* V = ws + J.pts_off + (int64_t)pi * n1;
+  const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int top = 64 * (j + 1);               // inputs and weights below 64 (j + 1) are read
+  for (int t = tid; t < IPAD + top; t += 64 * IBT) {
+    const int i = t - IPAD;
+    uint32_t w = 0;
+    if (i >= 0 && i < n1) {
+      const uint32_t f = IF[i];
+      w = (i & 1) ? mneg(f, c.p) : f;
+    }
+    Wp[t] = w;
+    if (t < top) U[t] = t < n1 ? mmulc(canon(V[t], c.p), IF[t], c.p, c.pinv) : 0u;
+  }
+  __syncthreads();
+  // a_k, k = 64 j + lane: input block ib on wavefront ib
+  if (wave <= j) part[wave][lane] = toeplitz64(0u, U[wave * 64 + lane], Wp + IPAD + 64 * (j - wave) + lane, c);
+  __syncthreads();
+  if (wave != 0) return;
+  uint32_t a = 0;
+  for (int ib = 0; ib <= j; ++ib) a = madd(a, part[ib][lane], c.p);
+  // Q_j, coefficient of x^lane in lane
+  const int b0 = 64 * j;
+  const int len = min(64, n1 - b0);
+  const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
+  uint32_t q = lane == 0 ? bcast(a, len - 1) : 0u;
+  for (int s = 0; s + 2 <= len; ++s) {  // Q <- Q (x - (b0 + kq)) + a_{b0 + kq}, kq = len - 2 - s
+    const int kq = len - 2 - s;
+    const uint32_t add = bcast(a, kq);
+    const uint32_t qprev = lane_shr1(q) + (lane == 0 ? add : 0u);
+    q = canon(redc((uint64_t)bcast(nk, kq) * q + ((uint64_t)qprev << 32), c.p, c.pinv), c.p);
+  }
+  ws[J.nq_off + (int64_t)pi * nblk * 64 + b0 + lane] = q;
+}
+
+__global__ __launch_bounds__(64 * IBT) void k_interp_out(const ResJob* jobs, const int64_t* prefix, int njobs,
+                                                         uint32_t* ws) {
+  __shared__ uint32_t Gs[IFF_J][128];   // coefficients 64 ob - 64 .. 64 ob + 63 of G_j
+  __shared__ uint32_t outp[IFF_J][64];  // G_j Q_j on this block
+  const int64_t b = blockIdx.x;
+  const int jj = find_job(prefix, njobs, b);
+  const ResJob J = jobs[jj];
+  const int n1 = J.D + 1;
+  const int nblk = (n1 + 63) / 64;
+  const int64_t lb = b - prefix[jj];
+  const int pi = (int)(lb / nblk);
+  const int ob = (int)(lb % nblk);      // output block
+  const PrimeC c = g_primes[pi];
+  const uint32_t* GF = g_ffact + (int64_t)pi * IFF_W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = ob + wave;              // Newton block of this wavefront
+  if (j < nblk) {
+    for (int m = lane; m < 128; m += 64) {
+      const int g = 64 * ob - 64 + m;
+      Gs[wave][m] = (g >= 0 && g <= 64 * j) ? GF[iff_off(j) + g] : 0u;
+    }
+    const uint32_t q = ws[J.nq_off + (int64_t)pi * nblk * 64 + 64 * j + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    outp[wave][lane] = toeplitz64(0u, q, &Gs[wave][64 + lane], c);
+  }
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < nblk - ob; ++w) s = madd(s, outp[w][lane], c.p);
+    const int t = 64 * ob + lane;
+    if (t < n1) ws[J.val_off + (int64_t)pi * n1 + t] = from_mont(s, c);
+  }
+}
+
+void launch_interp_blk(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks, uint32_t* ws,
+                       hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_interp_q, dim3((unsigned)nblocks), dim3(64 * IBT), 0, s, jobs_d, blk_prefix_d, njobs, ws);
+  hipLaunchKernelGGL(k_interp_out, dim3((unsigned)nblocks), dim3(64 * IBT), 0, s, jobs_d, blk_prefix_d, njobs, ws);
 }
 
 size_t interp_lds_bytes(int max_D) {
@@ -775,6 +916,11 @@ CrtTables global_crt_tables() {
   t.pstride = LPS;
   if (dev >= 0 && dev < 64) { cache[dev] = t; have[dev] = true; }
   return t;
+}
+
+void launch_ffact_init(hipStream_t s) {
+  static_assert(IFF_K <= KMAX, "falling-factorial table covers table primes only");
+  hipLaunchKernelGGL(k_ffact_init, dim3(IFF_K), dim3(256), 0, s);
 }
 
 }  // namespace snc

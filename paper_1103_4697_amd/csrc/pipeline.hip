@@ -67,6 +67,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   lay.rows_off = off; off = align256(off + sizeof(RowDesc) * nrows);
   lay.pref_red = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_interp = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_interp_blk = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtd = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtc = off; off = align256(off + 8 * (NJ + 1));
   for (int j = 0; j < NJ; ++j) {
@@ -102,10 +103,13 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     const size_t n1 = (size_t)P.D + 1;
     J.res_off = (int64_t)w; w += align_words((size_t)P.k * P.T);
     J.val_off = (int64_t)w; w += align_words((size_t)P.k * n1);
+    J.pts_off = (int64_t)w; w += align_words((size_t)P.k * n1);
+    J.nq_off = (int64_t)w; w += align_words((size_t)P.k * ((n1 + 63) / 64) * 64);
     J.dig_off = (int64_t)w; w += align_words(n1 * P.k);
     J.acc_off = (int64_t)w;  // unused: the combine step keeps its accumulators in LDS
     lay.nb_red += (int64_t)P.k * ((P.T + 255) / 256);
     lay.nb_interp += P.k;
+    lay.nb_interp_blk += (int64_t)P.k * ((n1 + 63) / 64);
     lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
     lay.nb_crtc += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
     lay.max_k = std::max(lay.max_k, P.k);
@@ -117,6 +121,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.total_inst += (int64_t)P.k * n1;
     lay.max_D = std::max(lay.max_D, P.D);
   }
+  lay.interp_blk = NJ > 0 && interp_blk_fits(lay.max_D, lay.max_k);
   lay.abn_count_off = w * 4; w += 64;
   lay.abn_list_off = w * 4;
   lay.abn_cap = (uint32_t)std::min<int64_t>(lay.total_inst, 0x7fffffff);
@@ -201,7 +206,10 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   launch_elim_general(jobs, rows, wsw, abn_count, abn_list,
                       (int)std::min<int64_t>(std::max<int64_t>(lay.total_inst, 64), 16384), s);
   if (tm) tm->mark("elim_general", 1);
-  launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, s);
+  if (lay.interp_blk)
+    launch_interp_blk(jobs, (const int64_t*)(ws + lay.pref_interp_blk), NJ, lay.nb_interp_blk, wsw, s);
+  else
+    launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, s);
   if (tm) tm->mark("interp", 1);
   }
   if (part == PIPE_TO_INTERP) return;
@@ -222,6 +230,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   uint32_t* coef = (uint32_t*)(h + lay.coef_off);
   int64_t* pr = (int64_t*)(h + lay.pref_red);
   int64_t* pi = (int64_t*)(h + lay.pref_interp);
+  int64_t* pib = (int64_t*)(h + lay.pref_interp_blk);
   int64_t* pd = (int64_t*)(h + lay.pref_crtd);
   int64_t* pc = (int64_t*)(h + lay.pref_crtc);
   int64_t* pe[NCLS];
@@ -236,7 +245,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   int32_t* lg = (int32_t*)(h + lay.list_gen);
   int ng = 0;
   pg[0] = 0;
-  pr[0] = pi[0] = pd[0] = pc[0] = 0;
+  pr[0] = pi[0] = pib[0] = pd[0] = pc[0] = 0;
   size_t cw = 0;
   for (int j = 0; j < NJ; ++j) {
     const int idx = lay.dev[j];
@@ -277,6 +286,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     const int64_t n1 = P.D + 1;
     pr[j + 1] = pr[j] + (int64_t)P.k * ((P.T + 255) / 256);
     pi[j + 1] = pi[j] + P.k;
+    pib[j + 1] = pib[j] + (int64_t)P.k * ((P.D + 1 + 63) / 64);
     pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     pc[j + 1] = pc[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     if (P.cls >= 0) {
@@ -298,6 +308,7 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
   key.push_back((int64_t)lay.total_bytes);
   key.push_back((int64_t)lay.jobs.size());
   key.push_back(lay.nb_red); key.push_back(lay.nb_interp); key.push_back(lay.nb_crtd);
+  key.push_back(lay.nb_interp_blk); key.push_back(lay.interp_blk ? 1 : 0);
   key.push_back(lay.nb_crtc); key.push_back(lay.n_gen_inst); key.push_back(lay.max_D);
   key.push_back(lay.total_inst);
   for (int c = 0; c < NCLS; ++c) {
@@ -305,7 +316,7 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
   }
   key.push_back(lay.n_gen_jobs);
   key.push_back((int64_t)lay.abn_count_off); key.push_back((int64_t)lay.abn_list_off);
-  for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_crtd, lay.pref_crtc,
+  for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_interp_blk, lay.pref_crtd, lay.pref_crtc,
                    lay.pref_gen, lay.list_gen})
     key.push_back((int64_t)o);
   for (int c = 0; c < NCLS; ++c) { key.push_back((int64_t)lay.pref_ee[c]); key.push_back((int64_t)lay.list_ee[c]); }

@@ -48,6 +48,8 @@ struct BatchLayout {
   std::vector<ResJob> jobs;          // device job descriptors (offsets filled)
   size_t jobs_off = 0, rows_off = 0, coef_off = 0;        // bytes
   size_t pref_red = 0, pref_interp = 0, pref_crtd = 0, pref_crtc = 0, pref_gen = 0;  // bytes
+  size_t pref_interp_blk = 0;        // bytes: block prefix of the block-parallel interpolation
+  bool interp_blk = false;           // every job fits the block-parallel interpolation
   size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes
   size_t header_bytes = 0;
   size_t abn_count_off = 0, abn_list_off = 0;              // bytes
@@ -55,7 +57,7 @@ struct BatchLayout {
   size_t out_off = 0, out_words = 0;                       // bytes / words
   size_t sq_off = 0, sq_words = 0;  // bytes / words: gcd(R, R') descriptors, work items, e and d
   size_t total_bytes = 0;
-  int64_t nb_red = 0, nb_interp = 0, nb_crtd = 0, nb_crtc = 0, n_gen_inst = 0;
+  int64_t nb_red = 0, nb_interp = 0, nb_crtd = 0, nb_crtc = 0, n_gen_inst = 0, nb_interp_blk = 0;
   int64_t nb_ee[NCLS] = {0};
   int n_ee_jobs[NCLS] = {0}, n_gen_jobs = 0, n_rows = 0, max_D = 0, max_k = 0;
   int max_T_ee[NCLS] = {0};  // largest residue count per prime among a class's jobs

@@ -33,7 +33,9 @@ struct ResJob {
   int32_t rstride;     // row groups per operand: ceil((width + 1) / 4), width = register class or m
   int64_t coef_off;    // input limbs [T][nl] (uint32 index)
   int64_t res_off;     // residues [k][T] (uint32 index)
-  int64_t val_off;     // values at points, then coefficients mod p: [k][D+1]
+  int64_t val_off;     // coefficients mod p: [k][D+1]
+  int64_t pts_off;     // values at the points: [k][D+1]
+  int64_t nq_off;      // Newton blocks Q_j of the block-parallel interpolation: [k][64 ceil((D+1)/64)]
   int64_t dig_off;     // mixed-radix digits [D+1][k]
   int64_t acc_off;     // CRT accumulator [D+1][LX] with LX = lx_of(k)
   int64_t out_off;     // output limbs [D+1][L]
@@ -110,6 +112,13 @@ void upload_tables(const PrimeC* primes, const uint32_t* garner_c, const uint32_
 hipError_t configure_kernels();
 void launch_ifact_init(hipStream_t s);
 size_t interp_lds_bytes(int max_D);
+// block-parallel interpolation: one workgroup per (resultant, prime, block of 64 coefficients),
+// for degree bounds below 64 IFF_J and the first IFF_K primes (falling-factorial table)
+constexpr int IFF_J = 16;
+constexpr int IFF_K = 256;
+inline bool interp_blk_fits(int max_D, int max_k) { return max_D + 1 <= 64 * IFF_J && max_k <= IFF_K; }
+void launch_interp_blk(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks, uint32_t* ws,
+                       hipStream_t s);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 // zero_word (may be null) is set to zero by the same launch
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,

@@ -194,3 +194,27 @@ def test_batch_matches_plain_and_oracle(snc):
     first = b.results()
     b.run()
     assert b.results() == first == batch
+
+
+@pytest.mark.parametrize("da,db", [(63, 20), (64, 32), (1000, 500), (1023, 300), (1024, 512)])
+def test_interpolation_block_boundaries(snc, da, db):
+    """res_y(y^2 - a, y - b) = b^2 - a exactly (f at the root y = b of the
+    monic g).  The degree bounds 63/64 (one and two blocks of 64), 1000 and
+    1023 (sixteen blocks, the last row of the falling-factorial table) take
+    the block-parallel interpolation; 1024 takes the one-workgroup kernel.
+    Plain calls and a batch replay agree with the exact value."""
+    rng = random.Random(da)
+    a = [rng.randrange(-(1 << 40), 1 << 40) for _ in range(da + 1)]
+    a[-1] = a[-1] or 1
+    b = [rng.randrange(-(1 << 20), 1 << 20) for _ in range(db + 1)]
+    b[-1] = b[-1] or 1
+    want = zx.sub(zx.mul(b, b), a)
+    n = max(da, db) + 1
+    f = [[-c for c in a] + [0] * (n - len(a)), [0] * n, [1] + [0] * (n - 1)]
+    g = [[-c for c in b] + [0] * (n - len(b)), [1] + [0] * (n - 1)]
+    assert snc.resultant_y(f, g) == want
+    batch = snc.ResultantBatch([(f, g), (g, f)])
+    for _ in range(2):
+        batch.run()
+        r_fg, r_gf = batch.results()
+        assert r_fg == want and r_gf == want  # (-1)^(2*1) = 1
