@@ -474,7 +474,8 @@ int run_prepared_fork(snc_prepared* pr, hipStream_t stream, const std::function<
   if (pr->lay.dev.empty()) { on_results(); return SNC_OK; }
   HIPCHK(hipSetDevice(c->device));
   if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-  if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming));
+  // the side stream runs on this device only: a device-scope release suffices
+  if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming | hipEventReleaseToDevice));
   StageTimer tm{c, stream, false};
   int st = launch_prepared_part(pr, stream, PIPE_TO_INTERP, tm);
   if (st) return st;
