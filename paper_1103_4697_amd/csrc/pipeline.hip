@@ -402,15 +402,16 @@ static bool prepared_outputs(snc_prepared* pr, snc_upoly* out) {
   return true;
 }
 
-// one part of the pipeline on `stream`, as a HIP graph captured on first use
-static int launch_prepared_part(snc_prepared* pr, hipStream_t stream, int part, StageTimer& tm) {
+// the whole pipeline on `stream`, as a HIP graph captured on first use
+static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer& tm) {
+  const int part = PIPE_ALL;
   snc_ctx* c = pr->c;
   if (!pr->use_graph) {
     launch_pipeline(pr->lay, pr->ws, stream, tm.on ? &tm : nullptr, part);
     HIPCHK(hipGetLastError());
     return SNC_OK;
   }
-  hipGraphExec_t& gx = part == PIPE_ALL ? pr->gexec : part == PIPE_TO_INTERP ? pr->gexec_a : pr->gexec_b;
+  hipGraphExec_t& gx = pr->gexec;
   if (!gx) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
@@ -422,7 +423,7 @@ static int launch_prepared_part(snc_prepared* pr, hipStream_t stream, int part, 
     if (e != hipSuccess) { gx = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   }
   HIPCHK(hipGraphLaunch(gx, stream));
-  if (tm.on) tm.mark(part == PIPE_CRT ? "pipeline_crt" : "pipeline", 1);
+  if (tm.on) tm.mark("pipeline", 1);
   return SNC_OK;
 }
 
@@ -457,7 +458,7 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   HIPCHK(hipSetDevice(c->device));
   StageTimer tm{c, stream, c->timing && !pr->use_graph};
   tm.start();
-  int st = launch_prepared_part(pr, stream, PIPE_ALL, tm);
+  int st = launch_prepared_all(pr, stream, tm);
   if (st) return st;
   HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, stream));
   tm.mark("d2h", 1);
@@ -476,18 +477,19 @@ int run_prepared_fork(snc_prepared* pr, hipStream_t stream, const std::function<
   if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
   // the side stream runs on this device only: a device-scope release suffices
   if (!c->ev_mid) HIPCHK(hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming | hipEventReleaseToDevice));
-  StageTimer tm{c, stream, false};
-  int st = launch_prepared_part(pr, stream, PIPE_TO_INTERP, tm);
-  if (st) return st;
+  // plain launches: the host queues the whole step (both streams) while the
+  // first kernels run, which measured slightly faster than replaying graphs here
+  launch_pipeline(pr->lay, pr->ws, stream, nullptr, PIPE_TO_INTERP);
+  HIPCHK(hipGetLastError());
   // the branch is queued on this stream right behind the interpolation, so
   // it starts without a cross-stream wait; the Chinese remaindering and the
   // download of the results go to the side stream
   HIPCHK(hipEventRecord(c->ev_mid, stream));
-  st = branch(stream);
+  const int st = branch(stream);
   if (st) return st;
   HIPCHK(hipStreamWaitEvent(c->side_stream, c->ev_mid, 0));
-  st = launch_prepared_part(pr, c->side_stream, PIPE_CRT, tm);
-  if (st) return st;
+  launch_pipeline(pr->lay, pr->ws, c->side_stream, nullptr, PIPE_CRT);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost,
                         c->side_stream));
   HIPCHK(hipStreamSynchronize(c->side_stream));
@@ -510,8 +512,6 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
 void destroy_prepared(snc_prepared* pr) {
   if (!pr) return;
   if (pr->gexec) (void)hipGraphExecDestroy(pr->gexec);
-  if (pr->gexec_a) (void)hipGraphExecDestroy(pr->gexec_a);
-  if (pr->gexec_b) (void)hipGraphExecDestroy(pr->gexec_b);
   if (pr->h_out) (void)hipHostFree(pr->h_out);
   if (pr->h_ed) (void)hipHostFree(pr->h_ed);
   delete pr;

@@ -109,8 +109,6 @@ struct snc_prepared {
   uint8_t* ws = nullptr;
   void* h_out = nullptr;
   hipGraphExec_t gexec = nullptr;    // whole pipeline
-  hipGraphExec_t gexec_a = nullptr;  // reduction .. interpolation
-  hipGraphExec_t gexec_b = nullptr;  // Chinese remaindering
   // projection step (resultant and gcd(R, R')): the Euclid descriptors are
   // uploaded into the workspace on the first run
   void* h_ed = nullptr;              // pinned download of e and d
