@@ -32,20 +32,23 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 VALU lane-ops/s of the MI
 def eval_elim_lane_ops(m: int, n: int, T: int) -> int:
     """Essential VALU lane-ops of one (prime, point) instance of the fused
     evaluate+eliminate kernel: 3 per Horner step (64-bit multiply-add, low
-    multiply, multiply-add), 4 per two-product update lc(Y) X_i - lc(X) Y_i and
-    3 per scale-only update lc(Y) X_i, over the normal remainder sequence."""
+    multiply, multiply-add); for the first remainder's elementary steps 4 per
+    two-product update lc(Y) X_i - lc(X) Y_i and 3 per scale-only update
+    lc(Y) X_i; for every later (normal) remainder one fused update of three
+    products and one REDC, 5 per coefficient of the new remainder."""
     ops = 3 * T
     if m < n:
         m, n = n, m
     if n == 0:
         return ops
-    a, b, s = m, n, m - n + 1
+    dX, b = m, n
+    for _ in range(m - n + 1):
+        ops += 4 * b + 3 * (dX - b)
+        dX -= 1
+    b -= 1
     while b >= 1:
-        dX = a
-        for _ in range(s):
-            ops += 4 * b + 3 * (dX - b)
-            dX -= 1
-        a, b, s = b, b - 1, 2
+        ops += 5 * b
+        b -= 1
     return ops
 
 

@@ -640,6 +640,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
     if (!p.Q.deriv) pack_rows(p.b, p.Q.db, p.Q.nl, h + p.coef + (size_t)(p.Q.da + 1) * p.Q.nl);
     GcdDesc& G = p.G;
     G.da = p.Q.da; G.db = p.Q.db; G.nl = p.Q.nl; G.wl = p.wl; G.deriv = p.Q.deriv ? 1 : 0; G.fused = 0; G.vals = nullptr; G.vstride = 0; G.d_off = 0;
+    G.ed_out = nullptr;
     G.coef_off = (int64_t)p.coef; G.slot_prime_off = (int64_t)p.slot_prime;
     G.res_off = (int64_t)p.res; G.e_off = (int64_t)p.e; G.w_off = (int64_t)p.w; G.u_off = (int64_t)p.u;
     G.v_off = (int64_t)p.v;
@@ -990,6 +991,16 @@ static int sqfree_setup(snc_prepared* pr, const SqfreeLayout& S, hipStream_t str
   snc_ctx* ctx = pr->c;
   const BatchLayout& lay = pr->lay;
   if (S.fused > lay.sq_words) { ctx->err = "projection-step region too small"; return SNC_EINTERNAL; }
+  const size_t e_words = S.fused - S.e;
+  int32_t* ed_dev = nullptr;
+  if (!pr->h_ed) {
+    if (hipHostMalloc(&pr->h_ed, std::max<size_t>(e_words * 4, 4), hipHostMallocMapped) != hipSuccess) {
+      pr->h_ed = nullptr;
+      ctx->err = "pinned staging allocation failed";
+      return SNC_EDEVICE;
+    }
+  }
+  HIPCHK(hipHostGetDevicePointer((void**)&ed_dev, pr->h_ed, 0));
   const int64_t base = (int64_t)(lay.sq_off / 4);
   std::vector<uint32_t> hf(S.e, 0u);
   GcdDesc* descs = (GcdDesc*)(hf.data() + S.descs);
@@ -1005,8 +1016,9 @@ static int sqfree_setup(snc_prepared* pr, const SqfreeLayout& S, hipStream_t str
     G.vals = (const uint32_t*)pr->ws + J.val_off;
     G.vstride = J.D + 1;
     G.slot_prime_off = base + (int64_t)S.slotp;
-    G.e_off = base + (int64_t)(S.e + S.job_base[j]);
-    G.d_off = base + (int64_t)(S.d + S.job_base[j]);
+    G.e_off = (int64_t)S.job_base[j];                  // relative to ed_out
+    G.d_off = (int64_t)(S.d - S.e + S.job_base[j]);
+    G.ed_out = ed_dev;
   }
   pr->sq_ranges.clear();
   int nitems = 0;
@@ -1021,12 +1033,6 @@ static int sqfree_setup(snc_prepared* pr, const SqfreeLayout& S, hipStream_t str
     }
     if (nitems > off) pr->sq_ranges.insert(pr->sq_ranges.end(), {cls, off, nitems - off, maxd});
   }
-  const size_t e_words = S.fused - S.e;
-  if (!pr->h_ed && hipHostMalloc(&pr->h_ed, std::max<size_t>(e_words * 4, 4), hipHostMallocDefault) != hipSuccess) {
-    pr->h_ed = nullptr;
-    ctx->err = "pinned staging allocation failed";
-    return SNC_EDEVICE;
-  }
   if (ctx->stage_in(S.e * 4)) { ctx->err = "pinned staging allocation failed"; return SNC_EDEVICE; }
   std::memcpy(ctx->h_in, hf.data(), S.e * 4);
   HIPCHK(hipMemcpyAsync(pr->ws + lay.sq_off, ctx->h_in, S.e * 4, hipMemcpyHostToDevice, stream));
@@ -1040,9 +1046,18 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
   snc_ctx* ctx = pr->c;
   const int n = pr->n;
   const BatchLayout& lay = pr->lay;
-  SqfreeLayout S;
-  std::vector<Quick> B;
-  sqfree_layout(pr, S, &B);
+  struct SqCache {
+    SqfreeLayout S;
+    std::vector<Quick> B;
+  };
+  if (!pr->sq_cache) {
+    auto sc = std::make_shared<SqCache>();
+    sqfree_layout(pr, sc->S, &sc->B);
+    pr->sq_cache = sc;
+  }
+  const SqCache& SC = *static_cast<const SqCache*>(pr->sq_cache.get());
+  const SqfreeLayout& S = SC.S;
+  const std::vector<Quick>& B = SC.B;
   bool short_out = false;
   for (int i = 0; i < n; ++i) {
     const int need_deg = std::max(B[i].deg_bound, 0);
@@ -1064,7 +1079,6 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     const int st = sqfree_setup(pr, S, stream);
     if (st) return st;
   }
-  const size_t e_words = S.fused - S.e;  // e and d arrays
   uint32_t* ws = (uint32_t*)pr->ws;
   const int64_t base = (int64_t)(lay.sq_off / 4);
   int nitems = 0;
@@ -1089,8 +1103,7 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     }
     HIPCHK(hipGetLastError());
     if (timing) HIPCHK(hipEventRecord(t1, s));
-    HIPCHK(hipMemcpyAsync(pr->h_ed, ws + base + S.e, e_words * 4, hipMemcpyDeviceToHost, s));
-    return SNC_OK;
+    return SNC_OK;  // e and d land in mapped host memory: no download
   };
   // while the Euclid runs: cont R, which is also gcd(cont R, cont R') since
   // cont R divides every i R_i

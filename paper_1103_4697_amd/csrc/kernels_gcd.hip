@@ -19,6 +19,11 @@
 
 namespace snc {
 
+// where the fused check writes e and d: mapped host memory when given, else the workspace
+__device__ __forceinline__ int32_t* fused_out(const GcdDesc& G, uint32_t* ws) {
+  return G.ed_out ? G.ed_out : (int32_t*)ws;
+}
+
 __device__ __forceinline__ uint32_t reduce_coef(const uint32_t* limbs, int nl, const PrimeC& c) {
   const uint32_t mask = (limbs[nl - 1] >> 31) ? 0xffffffffu : 0u;
   uint32_t acc = 0;
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
   while (dA >= 0 && A[dA] == 0) --dA;
   int dB = G.db;
   while (dB >= 0 && B[dB] == 0) --dB;
-  if (G.fused && tid == 0) ((int32_t*)(ws + G.d_off))[slot] = dA;
+  if (G.fused && tid == 0) fused_out(G, ws)[G.d_off + slot] = dA;
   if (!G.fused && dA < G.da && dB < G.db) {
     if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = GCD_SLOT_UNUSABLE;
     return;
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
     while (dA >= 0 && A[dA] == 0) --dA;
   }
   const int e = dA;  // gcd degree mod p (>= 0 unless both operands vanish mod p)
-  if (tid == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+  if (tid == 0) (G.fused ? fused_out(G, ws) : (int32_t*)ws)[G.e_off + slot] = e;
   if (e <= 0 || G.fused) return;  // a usable prime with a constant gcd ends the problem on the host: no rows needed
   const uint32_t inv = minv(A[e], c);
   for (int i = tid; i <= e; i += GCD_THREADS) Gm[i] = mmulc(A[i], inv, c.p, c.pinv);
@@ -198,13 +203,6 @@ __device__ __forceinline__ int reg_trim(uint32_t (&X)[E], int d, const PrimeC& c
   return d;
 }
 
-// a x + b y + c z with a, b, c canonical and x, y, z < 4p: the sum stays
-// below 12 p^2 + 2^32 p < 2^64 (p < 2^30) and the result below 4p.
-__device__ __forceinline__ uint32_t mmul3(uint32_t a, uint32_t x, uint32_t b, uint32_t y, uint32_t cc,
-                                          uint32_t z, uint32_t p, uint32_t pinv) {
-  const uint64_t t = (uint64_t)a * x + (uint64_t)b * y + (uint64_t)cc * z;
-  return redc(t, p, pinv);
-}
 
 // The normal remainder step (deg X = deg Y + 1) as one update: the pseudo-
 // remainder lc(Y)^2 X - (lc(Y) lc(X) x + lc(Y) X_1 - lc(X) Y_1) Y, top-aligned
@@ -401,9 +399,9 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   const int dX = reg_trim<E>(X, G.da, c);
   const int dY = reg_trim<E>(Y, G.db, c);
   if (G.fused) {
-    if (lane == 0) ((int32_t*)(ws + G.d_off))[slot] = dX;
+    if (lane == 0) fused_out(G, ws)[G.d_off + slot] = dX;
     const int e = dX < 0 ? -1 : euclid_levels<E>(X, dX, Y, dY, sm, lane, c);
-    if (lane == 0) ((int32_t*)(ws + G.e_off))[slot] = e;
+    if (lane == 0) fused_out(G, ws)[G.e_off + slot] = e;
     return;
   }
   if (dX < G.da && dY < G.db) {

@@ -38,9 +38,18 @@ __device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, uint32_t p, uin
 }
 
 // a*b + c*d (Montgomery), a,c canonical-ish (<= p), b,d < 3p  ->  [0, 2.5p)
+// (b,d < 4p -> [0, 3p))
 __device__ __forceinline__ uint32_t mmul2(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
                                           uint32_t p, uint32_t pinv) {
   uint64_t t = (uint64_t)a * b + (uint64_t)c * d;
+  return redc(t, p, pinv);
+}
+
+// a x + b y + c z with a, b, c canonical and x, y, z < 4p: the sum stays
+// below 12 p^2 + 2^32 p < 2^64 (p < 2^30) and the result below 4p.
+__device__ __forceinline__ uint32_t mmul3(uint32_t a, uint32_t x, uint32_t b, uint32_t y, uint32_t cc,
+                                          uint32_t z, uint32_t p, uint32_t pinv) {
+  const uint64_t t = (uint64_t)a * x + (uint64_t)b * y + (uint64_t)cc * z;
   return redc(t, p, pinv);
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -111,8 +112,9 @@ struct snc_prepared {
   hipGraphExec_t gexec = nullptr;    // whole pipeline
   // projection step (resultant and gcd(R, R')): the Euclid descriptors are
   // uploaded into the workspace on the first run
-  void* h_ed = nullptr;              // pinned download of e and d
+  void* h_ed = nullptr;              // mapped pinned memory the Euclid writes e and d to
   bool sq_ready = false;
+  std::shared_ptr<void> sq_cache;    // the projection step's plan, built on the first run
   std::vector<int> sq_ranges;        // (register class, first item, items, largest degree) per launch
 };
 

@@ -94,6 +94,7 @@ struct GcdDesc {
   int64_t w_off;           // [slot][wl]   monic gcd mod p (plain)
   int64_t u_off;           // [slot][da+1] a / monic gcd mod p (plain)
   int64_t v_off;           // [slot][db+1] b / monic gcd mod p (plain)
+  int32_t* ed_out;         // fused: if set, e and d are written at ed_out + e_off / d_off (host-mapped)
 };
 
 // gcd degree written for a prime dividing both leading coefficients (the prime is not used)
