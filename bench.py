@@ -31,21 +31,26 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 VALU lane-ops/s of the MI
 
 def eval_elim_lane_ops(m: int, n: int, T: int) -> int:
     """Essential VALU lane-ops of one (prime, point) instance of the fused
-    evaluate+eliminate kernel: 3 per Horner step (64-bit multiply-add, low
-    multiply, multiply-add); for the first remainder's elementary steps 4 per
-    two-product update lc(Y) X_i - lc(X) Y_i and 3 per scale-only update
-    lc(Y) X_i; for every later (normal) remainder one fused update of three
-    products and one REDC, 5 per coefficient of the new remainder."""
-    ops = 3 * T
+    evaluate+eliminate kernel: Horner's rule in x^4 costs 6 per 4
+    coefficients (four 64-bit multiply-adds, low multiply, multiply-add);
+    every normal remainder (the first one when deg A = deg B + 1, and all
+    later ones) is one fused update of three products and one REDC, 5 per
+    coefficient of the new remainder; a first remainder with a larger degree
+    gap takes elementary steps, 4 per two-product update lc(Y) X_i -
+    lc(X) Y_i and 3 per scale-only update lc(Y) X_i."""
+    ops = (3 * T) // 2
     if m < n:
         m, n = n, m
     if n == 0:
         return ops
-    dX, b = m, n
-    for _ in range(m - n + 1):
-        ops += 4 * b + 3 * (dX - b)
-        dX -= 1
-    b -= 1
+    if m == n + 1:
+        ops += 5 * n
+    else:
+        dX = m
+        for _ in range(m - n + 1):
+            ops += 4 * n + 3 * (dX - n)
+            dX -= 1
+    b = n - 1
     while b >= 1:
         ops += 5 * b
         b -= 1

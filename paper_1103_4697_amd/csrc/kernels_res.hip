@@ -129,30 +129,44 @@ __device__ __forceinline__ uint32_t horner_grouped(const uint32_t* r, const RowD
 }
 
 // The N+1 rows of one operand evaluated at X, four rows at a time from the
-// interleaved group layout: each 64-byte scalar load holds four Horner steps
-// of four independent chains (instruction-level parallelism for a lone
-// wavefront), so one load latency is paid per 48 multiply-adds.  Group
-// lengths are padded at the top with zeros, which keep a Horner accumulator
-// at zero.
+// interleaved group layout: each 64-byte load holds four coefficients of
+// four independent rows (instruction-level parallelism for a lone
+// wavefront).  A chunk of four coefficients is one step of Horner's rule in
+// x^4 with the powers x, x^2, x^3, x^4 kept per lane:
+//   acc <- acc x^4 + v0 + v1 x + v2 x^2 + v3 x^3,
+// four 64-bit multiply-adds and one reduction (v0 enters as v0 2^32).  With
+// canonical coefficients and powers and acc < 4p the sum stays below
+// 7 p^2 + 2^32 p and the result below 4p.  Group lengths are padded at the
+// top with zeros, which keep an accumulator at zero.
 struct alignas(16) HChunk {
   uint4 v[HCHUNK];
 };
+static_assert(HCHUNK == 4, "a chunk is four coefficients");
+
+struct XPow {
+  uint32_t x1, x2, x3, x4;  // Montgomery forms of x, x^2, x^3, x^4, canonical
+};
+
+__device__ __forceinline__ uint32_t hstep4(uint32_t acc, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                           const XPow& xp, const PrimeC& c) {
+  uint64_t t = (uint64_t)acc * xp.x4 + ((uint64_t)v0 << 32);
+  t += (uint64_t)v1 * xp.x1;
+  t += (uint64_t)v2 * xp.x2;
+  t += (uint64_t)v3 * xp.x3;
+  return redc(t, c.p, c.pinv);
+}
 
 __device__ __forceinline__ void horner_chunk(uint32_t& a0, uint32_t& a1, uint32_t& a2, uint32_t& a3,
-                                             const HChunk& h, uint32_t X, const PrimeC& c) {
-#pragma unroll
-  for (int u = HCHUNK - 1; u >= 0; --u) {
-    const uint4 v = h.v[u];
-    a0 = mhorner(a0, X, v.x, c.p, c.pinv);
-    a1 = mhorner(a1, X, v.y, c.p, c.pinv);
-    a2 = mhorner(a2, X, v.z, c.p, c.pinv);
-    a3 = mhorner(a3, X, v.w, c.p, c.pinv);
-  }
+                                             const HChunk& h, const XPow& xp, const PrimeC& c) {
+  a0 = hstep4(a0, h.v[0].x, h.v[1].x, h.v[2].x, h.v[3].x, xp, c);
+  a1 = hstep4(a1, h.v[0].y, h.v[1].y, h.v[2].y, h.v[3].y, xp, c);
+  a2 = hstep4(a2, h.v[0].z, h.v[1].z, h.v[2].z, h.v[3].z, xp, c);
+  a3 = hstep4(a3, h.v[0].w, h.v[1].w, h.v[2].w, h.v[3].w, xp, c);
 }
 
 template <int N>
 __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* r, const RowDesc* rd,
-                                          uint32_t X, const PrimeC& c) {
+                                          const XPow& X, const PrimeC& c) {
 #pragma unroll
   for (int t0 = 0; t0 <= N; t0 += ROWGRP) {
     const RowDesc d = rd[t0 / ROWGRP];
@@ -208,6 +222,16 @@ __device__ __forceinline__ uint32_t rem2_c(uint32_t (&X)[N + 1], const uint32_t 
   X[C] = 0;
   if (canon(X[0], c.p) == 0) ok = false;
   return q0;
+}
+
+// rem2_c on the narrowest width (a multiple of 8) that holds deg X = a
+template <int N, int C>
+__device__ __forceinline__ uint32_t rem2_fit(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, bool& ok,
+                                             const PrimeC& c) {
+  if constexpr (C > 8) {
+    if (a <= C - 8) return rem2_fit<N, C - 8>(X, Y, a, ok, c);
+  }
+  return rem2_c<N, C>(X, Y, ok, c);
 }
 
 // Scale factors of the normal steps.  A normal step with divisor degree b
@@ -268,7 +292,11 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
     __syncthreads();
     r = er;
   }
-  const uint32_t X = to_mont((uint32_t)j, c);
+  XPow X;
+  X.x1 = to_mont((uint32_t)j, c);
+  X.x2 = mmulc(X.x1, X.x1, c.p, c.pinv);
+  X.x3 = mmulc(X.x2, X.x1, c.p, c.pinv);
+  X.x4 = mmulc(X.x2, X.x2, c.p, c.pinv);
   // rows are padded to N+1 per operand (length 0 above the degree): no branches
   const RowDesc* ra = rows + J.rows_off;
   const RowDesc* rb = ra + J.rstride;  // J.rstride == N + 1 on this path
@@ -288,7 +316,7 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
     // first remainder: A <- prem(A, B) with s = m - n + 1 elementary steps,
     // scale lc(B)^{s (n - 1)}
     const int s0 = a - bb + 1;
-    const uint32_t y0 = rem_c<N, N>(A, B, s0, ok, c);
+    const uint32_t y0 = s0 == 2 ? rem2_fit<N, N>(A, B, a, ok, c) : rem_c<N, N>(A, B, s0, ok, c);
     den = mpow(y0, (uint32_t)(s0 * (bb - 1)), c);
     sg ^= (a & bb & 1); a = bb; bb -= 1;
     // from here on: dividend B (degree a), divisor A (degree bb)
