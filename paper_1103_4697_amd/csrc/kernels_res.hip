@@ -16,7 +16,7 @@ __device__ uint32_t g_garner[KMAX];            // Montgomery form of (P_i mod p_
 __device__ uint32_t g_wtab[KMAX * KMAX];       // [j*KMAX + i] = Montgomery form of P_j mod p_i (j < i)
 __device__ uint32_t g_ptab[(KMAX + 1) * LPS];  // row j: P_j = prod_{l<j} p_l, little-endian limbs
 
-__global__ void k_interp(const ResJob* jobs, const int64_t* prefix, int njobs, uint32_t* ws);
+__global__ void k_interp(const ResJob* jobs, const int64_t* prefix, int njobs, uint32_t* ws, uint32_t* zero_word);
 
 // per-device kernel attributes (called once per device before any launch)
 hipError_t configure_kernels() {
@@ -64,6 +64,19 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 256;
 
+// signed coefficient of nl two's-complement limbs -> canonical Montgomery residue
+__device__ __forceinline__ uint32_t reduce_limbs(const uint32_t* limbs, int nl, const PrimeC& c) {
+  const uint32_t mask = (limbs[nl - 1] >> 31) ? 0xffffffffu : 0u;
+  uint32_t acc = 0;
+  for (int l = nl - 1; l >= 0; --l) {
+    uint64_t v = (uint64_t)acc * c.r2 + (uint64_t)(limbs[l] ^ mask) * c.r2;
+    acc = redc(v, c.p, c.pinv);
+  }
+  acc = canon(acc, c.p);
+  if (mask) acc = mneg(madd(acc, c.r1, c.p), c.p);  // -(~x + 1)
+  return acc;
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const ResJob* jobs, const int64_t* prefix,
                                                         int njobs, const uint32_t* ws,
                                                         uint32_t* wsw, uint32_t* zero_word) {
@@ -77,16 +90,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const ResJob* jobs, cons
   const int t = (int)(lb % nb) * RED_THREADS + threadIdx.x;
   if (t >= J.T) return;
   const PrimeC c = g_primes[pi];
-  const uint32_t* limbs = ws + J.coef_off + (int64_t)t * J.nl;
-  const uint32_t mask = (limbs[J.nl - 1] >> 31) ? 0xffffffffu : 0u;
-  uint32_t acc = 0;
-  for (int l = J.nl - 1; l >= 0; --l) {
-    uint64_t v = (uint64_t)acc * c.r2 + (uint64_t)(limbs[l] ^ mask) * c.r2;
-    acc = redc(v, c.p, c.pinv);
-  }
-  acc = canon(acc, c.p);
-  if (mask) acc = mneg(madd(acc, c.r1, c.p), c.p);  // -(~x + 1)
-  wsw[J.res_off + (int64_t)pi * J.T + t] = acc;
+  wsw[J.res_off + (int64_t)pi * J.T + t] = reduce_limbs(ws + J.coef_off + (int64_t)t * J.nl, J.nl, c);
 }
 
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
@@ -264,15 +268,16 @@ __device__ __forceinline__ void elim_phases(uint32_t (&A)[N + 1], uint32_t (&B)[
 
 // LDSROWS: the wavefront first copies its prime's residues into LDS
 // (coalesced) and reads the row chunks from there, so the reads pipeline;
-// otherwise they are 64-byte scalar loads.
-constexpr int EE_LDS_MAX = 64 * 1024;
-
+// otherwise they are 64-byte scalar loads.  With reduce_in (LDSROWS only)
+// the residues are reduced from the input limbs on the way into LDS, and the
+// first point block of each prime also stores them for the general
+// elimination: no separate reduction launch.
 template <int N, bool LDSROWS>
 __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, const int32_t* job_list,
                                                         const int64_t* prefix, int njobs,
                                                         const RowDesc* rows, uint32_t* ws,
                                                         uint32_t* abn_count, AbnEntry* abn_list,
-                                                        uint32_t abn_cap) {
+                                                        uint32_t abn_cap, int reduce_in) {
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const int jid = job_list[jj];
@@ -288,7 +293,17 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   if constexpr (LDSROWS) {
     extern __shared__ uint4 er4[];  // J.T words
     uint32_t* er = reinterpret_cast<uint32_t*>(er4);
-    for (int x = threadIdx.x; x < J.T; x += EE_BLOCK) er[x] = r[x];
+    if (reduce_in) {
+      uint32_t* rg = ws + J.res_off + (int64_t)pi * J.T;
+      const bool store = lb % npb == 0;
+      for (int x = threadIdx.x; x < J.T; x += EE_BLOCK) {
+        const uint32_t v = reduce_limbs(ws + J.coef_off + (int64_t)x * J.nl, J.nl, c);
+        er[x] = v;
+        if (store) rg[x] = v;
+      }
+    } else {
+      for (int x = threadIdx.x; x < J.T; x += EE_BLOCK) er[x] = r[x];
+    }
     __syncthreads();
     r = er;
   }
@@ -353,18 +368,19 @@ int fast_class_cap(int cls) { return kClassCap[cls]; }
 void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
                       const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
-                      hipStream_t s) {
+                      bool reduce_in, hipStream_t s) {
   if (nblocks <= 0) return;
   dim3 g((unsigned)nblocks), blk(EE_BLOCK);
   const size_t lds = (size_t)max_T * sizeof(uint32_t);
-  const bool in_lds = lds <= (size_t)EE_LDS_MAX;
+  const bool in_lds = eval_elim_in_lds(max_T);
+  const int red = reduce_in && in_lds ? 1 : 0;
 #define SNC_EE(NN)                                                                                        \
   if (in_lds)                                                                                             \
     hipLaunchKernelGGL((k_eval_elim<NN, true>), g, blk, lds, s, jobs_d, job_list_d, blk_prefix_d, njobs,   \
-                       rows_d, ws, abn_count, abn_list, abn_cap);                                          \
+                       rows_d, ws, abn_count, abn_list, abn_cap, red);                                     \
   else                                                                                                    \
     hipLaunchKernelGGL((k_eval_elim<NN, false>), g, blk, 0, s, jobs_d, job_list_d, blk_prefix_d, njobs,    \
-                       rows_d, ws, abn_count, abn_list, abn_cap);
+                       rows_d, ws, abn_count, abn_list, abn_cap, 0);
   switch (kClassCap[cls]) {
     case 8: SNC_EE(8) break;
     case 16: SNC_EE(16) break;
@@ -554,7 +570,8 @@ __device__ __forceinline__ uint32_t toeplitz64(uint32_t s, uint32_t u, const uin
 }
 
 __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, const int64_t* prefix,
-                                                           int njobs, uint32_t* ws) {
+                                                           int njobs, uint32_t* ws, uint32_t* zero_word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
   extern __shared__ uint32_t sm[];
   constexpr int NW = INTERP_THREADS / 64;
   const int64_t b = blockIdx.x;
@@ -691,7 +708,8 @@ __global__ __launch_bounds__(256) void k_ffact_init() {
 }
 
 __global__ __launch_bounds__(64 * IBT) void k_interp_q(const ResJob* jobs, const int64_t* prefix, int njobs,
-                                                       uint32_t* ws) {
+                                                       uint32_t* ws, uint32_t* zero_word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
   __shared__ uint32_t U[64 * IFF_J];          // v_i / i!
   __shared__ uint32_t Wp[IPAD + 64 * IFF_J];  // zeros, then (-1)^j / j!
   __shared__ uint32_t part[IFF_J][64];        // convolution units of this Newton block
@@ -776,9 +794,10 @@ __global__ __launch_bounds__(64 * IBT) void k_interp_out(const ResJob* jobs, con
 }
 
 void launch_interp_blk(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks, uint32_t* ws,
-                       hipStream_t s) {
+                       uint32_t* zero_word, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_interp_q, dim3((unsigned)nblocks), dim3(64 * IBT), 0, s, jobs_d, blk_prefix_d, njobs, ws);
+  hipLaunchKernelGGL(k_interp_q, dim3((unsigned)nblocks), dim3(64 * IBT), 0, s, jobs_d, blk_prefix_d, njobs, ws,
+                     zero_word);
   hipLaunchKernelGGL(k_interp_out, dim3((unsigned)nblocks), dim3(64 * IBT), 0, s, jobs_d, blk_prefix_d, njobs, ws);
 }
 
@@ -788,10 +807,10 @@ size_t interp_lds_bytes(int max_D) {
 }
 
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
-                   int max_D, uint32_t* ws, hipStream_t s) {
+                   int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s) {
   if (nblocks <= 0) return;
   hipLaunchKernelGGL(k_interp, dim3((unsigned)nblocks), dim3(INTERP_THREADS), interp_lds_bytes(max_D), s,
-                     jobs_d, blk_prefix_d, njobs, ws);
+                     jobs_d, blk_prefix_d, njobs, ws, zero_word);
 }
 
 // ---------------------------------------------------------------------------

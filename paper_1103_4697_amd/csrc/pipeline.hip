@@ -122,6 +122,10 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.max_D = std::max(lay.max_D, P.D);
   }
   lay.interp_blk = NJ > 0 && interp_blk_fits(lay.max_D, lay.max_k);
+  // every job on the evaluation kernel's LDS variant: it reduces the inputs itself
+  lay.reduce_in_eval = NJ > 0 && lay.n_gen_jobs == 0;
+  for (int c = 0; c < NCLS; ++c)
+    if (lay.n_ee_jobs[c] && !eval_elim_in_lds(lay.max_T_ee[c])) lay.reduce_in_eval = false;
   lay.abn_count_off = w * 4; w += 64;
   lay.abn_list_off = w * 4;
   lay.abn_cap = (uint32_t)std::min<int64_t>(lay.total_inst, 0x7fffffff);
@@ -187,14 +191,15 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   uint32_t* abn_count = (uint32_t*)(ws + lay.abn_count_off);
   AbnEntry* abn_list = (AbnEntry*)(ws + lay.abn_list_off);
   if (part != PIPE_CRT) {
-  launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, abn_count, s);
-  if (tm) tm->mark("reduce", 1);
+  // the counter is cleared by the previous run's interpolation (and at preparation)
+  if (!lay.reduce_in_eval) launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, abn_count, s);
+  if (tm) tm->mark("reduce", lay.reduce_in_eval ? 0 : 1);
   int nee = 0;
   for (int c = 0; c < NCLS; ++c) {
     if (!lay.n_ee_jobs[c]) continue;
     launch_eval_elim(c, jobs, (const int32_t*)(ws + lay.list_ee[c]), (const int64_t*)(ws + lay.pref_ee[c]),
                      lay.n_ee_jobs[c], lay.nb_ee[c], lay.max_T_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap,
-                     s);
+                     lay.reduce_in_eval, s);
     ++nee;
   }
   if (lay.n_gen_jobs) {
@@ -207,9 +212,9 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
                       (int)std::min<int64_t>(std::max<int64_t>(lay.total_inst, 64), 16384), s);
   if (tm) tm->mark("elim_general", 1);
   if (lay.interp_blk)
-    launch_interp_blk(jobs, (const int64_t*)(ws + lay.pref_interp_blk), NJ, lay.nb_interp_blk, wsw, s);
+    launch_interp_blk(jobs, (const int64_t*)(ws + lay.pref_interp_blk), NJ, lay.nb_interp_blk, wsw, abn_count, s);
   else
-    launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, s);
+    launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, abn_count, s);
   if (tm) tm->mark("interp", 1);
   }
   if (part == PIPE_TO_INTERP) return;
@@ -308,7 +313,7 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
   key.push_back((int64_t)lay.total_bytes);
   key.push_back((int64_t)lay.jobs.size());
   key.push_back(lay.nb_red); key.push_back(lay.nb_interp); key.push_back(lay.nb_crtd);
-  key.push_back(lay.nb_interp_blk); key.push_back(lay.interp_blk ? 1 : 0);
+  key.push_back(lay.nb_interp_blk); key.push_back(lay.interp_blk ? 1 : 0); key.push_back(lay.reduce_in_eval ? 1 : 0);
   key.push_back(lay.nb_crtc); key.push_back(lay.n_gen_inst); key.push_back(lay.max_D);
   key.push_back(lay.total_inst);
   for (int c = 0; c < NCLS; ++c) {
@@ -369,6 +374,10 @@ int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly*
     StageTimer tm{c, stream, c->timing && !use_graph};
     tm.start();
     hipError_t e = hipMemcpyAsync(pr->ws, c->h_in, lay.header_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {  // the abnormal-instance counter starts at zero; each run's interpolation clears it
+      launch_zero_u32((uint32_t*)(pr->ws + lay.abn_count_off), 1, stream);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) { c->err = std::string("input upload: ") + hipGetErrorString(e); delete pr; return SNC_EDEVICE; }
   }

@@ -51,6 +51,7 @@ struct BatchLayout {
   size_t pref_red = 0, pref_interp = 0, pref_crtd = 0, pref_crtc = 0, pref_gen = 0;  // bytes
   size_t pref_interp_blk = 0;        // bytes: block prefix of the block-parallel interpolation
   bool interp_blk = false;           // every job fits the block-parallel interpolation
+  bool reduce_in_eval = false;       // the evaluation kernel reduces the inputs (no reduction launch)
   size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes
   size_t header_bytes = 0;
   size_t abn_count_off = 0, abn_list_off = 0;              // bytes

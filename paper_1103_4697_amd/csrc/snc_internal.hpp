@@ -119,23 +119,28 @@ constexpr int IFF_J = 16;
 constexpr int IFF_K = 256;
 inline bool interp_blk_fits(int max_D, int max_k) { return max_D + 1 <= 64 * IFF_J && max_k <= IFF_K; }
 void launch_interp_blk(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks, uint32_t* ws,
-                       hipStream_t s);
+                       uint32_t* zero_word, hipStream_t s);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 // zero_word (may be null) is set to zero by the same launch
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    const uint32_t* ws, uint32_t* res_base, uint32_t* zero_word, hipStream_t s);
+// the evaluation kernel stages a prime's residues in LDS up to this size
+constexpr int EE_LDS_MAX = 64 * 1024;
+inline bool eval_elim_in_lds(int max_T) { return (size_t)max_T * sizeof(uint32_t) <= (size_t)EE_LDS_MAX; }
+// reduce_in: the residues are reduced from the input limbs inside the kernel (LDS variant only)
 void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
                       const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
-                      hipStream_t s);
+                      bool reduce_in, hipStream_t s);
 void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,
                          const uint32_t* abn_count, const AbnEntry* abn_list, int nthreads,
                          hipStream_t s);
 void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
                              const int64_t* inst_prefix_d, int njobs, int64_t ninst,
                              const RowDesc* rows_d, uint32_t* ws, hipStream_t s);
+// the interpolation launches also clear zero_word (the abnormal-instance counter)
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
-                   int max_D, uint32_t* ws, hipStream_t s);
+                   int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s);
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
                        int64_t nblocks, uint32_t* ws, hipStream_t s);
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
