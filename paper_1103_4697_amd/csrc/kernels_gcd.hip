@@ -299,7 +299,7 @@ __device__ __forceinline__ void normal_run(uint32_t (&X)[E], int& dX, uint32_t (
 // moves to the next smaller count once both remainders fit, so the work of a
 // step follows the current degree instead of the input degree.
 __host__ __device__ constexpr int next_slots(int E) {
-  return E == 32 ? 24 : E == 24 ? 16 : E == 16 ? 12 : E == 12 ? 9 : E == 9 ? 6 : E == 6 ? 4 : E == 4 ? 2 : 0;
+  return E == 32 ? 24 : E == 24 ? 16 : E == 16 ? 12 : E == 12 ? 9 : E >= 3 && E <= 9 ? E - 1 : 0;
 }
 
 template <int E>
