@@ -159,6 +159,26 @@ int snc_prepared_sqfree_plan(const snc_prepared* prep, snc_plan* gcd_each, snc_p
 int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, void* stream, snc_upoly* R,
                             snc_upoly* G);
 
+/* Square-free factorisation (Section 2.1: R's square-free part and the
+ * multiplicities of its real roots come from Yun's algorithm on R):
+ *   a = content * prod_i f_i^{m_i},
+ * content = cont(a) with the sign of lc(a) (0 for a = 0), the f_i primitive
+ * with positive leading coefficients, square-free and pairwise coprime,
+ * m_1 < m_2 < ....  Each step of Yun's algorithm is one modular gcd
+ * (snc_gcd_z) whose lifted cofactors give the exact quotients.
+ * plan: deg_bound = deg a, out_nlimbs = limbs per output coefficient (a bound
+ * for every factor and the content), workspace_bytes = device workspace for
+ * the steps.  run: content receives nlimbs limbs; the factors' coefficients
+ * (ascending) go to limbs, concatenated, factor i taking degs[i] + 1
+ * coefficients of nlimbs limbs each; mults[i] is its multiplicity;
+ * *nfactors their number.  cap_coefs = 2 deg a + 1 and max_factors = deg a
+ * always suffice; smaller capacities give SNC_ERANGE with *nfactors set.
+ * SNC_ENOMEM if a step needs more workspace (the message says how much). */
+int snc_sqfree_plan(const snc_upoly* a, snc_plan* out);
+int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, int32_t nlimbs,
+               uint32_t* content, uint32_t* limbs, int32_t cap_coefs, int32_t* degs, int32_t* mults,
+               int32_t max_factors, int32_t* nfactors);
+
 /* ---- gcd in Z[x] ---------------------------------------------------------
  * Modular (small primes) gcd: contents on the host, monic gcd and cofactors
  * mod each prime on the device, primes of minimal gcd degree kept, CRT, and

@@ -124,3 +124,33 @@ def certify_gcd(a, b, G) -> bool:
 def squarefree_part_sqfree(R, G):
     """R / G for G = gcd(R, R') (the square-free part up to content)."""
     return zx.divexact(R, G)
+
+
+def sqfree_zx(a):
+    """Square-free factorisation in Z[x]: a = c * prod_k f_k^k with c = cont(a)
+    carrying the sign of lc(a), the f_k primitive with positive leading
+    coefficients, square-free and pairwise coprime (the decomposition the
+    projection step of Section 2.1 takes of R).  Computed from repeated gcds
+    with the derivative: D_0 = pp(a), D_k = gcd(D_{k-1}, D_{k-1}'), so
+    D_k = prod_{i > k} f_i^{i-k}; E_k = D_{k-1} / D_k = prod_{i >= k} f_i and
+    f_k = E_k / E_{k+1}.  Returns (c, [(f_k, k), ...]) for the f_k of positive
+    degree, k increasing; (0, []) for a = 0."""
+    a = zx.trim(list(a))
+    if not a:
+        return 0, []
+    c = zx.content(a)
+    if a[-1] < 0:
+        c = -c
+    P = [x // c for x in a]
+    if len(P) == 1:
+        return c, []
+    D = [P]
+    while len(D[-1]) > 1:
+        D.append(gcd_zx(D[-1], zx.deriv(D[-1])))
+    E = [zx.divexact(D[k - 1], D[k]) for k in range(1, len(D))] + [[1]]
+    out = []
+    for k in range(1, len(D)):
+        f = zx.divexact(E[k - 1], E[k])
+        if len(f) > 1:
+            out.append((f, k))
+    return c, out

@@ -87,6 +87,9 @@ def lib():
                 "snc_prepared_run_sqfree": (C.c_int, [VP, VP, SZ, VP, P(Upoly), P(Upoly)]),
                 "snc_gcd_z_batch": (C.c_int, [VP, I32, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
+                "snc_sqfree_plan": (C.c_int, [P(Upoly), P(Plan)]),
+                "snc_sqfree": (C.c_int, [VP, P(Upoly), VP, SZ, VP, I32, P(C.c_uint32), P(C.c_uint32), I32,
+                                         P(I32), P(I32), I32, P(I32)]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(L, name, None)
@@ -543,6 +546,44 @@ def gcd_z_deriv(a, ctx: Context | None = None, stream=None) -> list:
                                                         C.c_size_t(ws.numel()), sh, C.byref(u)),
                     lambda p: lib().snc_gcd_z_deriv_plan(C.byref(ua), C.byref(p)))
     return limbs_to_ints(rows) if len(rows) else []
+
+
+def sqfree_factor(a, ctx: Context | None = None, stream=None):
+    """Square-free factorisation of a in Z[x] (snc_sqfree, Yun's algorithm):
+    returns (content, [(f_1, m_1), (f_2, m_2), ...]) with
+    a = content * prod f_i^m_i, the f_i primitive with positive leading
+    coefficients, square-free and pairwise coprime, m_1 < m_2 < ...
+    (polynomials as lists of Python ints, ascending)."""
+    ctx = ctx or default_context()
+    keep = []
+    ua = _as_upoly(a, keep)
+    p = Plan()
+    ctx.check(lib().snc_sqfree_plan(C.byref(ua), C.byref(p)), "snc_sqfree_plan")
+    d, nl = max(p.deg_bound, 0), max(p.out_nlimbs, 1)
+    cap, maxf = 2 * d + 1, max(d, 1)
+    content = np.zeros(nl, dtype=np.uint32)
+    limbs = np.zeros((cap, nl), dtype=np.uint32)
+    degs = np.zeros(maxf, dtype=np.int32)
+    mults = np.zeros(maxf, dtype=np.int32)
+    nf = C.c_int32(0)
+    sh = ctx.stream_handle(stream)
+    U32, I32 = C.POINTER(C.c_uint32), C.POINTER(C.c_int32)
+    need = p.workspace_bytes
+    for _ in range(3):
+        ws = ctx.workspace(need)
+        st = lib().snc_sqfree(ctx.h, C.byref(ua), C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()), sh, nl,
+                              content.ctypes.data_as(U32), limbs.ctypes.data_as(U32), cap,
+                              degs.ctypes.data_as(I32), mults.ctypes.data_as(I32), maxf, C.byref(nf))
+        if st != SNC_ENOMEM:
+            break
+        need = 4 * max(need, ws.numel())
+    ctx.check(st, "snc_sqfree")
+    out, pos = [], 0
+    for i in range(nf.value):
+        n = int(degs[i]) + 1
+        out.append((limbs_to_ints(limbs[pos:pos + n]), int(mults[i])))
+        pos += n
+    return limbs_to_ints(content[None, :])[0], out
 
 
 class Server:

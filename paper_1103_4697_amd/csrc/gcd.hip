@@ -197,6 +197,43 @@ UPoly normalise_sign(UPoly P) {
   return P;
 }
 
+void trim(UPoly& P) {
+  while (!P.c.empty() && P.c.back().is_zero()) P.c.pop_back();
+}
+
+// exact quotient num / den of integers known to divide; false if they do not
+bool div_exact(const BigInt& num, const BigInt& den, BigInt& q) {
+  BigInt r;
+  BigInt::divmod(num, den, q, r);
+  return r.is_zero();
+}
+
+// every coefficient times mul, divided exactly by den
+bool scale_exact(const UPoly& A, const BigInt& mul, const BigInt& den, UPoly& Q) {
+  Q.c.resize(A.c.size());
+  for (size_t j = 0; j < A.c.size(); ++j)
+    if (!div_exact(A.c[j] * mul, den, Q.c[j])) return false;
+  trim(Q);
+  return true;
+}
+
+// cofactors A / G, B / G of a gcd computed on the host (a zero or constant operand)
+bool trivial_cofactors(const UPoly& A, const UPoly& B, const UPoly& G, UPoly& qa, UPoly& qb) {
+  qa.c.clear();
+  qb.c.clear();
+  if (G.c.empty()) return A.c.empty() && B.c.empty();  // gcd(0, 0) = 0: cofactors 0
+  if (G.deg() == 0) {
+    const BigInt one = BigInt::from_u64(1);
+    return scale_exact(A, one, G.c[0], qa) && scale_exact(B, one, G.c[0], qb);
+  }
+  // G = +-(the non-zero operand), the other one is zero
+  const UPoly& N = A.c.empty() ? B : A;
+  UPoly& qn = A.c.empty() ? qb : qa;
+  qn.c = {BigInt::from_u64(1)};
+  if (N.c.back().neg != G.c.back().neg) qn.c[0] = -qn.c[0];
+  return true;
+}
+
 double bits_needed_full(const GcdInfo& I, int e) {
   const double bw = I.lbeta + e + std::min(I.l2a, I.l2b) + std::log2(e + 1.0);
   const double bu = (I.da - e) + I.l2a + std::log2(I.da - e + 1.0);
@@ -423,6 +460,8 @@ struct GcdProb {
   UPoly A, B;
   GcdInfo I;
   snc_upoly* out = nullptr;
+  UPoly* cofa = nullptr;  // optional: a / gcd and b / gcd (exact), host big integers
+  UPoly* cofb = nullptr;
   bool done = false, parsed = false;
   int K = 0, T = 0, wl = 0, lg = 0, cls = 0;
   size_t nmax = 0;
@@ -607,6 +646,10 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       st = write_upoly(p.I.triv, p.out, ctx->err);
       if (st == SNC_ERANGE) { short_out = true; continue; }
       if (st) return st;
+      if (p.cofa && !trivial_cofactors(p.A, p.B, p.I.triv, *p.cofa, *p.cofb)) {
+        ctx->err = "gcd: inexact cofactor";
+        return SNC_EINTERNAL;
+      }
       p.done = true;
     } else if (p.out->deg < p.Q.deg_bound || p.out->nlimbs < p.Q.out_nlimbs || !p.out->limbs) {
       p.out->deg = p.Q.deg_bound;
@@ -745,6 +788,11 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         R.c = {p.I.c};
         const int st = write_upoly(R, p.out, ctx->err);
         if (st) return st;
+        const BigInt one = BigInt::from_u64(1);
+        if (p.cofa && !(scale_exact(p.A, one, p.I.c, *p.cofa) && scale_exact(p.B, one, p.I.c, *p.cofb))) {
+          ctx->err = "gcd: inexact cofactor";
+          return SNC_EINTERNAL;
+        }
         p.done = true;
         --active;
         continue;
@@ -819,6 +867,15 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
         }
         const int st = write_upoly(normalise_sign(R), p.out, ctx->err);
         if (st) return st;
+        if (p.cofa) {
+          // beta abar = w u with w = cw pp(w) and gcd = c pp(w) (lc(w) = beta > 0):
+          // a / gcd = u cont(a) cw / (c beta), b / gcd = v cont(b) cw / (c beta)
+          const BigInt den = p.I.c * p.I.beta;
+          if (!(scale_exact(U, p.I.ca * cw, den, *p.cofa) && scale_exact(V, p.I.cb * cw, den, *p.cofb))) {
+            ctx->err = "gcd: inexact cofactor";
+            return SNC_EINTERNAL;
+          }
+        }
         p.done = true;
         --active;
         continue;
@@ -840,7 +897,8 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
 }
 
 static int gcd_run(snc_ctx* ctx, int n, const snc_upoly* a, const snc_upoly* b, bool deriv, void* d_ws,
-                   size_t ws_bytes, hipStream_t stream, snc_upoly* out) {
+                   size_t ws_bytes, hipStream_t stream, snc_upoly* out, UPoly* cofa = nullptr,
+                   UPoly* cofb = nullptr) {
   HIPCHK(hipSetDevice(ctx->device));
   GcdTimer tm(ctx, stream);
   std::vector<GcdProb> P(n);
@@ -848,6 +906,7 @@ static int gcd_run(snc_ctx* ctx, int n, const snc_upoly* a, const snc_upoly* b, 
     P[i].a = &a[i];
     P[i].b = deriv ? nullptr : &b[i];
     P[i].out = &out[i];
+    if (cofa && cofb) { P[i].cofa = &cofa[i]; P[i].cofb = &cofb[i]; }
     const int st = quick_scan(P[i].a, P[i].b, deriv, P[i].Q, ctx->err);
     if (st) return st;
   }
@@ -1158,6 +1217,152 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
   return SNC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Square-free factorisation by Yun's algorithm (Section 2.1: the square-free
+// part of R and the multiplicities of its roots).  With P the primitive part
+// of a (positive leading coefficient):
+//   g = gcd(P, P'),  b_1 = P / g,  c_1 = P' / g;
+//   for i = 1, 2, ...: d_i = c_i - b_i',  f_i = gcd(b_i, d_i),
+//                      b_{i+1} = b_i / f_i,  c_{i+1} = d_i / f_i,
+// until b_i is constant; P = prod f_i^i, the f_i square-free and pairwise
+// coprime.  Every step is one modular gcd (the batched driver above) and
+// its exact quotients are the cofactors that the driver's certificate
+// already lifted, so no division of polynomials is done.
+// ---------------------------------------------------------------------------
+static void to_limbs(const UPoly& A, std::vector<uint32_t>& buf, snc_upoly& u) {
+  int nl = 1;
+  for (const auto& x : A.c) nl = std::max(nl, x.twos_limbs());
+  buf.assign(std::max<size_t>(A.c.size(), 1) * nl, 0u);
+  for (size_t j = 0; j < A.c.size(); ++j) (void)A.c[j].to_twos(buf.data() + j * nl, nl);
+  u = snc_upoly{buf.data(), A.deg(), nl};
+}
+
+static UPoly poly_sub(const UPoly& A, const UPoly& B) {
+  UPoly R;
+  R.c.resize(std::max(A.c.size(), B.c.size()));
+  for (size_t j = 0; j < R.c.size(); ++j) {
+    if (j < A.c.size() && j < B.c.size()) R.c[j] = A.c[j] - B.c[j];
+    else if (j < A.c.size()) R.c[j] = A.c[j];
+    else R.c[j] = -B.c[j];
+  }
+  trim(R);
+  return R;
+}
+
+// gcd(a, b) and the exact cofactors a / gcd, b / gcd
+static int gcd_with_cofactors(snc_ctx* ctx, const UPoly& a, const UPoly& b, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream, UPoly& g, UPoly& qa, UPoly& qb) {
+  std::vector<uint32_t> la, lb;
+  snc_upoly ua, ub;
+  to_limbs(a, la, ua);
+  to_limbs(b, lb, ub);
+  snc_plan pl{};
+  int st = gcd_plan(1, &ua, &ub, false, nullptr, &pl);
+  if (st) return st;
+  std::vector<uint32_t> lo((size_t)(std::max(pl.deg_bound, 0) + 1) * pl.out_nlimbs, 0u);
+  snc_upoly uo{lo.data(), pl.deg_bound, pl.out_nlimbs};
+  st = gcd_run(ctx, 1, &ua, &ub, false, d_ws, ws_bytes, stream, &uo, &qa, &qb);
+  if (st) return st;
+  int nl = 1;
+  return parse_upoly(&uo, g, nl, ctx->err);
+}
+
+struct SqfResult {
+  BigInt content;
+  std::vector<UPoly> f;
+  std::vector<int> m;
+};
+
+static int sqfree_run(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                      SqfResult& R) {
+  R = SqfResult();
+  UPoly A;
+  int nl = 1;
+  int st = parse_upoly(a, A, nl, ctx->err);
+  if (st) return st;
+  if (A.c.empty()) return SNC_OK;  // zero: content 0, no factors
+  R.content = content(A);
+  if (A.c.back().neg) R.content = -R.content;
+  if (A.deg() == 0) return SNC_OK;
+  UPoly P, dP;
+  if (!scale_exact(A, BigInt::from_u64(1), R.content, P)) { ctx->err = "sqfree: content"; return SNC_EINTERNAL; }
+  derivative(P, dP);
+  UPoly g, b, c;
+  st = gcd_with_cofactors(ctx, P, dP, d_ws, ws_bytes, stream, g, b, c);
+  if (st) return st;
+  for (int i = 1; b.deg() > 0; ++i) {
+    if (i > P.deg()) { ctx->err = "sqfree: multiplicity above the degree"; return SNC_EINTERNAL; }
+    UPoly db;
+    derivative(b, db);
+    const UPoly d = poly_sub(c, db);
+    UPoly f, bn, cn;
+    st = gcd_with_cofactors(ctx, b, d, d_ws, ws_bytes, stream, f, bn, cn);
+    if (st) return st;
+    if (f.deg() > 0) { R.f.push_back(f); R.m.push_back(i); }
+    b = std::move(bn);
+    c = std::move(cn);
+  }
+  return SNC_OK;
+}
+
+// sizes of a gcd problem from bounds: degrees da, db, coefficients below 2^ba, 2^bb
+static void bound_quick(int da, int db, double ba, double bb, Quick& Q) {
+  Q = Quick();
+  Q.da = da;
+  Q.db = db;
+  Q.nla = (int)std::ceil((ba + 1.0) / 32.0) + 1;
+  Q.nlb = (int)std::ceil((bb + 1.0) / 32.0) + 1;
+  Q.nl = std::max(Q.nla, Q.nlb);
+  Q.trivial = da <= 0 || db <= 0;
+  if (Q.trivial) { Q.deg_bound = 0; Q.out_nlimbs = Q.nl; return; }
+  const double la = std::log2(da + 1.0), lbn = std::log2(db + 1.0);
+  Q.l2[0] = ba + 0.5 * la; Q.l1[0] = ba + la; Q.llc[0] = ba;
+  Q.l2[1] = bb + 0.5 * lbn; Q.l1[1] = bb + lbn; Q.llc[1] = bb;
+  GcdInfo sz;
+  sz.da = da; sz.db = db;
+  sz.l2a = Q.l2[0]; sz.l1a = Q.l1[0]; sz.l2b = Q.l2[1]; sz.l1b = Q.l1[1];
+  sz.lbeta = std::min(Q.llc[0], Q.llc[1]);
+  Q.deg_bound = std::min(da, db);
+  Q.out_nlimbs = (int)std::ceil((Q.deg_bound + std::min(Q.l2[0], Q.l2[1]) + 3.0) / 32.0) + 1;
+  double worst = 0.0;
+  for (int e : {0, Q.deg_bound}) worst = std::max(worst, bits_needed_full(sz, e));
+  Q.kmax = std::min(KMAX, std::max(primes_for_bits(worst), primes_for_bits(bits_needed_opt(sz))) + 12);
+  Q.target0 = std::min(Q.kmax, std::max(3, primes_for_bits(bits_needed_opt(sz)) + 2));
+}
+
+static int sqfree_plan(const snc_upoly* a, snc_plan* out) {
+  std::string err;
+  int st = check_upoly(a, err);
+  if (st) return st;
+  *out = snc_plan{};
+  const int d = trimmed_degree(a);
+  out->deg_bound = std::max(d, 0);
+  out->out_nlimbs = a->deg >= 0 ? a->nlimbs : 1;
+  out->workspace_bytes = 256;
+  if (d < 1) return SNC_OK;
+  snc_plan p0{};  // the first step, gcd(a, a'), on a's own sizes
+  st = gcd_plan(1, a, nullptr, true, nullptr, &p0);
+  if (st) return st;
+  // later steps: b_i divides a, d_i = c_i - b_i' with c_i dividing a' (Mignotte: a factor of degree e
+  // of a has coefficients below 2^e ||a||_2)
+  double l2 = 0, l1 = 0, llc = 0;
+  limb_norms(a->limbs, a->nlimbs, d, false, l2, l1, llc);
+  const double ba = d + l2 + 1.0, bd = d + l2 + 2.0 * std::log2(d + 1.0) + 2.0;
+  Quick Q;
+  bound_quick(d, d - 1, ba, bd, Q);
+  size_t w1 = 0;
+  if (!Q.trivial) {
+    std::vector<GcdProb> one(1);
+    one[0].Q = Q;
+    GcdBatchLayout L1;
+    layout_batch(one, L1);
+    w1 = L1.total * 4;
+  }
+  out->workspace_bytes = std::max<size_t>({p0.workspace_bytes, w1, 256});
+  out->out_nlimbs = std::max(out->out_nlimbs, (int)std::ceil((ba + 1.0) / 32.0) + 1);
+  return SNC_OK;
+}
+
 }  // namespace snc
 
 using namespace snc;
@@ -1203,6 +1408,42 @@ int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, v
 int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
   if (!out || !a) return SNC_EINVAL;
   return gcd_plan(1, a, nullptr, true, nullptr, out);
+}
+
+int snc_sqfree_plan(const snc_upoly* a, snc_plan* out) {
+  if (!a || !out) return SNC_EINVAL;
+  return sqfree_plan(a, out);
+}
+
+int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, int32_t nlimbs,
+               uint32_t* content, uint32_t* limbs, int32_t cap_coefs, int32_t* degs, int32_t* mults,
+               int32_t max_factors, int32_t* nfactors) {
+  if (!ctx || !a || !content || !nfactors || nlimbs < 1 || cap_coefs < 0 || max_factors < 0) return SNC_EINVAL;
+  if (max_factors > 0 && (!degs || !mults)) return SNC_EINVAL;
+  if (cap_coefs > 0 && !limbs) return SNC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  SqfResult R;
+  int st = sqfree_run(ctx, a, d_ws, ws_bytes, (hipStream_t)stream, R);
+  if (st) return st;
+  *nfactors = (int32_t)R.f.size();
+  size_t need = 0;
+  for (const auto& f : R.f) need += f.c.size();
+  if ((int32_t)R.f.size() > max_factors || need > (size_t)cap_coefs) {
+    ctx->err = "sqfree: output capacity too small (" + std::to_string(R.f.size()) + " factors, " +
+               std::to_string(need) + " coefficients)";
+    return SNC_ERANGE;
+  }
+  if (!R.content.to_twos(content, nlimbs)) { ctx->err = "sqfree: content exceeds nlimbs"; return SNC_ERANGE; }
+  size_t pos = 0;
+  for (size_t i = 0; i < R.f.size(); ++i) {
+    degs[i] = R.f[i].deg();
+    mults[i] = R.m[i];
+    for (const auto& x : R.f[i].c) {
+      if (!x.to_twos(limbs + pos * nlimbs, nlimbs)) { ctx->err = "sqfree: coefficient exceeds nlimbs"; return SNC_ERANGE; }
+      ++pos;
+    }
+  }
+  return SNC_OK;
 }
 
 int snc_gcd_z_deriv(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {

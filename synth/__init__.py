@@ -213,6 +213,23 @@ def gcd_request(rng, target_lo=100, target_hi=2000, h_lo=5, h_hi=50, bits_lo=8, 
     return univariate_product(h, u), univariate_product(h, v), h
 
 
+def sqfree_request(rng, degs=(120, 60, 30), bits=8, content=-6):
+    """Square-free factorisation input a = content * prod_i f_i^i with monic
+    random f_i of the given degrees (coefficients uniform signed `bits`-bit),
+    and the factor list [(f_1, 1), (f_2, 2), ...].  Random f_i of these
+    degrees are square-free and pairwise coprime with overwhelming
+    probability; tests that rely on it check it."""
+    fs = []
+    for d in degs:
+        f = [int(c) for c in uniform_signed(rng, (d,), bits)] + [1]
+        fs.append(f)
+    a = [content]
+    for i, f in enumerate(fs):
+        for _ in range(i + 1):
+            a = univariate_product(a, f)
+    return [int(c) for c in a], [(f, i + 1) for i, f in enumerate(fs)]
+
+
 def config4(nreq: int = 2000):
     """Serving stream: requests mixed 4:1 resultant : gcd.  Resultant
     requests have total degrees ~ U{10..50} and coefficient bits ~ U{8..64};

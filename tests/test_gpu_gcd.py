@@ -308,3 +308,47 @@ def test_sqfree_check_large_degree(snc):
     assert stages["sqfree_euclid"] > 0              # (pair, prime) items of the fused check
     batch.run_sqfree()                             # replay of the captured pipeline
     assert batch.sqfree_results() == G_all
+
+
+def test_sqfree_factor_against_oracle(snc):
+    """snc_sqfree (Yun's algorithm on the modular gcd with lifted cofactors)
+    against the oracle's repeated-gcd factorisation: random products of
+    powers with contents and signs, special cases, and the projection
+    resultant of the small curve workload."""
+    rng = random.Random(41)
+    cases = [[], [7], [-12], [0, 1], [-2, 2], [0, 0, 0, 5], zx.power([1, 1], 5),
+             zx.mul([0, -3], zx.power([1, 0, 1], 2))]
+    for _ in range(10):
+        a = [rng.choice([1, -1, 6, -10])]
+        for _ in range(rng.randint(1, 4)):
+            a = zx.mul(a, zx.power(rpoly(rng, rng.randint(1, 6), 12), rng.randint(1, 4)))
+        cases.append(a)
+    f, g = synth.config0()
+    r = snc.resultant_y(f, g)
+    cases += [r, zx.mul(r, r), zx.mul(zx.power([3, 1], 3), r)]
+    for a in cases:
+        assert snc.sqfree_factor(a) == G.sqfree_zx(a), a[:4]
+
+
+def test_sqfree_factor_large_by_construction(snc):
+    """a = -6 f1 f2^2 f3^3 with f1, f2, f3 of degrees 120, 60, 30 (total degree
+    330): the factorisation is known once the f_i are square-free and
+    pairwise coprime, which is checked mod a prime."""
+    rng = random.Random(57)
+    p = 1000003
+    fs = []
+    for d in (120, 60, 30):
+        while True:
+            f = [rng.randint(-40, 40) for _ in range(d)] + [1]
+            if igcd(*f) != 1:
+                continue
+            if _gcd_mod_p(f, zx.deriv(f), p) != [1] or any(_gcd_mod_p(f, h, p) != [1] for h in fs):
+                continue
+            fs.append(f)
+            break
+    a = [-6]
+    for i, f in enumerate(fs):
+        a = zx.mul(a, zx.power(f, i + 1))
+    c, got = snc.sqfree_factor(a)
+    assert c == -6
+    assert got == [(fs[0], 1), (fs[1], 2), (fs[2], 3)]
