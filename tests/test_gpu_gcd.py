@@ -323,11 +323,18 @@ def test_sqfree_factor_against_oracle(snc):
         for _ in range(rng.randint(1, 4)):
             a = zx.mul(a, zx.power(rpoly(rng, rng.randint(1, 6), 12), rng.randint(1, 4)))
         cases.append(a)
-    f, g = synth.config0()
-    r = snc.resultant_y(f, g)
-    cases += [r, zx.mul(r, r), zx.mul(zx.power([3, 1], 3), r)]
     for a in cases:
         assert snc.sqfree_factor(a) == G.sqfree_zx(a), a[:4]
+    # the small curve workload's resultant against the oracle; its square and
+    # (x + 3)^3 r by construction from that (the oracle's gcds over Q are slow there)
+    f, g = synth.config0()
+    r = snc.resultant_y(f, g)
+    c, fr = G.sqfree_zx(r)
+    assert snc.sqfree_factor(r) == (c, fr)
+    assert snc.sqfree_factor(zx.mul(r, r)) == (c * c, [(h, 2 * m) for h, m in fr])
+    if all(zx.evaluate(h, -3) != 0 for h, _ in fr) and all(m != 3 for _, m in fr):
+        want = sorted(fr + [([3, 1], 3)], key=lambda t: t[1])
+        assert snc.sqfree_factor(zx.mul(zx.power([3, 1], 3), r)) == (c, want)
 
 
 def test_sqfree_factor_large_by_construction(snc):
