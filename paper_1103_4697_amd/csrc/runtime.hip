@@ -122,20 +122,31 @@ static bool coef_is_zero(const uint32_t* c, int nl) {
   return true;
 }
 
-// |c| as a double (upper-rounded later by the caller's margin)
-static double coef_abs_double(const uint32_t* c, int nl) {
+// log2 |c| of a non-zero two's-complement coefficient, from its top three
+// magnitude limbs (the rest adds less than one unit of the third limb, which
+// the caller's margin covers); no overflow at any size
+static double coef_log2_abs(const uint32_t* c, int nl) {
   const bool neg = c[nl - 1] >> 31;
-  double v = 0.0;
-  if (!neg) {
-    for (int l = nl - 1; l >= 0; --l) v = v * 4294967296.0 + (double)c[l];
-    return v;
+  std::vector<uint32_t> m(c, c + nl);
+  if (neg) {  // magnitude = ~c + 1
+    uint64_t carry = 1;
+    for (int l = 0; l < nl; ++l) { uint64_t t = (uint64_t)(~c[l]) + carry; m[l] = (uint32_t)t; carry = t >> 32; }
   }
-  // magnitude = ~c + 1
-  uint64_t carry = 1;
-  std::vector<uint32_t> m(nl);
-  for (int l = 0; l < nl; ++l) { uint64_t t = (uint64_t)(~c[l]) + carry; m[l] = (uint32_t)t; carry = t >> 32; }
-  for (int l = nl - 1; l >= 0; --l) v = v * 4294967296.0 + (double)m[l];
-  return v;
+  int t = nl - 1;
+  while (t > 0 && m[t] == 0) --t;
+  double v = 0.0;
+  int used = 0;
+  for (int l = t; l >= 0 && used < 3; --l, ++used) v = v * 4294967296.0 + (double)m[l];
+  return std::log2(v + 1.0) + 32.0 * (t + 1 - used);
+}
+
+// log2 of a sum of 2^x over xs (xs non-empty)
+static double log2_sum_exp2(const std::vector<double>& xs) {
+  double mx = xs[0];
+  for (double x : xs) mx = std::max(mx, x);
+  double s = 0.0;
+  for (double x : xs) s += std::exp2(x - mx);
+  return mx + std::log2(s);
 }
 
 int parse_bipoly(const snc_bipoly* f, Operand& op, std::string& err) {
@@ -146,18 +157,22 @@ int parse_bipoly(const snc_bipoly* f, Operand& op, std::string& err) {
   if (f->dx < 0 || f->nlimbs < 1 || !f->limbs) { err = "invalid bivariate polynomial (dx < 0, nlimbs < 1 or NULL limbs)"; return SNC_EINVAL; }
   op.rowdeg.assign(f->dy + 1, -1);
   op.ydeg = -1;
-  double S = 0.0;
+  // log2 of S = sum_i ||f_i||_1^2, summed in the log domain (coefficients of any size)
+  std::vector<double> rows2;  // 2 log2 ||f_i||_1 of the non-zero rows
+  std::vector<double> lc;
   for (int i = 0; i <= f->dy; ++i) {
-    double norm1 = 0.0;
+    lc.clear();
     for (int k = 0; k <= f->dx; ++k) {
       const uint32_t* c = f->limbs + ((size_t)i * (f->dx + 1) + k) * f->nlimbs;
       if (!coef_is_zero(c, f->nlimbs)) {
         op.rowdeg[i] = k;
-        norm1 += coef_abs_double(c, f->nlimbs);
+        lc.push_back(coef_log2_abs(c, f->nlimbs));
       }
     }
-    if (op.rowdeg[i] >= 0) op.ydeg = i;
-    S += norm1 * norm1;
+    if (op.rowdeg[i] >= 0) {
+      op.ydeg = i;
+      rows2.push_back(2.0 * log2_sum_exp2(lc));
+    }
   }
   op.rowdeg.resize(op.ydeg + 1);
   op.total_deg = -1;
@@ -167,8 +182,8 @@ int parse_bipoly(const snc_bipoly* f, Operand& op, std::string& err) {
     op.total_deg = std::max(op.total_deg, i + op.rowdeg[i]);
     op.max_rowdeg = std::max(op.max_rowdeg, op.rowdeg[i]);
   }
-  // relative error of the double sums is far below 1e-9; the margin makes it an upper bound
-  op.log2S = op.ydeg >= 0 ? std::log2(S) + 1e-9 : 0.0;
+  // rounding of the log-domain sums is far below 1e-9 bits per term; the margin makes it an upper bound
+  op.log2S = op.ydeg >= 0 ? log2_sum_exp2(rows2) + 1e-9 * (1.0 + std::fabs(log2_sum_exp2(rows2))) : 0.0;
   return SNC_OK;
 }
 

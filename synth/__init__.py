@@ -213,6 +213,24 @@ def gcd_request(rng, target_lo=100, target_hi=2000, h_lo=5, h_hi=50, bits_lo=8, 
     return univariate_product(h, u), univariate_product(h, v), h
 
 
+def bigcoef_curve(rng, d: int, bits: int):
+    """Dense f of total degree d with uniform signed coefficients of up to
+    `bits` bits (any size: Python ints), and g = df/dy.  Lists of rows, row i
+    the coefficient of y^i as a polynomial in x (ascending)."""
+    def coef():
+        words = [int(w) for w in rng.integers(0, 1 << 32, size=(bits + 31) // 32, dtype=np.uint64)]
+        v = 0
+        for w in words:
+            v = (v << 32) | w
+        v &= (1 << (bits - 1)) - 1
+        return -v if rng.integers(0, 2) else v
+    f = [[coef() if i + k <= d else 0 for k in range(d + 1)] for i in range(d + 1)]
+    while f[d][0] == 0:
+        f[d][0] = coef()
+    g = [[(i + 1) * c for c in f[i + 1]] for i in range(d)]
+    return f, g
+
+
 def sqfree_request(rng, degs=(120, 60, 30), bits=8, content=-6):
     """Square-free factorisation input a = content * prod_i f_i^i with monic
     random f_i of the given degrees (coefficients uniform signed `bits`-bit),

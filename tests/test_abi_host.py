@@ -81,10 +81,12 @@ def test_prime_table(snc):
     assert snc.prime(-1) == 0 and snc.prime(1024) == 0
 
 
-@pytest.mark.parametrize("which", ["c0", "c1", "c3", "small", "swapped"])
+@pytest.mark.parametrize("which", ["c0", "c1", "c3", "small", "swapped", "big512", "big2048"])
 def test_resultant_plan_bounds(snc, which):
     rng = np.random.default_rng(1)
-    if which == "c0":
+    if which.startswith("big"):  # norms far beyond the range of a double
+        f, g = synth.bigcoef_curve(rng, 6, int(which[3:]))
+    elif which == "c0":
         f, g = synth.config0()
     elif which == "c1":
         f, g = synth.config1()

@@ -218,3 +218,23 @@ def test_interpolation_block_boundaries(snc, da, db):
         batch.run()
         r_fg, r_gf = batch.results()
         assert r_fg == want and r_gf == want  # (-1)^(2*1) = 1
+
+
+@pytest.mark.parametrize("d,bits", [(10, 128), (10, 512), (6, 1024), (4, 2048)])
+def test_multilimb_curves(snc, d, bits):
+    """The paper's 128..2048-bit curves: R = res_y(f, f_y) for dense f of
+    total degree d with bits-bit coefficients, checked on sampled values mod
+    two 61-bit primes against the oracle's determinant at the point, plus the
+    degree bound and a batch replay."""
+    f, g = synth.bigcoef_curve(np.random.default_rng(bits + d), d, bits)
+    plan = snc.resultant_plan(f, g)
+    r = snc.resultant_y(f, g)
+    assert len(r) - 1 <= plan.deg_bound
+    rs = random.Random(bits)
+    for q in (Q61, (1 << 61) - 31):
+        for x0 in (0, 1, plan.deg_bound, rs.randrange(q)):
+            assert zx.evaluate(r, x0) % q == R.resultant_at_mod(f, g, x0, q)
+    batch = snc.ResultantBatch([(f, g)])
+    for _ in range(2):
+        batch.run()
+        assert batch.results()[0] == r
