@@ -19,9 +19,15 @@ __device__ uint32_t g_ptab[(KMAX + 1) * LPS];  // row j: P_j = prod_{l<j} p_l, l
 __global__ void k_interp(const ResJob* jobs, const int64_t* prefix, int njobs, uint32_t* ws, uint32_t* zero_word);
 
 // per-device kernel attributes (called once per device before any launch)
+__global__ void k_crt_combine(CrtTables tb, const ResJob* jobs, const int64_t* prefix, int njobs, int lx_max,
+                              uint32_t* ws);
+
 hipError_t configure_kernels() {
-  return hipFuncSetAttribute((const void*)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024);
+  hipError_t e = hipFuncSetAttribute((const void*)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_crt_combine, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(CRT_COEF_PER_BLOCK * 3 * lx_of(KMAX) * sizeof(uint32_t)));
 }
 
 void upload_tables(const PrimeC* primes, const uint32_t* garner_c, const uint32_t* wtab,
@@ -823,15 +829,17 @@ void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 //     X - M when X > (M-1)/2, decided on the digits ((M-1)/2 has digits
 //     (p_j - 1)/2), written as L two's-complement limbs.
 // ---------------------------------------------------------------------------
-constexpr int CRT_SLOTS = KMAX / 64;
-
 constexpr int CRT_WCH = 8192;  // words of W table rows staged in LDS at a time
+static_assert(KMAX <= CRT_WCH, "one row of W fits the staging buffer");
 
+// NS: prime slots per lane (k <= 64 NS)
+template <int NS>
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTables tb, const ResJob* jobs,
                                                                         const int64_t* prefix,
                                                                         int njobs, uint32_t* ws) {
+  constexpr int CRT_SLOTS = NS;
   __shared__ uint32_t wrows[CRT_WCH];  // rows j0..j0+ch-1 of W, columns 0..k-1
-  __shared__ uint2 lp[KMAX];           // (p, pinv) of the k primes
+  __shared__ uint2 lp[64 * NS];        // (p, pinv) of the k primes
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
@@ -957,10 +965,18 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
 }
 
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, uint32_t* ws, hipStream_t s) {
+                       int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_crt_digits, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), 0, s, tb,
-                     jobs_d, prefix_d, njobs, ws);
+  static_assert(KMAX <= 64 * 48, "the largest slot variant covers the table");
+  const dim3 g((unsigned)nblocks), b(64 * CRT_COEF_PER_BLOCK);
+  if (kmax <= 64)
+    hipLaunchKernelGGL(k_crt_digits<1>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
+  else if (kmax <= 256)
+    hipLaunchKernelGGL(k_crt_digits<4>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
+  else if (kmax <= 1024)
+    hipLaunchKernelGGL(k_crt_digits<16>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
+  else
+    hipLaunchKernelGGL(k_crt_digits<48>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
 }
 
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
@@ -968,6 +984,8 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t
   if (nblocks <= 0) return;
   const int lxm = lx_of(kmax);
   const size_t shmem = (size_t)CRT_COEF_PER_BLOCK * 3 * lxm * sizeof(uint32_t);
+  static_assert((size_t)CRT_COEF_PER_BLOCK * 3 * ((30 * KMAX + 31) / 32 + 2) * 4 <= 160 * 1024,
+                "combination buffers for the whole table fit the LDS of a CU");
   hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), shmem, s, tb, jobs_d,
                      prefix_d, njobs, lxm, ws);
 }

@@ -219,7 +219,7 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   }
   if (part == PIPE_TO_INTERP) return;
   const CrtTables tb = global_crt_tables();
-  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
+  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, lay.max_k, wsw, s);
   if (tm) tm->mark("crt_digits", 1);
   launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, lay.max_k, wsw, s);
   if (tm) tm->mark("crt_combine", 1);

@@ -7,8 +7,8 @@
 
 namespace snc {
 
-constexpr int KMAX = 1024;        // primes in the modulus table (log2 of their product ~ 30700)
-constexpr int LPS = 964;          // limb stride of the prime-product table (30*1024/32 + 4)
+constexpr int KMAX = 3072;        // primes in the modulus table (log2 of their product ~ 92100)
+constexpr int LPS = 2884;         // limb stride of the prime-product table (30*3072/32 + 4)
 constexpr int MAXY_FAST = 64;     // largest y-degree handled by the register-resident elimination
 constexpr int MAXY_GEN = 255;     // largest y-degree handled at all
 constexpr int EE_WAVES = 1;       // wavefronts per eval_elim workgroup
@@ -141,8 +141,9 @@ void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
 // the interpolation launches also clear zero_word (the abnormal-instance counter)
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s);
+// kmax: the largest prime count among the jobs (sizes the per-lane digit slots)
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, uint32_t* ws, hipStream_t s);
+                       int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
                         int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)

@@ -72,20 +72,21 @@ def is_prime(n):
 
 
 def test_prime_table(snc):
-    ps = [snc.prime(i) for i in range(1024)]
-    assert ps == sorted(ps, reverse=True) and len(set(ps)) == 1024
+    ps = [snc.prime(i) for i in range(3072)]
+    assert ps == sorted(ps, reverse=True) and len(set(ps)) == 3072
     assert all(2 ** 29 < p < 2 ** 30 for p in ps)
     assert all(is_prime(p) for p in ps[:64] + ps[-64:])
     # no prime of the range above the last one is skipped
     assert all(not is_prime(n) for n in range(ps[0] + 2, 2 ** 30, 2))
-    assert snc.prime(-1) == 0 and snc.prime(1024) == 0
+    assert snc.prime(-1) == 0 and snc.prime(3072) == 0
 
 
-@pytest.mark.parametrize("which", ["c0", "c1", "c3", "small", "swapped", "big512", "big2048"])
+@pytest.mark.parametrize("which", ["c0", "c1", "c3", "small", "swapped", "big512", "big2048", "big2048d15"])
 def test_resultant_plan_bounds(snc, which):
     rng = np.random.default_rng(1)
     if which.startswith("big"):  # norms far beyond the range of a double
-        f, g = synth.bigcoef_curve(rng, 6, int(which[3:]))
+        d = 15 if which.endswith("d15") else 6
+        f, g = synth.bigcoef_curve(rng, d, int(which[3:7]))
     elif which == "c0":
         f, g = synth.config0()
     elif which == "c1":

@@ -220,13 +220,18 @@ def test_interpolation_block_boundaries(snc, da, db):
         assert r_fg == want and r_gf == want  # (-1)^(2*1) = 1
 
 
-@pytest.mark.parametrize("d,bits", [(10, 128), (10, 512), (6, 1024), (4, 2048)])
-def test_multilimb_curves(snc, d, bits):
-    """The paper's 128..2048-bit curves: R = res_y(f, f_y) for dense f of
-    total degree d with bits-bit coefficients, checked on sampled values mod
-    two 61-bit primes against the oracle's determinant at the point, plus the
-    degree bound and a batch replay."""
-    f, g = synth.bigcoef_curve(np.random.default_rng(bits + d), d, bits)
+@pytest.mark.parametrize("d,bits,pair", [(10, 128, False), (10, 512, False), (6, 1024, False), (4, 2048, False),
+                                         (9, 2048, False), (15, 2048, False), (15, 2048, True)])
+def test_multilimb_curves(snc, d, bits, pair):
+    """The paper's 128..2048-bit random curves: R = res_y(f, f_y) (or
+    res_y(f, h) of two such curves) for dense f of total degree d with
+    bits-bit coefficients, checked on sampled values mod two 61-bit primes
+    against the oracle's determinant at the point, plus the degree bound and
+    a batch replay.  Degree 15 at 2048 bits needs about 2000 primes."""
+    rng = np.random.default_rng(bits + d)
+    f, g = synth.bigcoef_curve(rng, d, bits)
+    if pair:
+        g, _ = synth.bigcoef_curve(rng, d, bits)
     plan = snc.resultant_plan(f, g)
     r = snc.resultant_y(f, g)
     assert len(r) - 1 <= plan.deg_bound
