@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sqfree", action="store_true")
+    ap.add_argument("--no-curve-sets", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
@@ -341,6 +342,29 @@ def main():
                           "plain_resultants_per_s": round(1.0 / pt, 2),
                           "speedup": round((len(pairs) / bt) * pt, 3),
                           "batched_ms": round(bt * 1e3, 3)}
+
+    if not args.no_curve_sets:
+        progress("random curve sets")
+        sets = {}
+        for d in (6, 9, 12, 15):
+            for bits in (10, 128, 512, 2048):
+                pairs = synth.random_curve_set(np.random.default_rng(100 * d + bits), d, bits)
+                bs = snc.ResultantBatch(pairs, ctx)
+                bs.run()
+                torch.cuda.synchronize()
+                nrep = 3
+                t0 = time.perf_counter()
+                for _ in range(nrep):
+                    bs.run()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) / nrep * 1e3
+                kmax = max(snc.resultant_plan(*pr).nprimes for pr in pairs)
+                sets[f"d{d}_b{bits}"] = {"ms": round(ms, 3), "max_primes": kmax}
+                progress(f"curve set degree {d}, {bits} bits: {ms:.3f} ms ({kmax} primes)")
+        out["random_curve_sets"] = {"workload": "five random dense curves of total degree d with signed b-bit "
+                                                "coefficients: res_y(f, f_y) of each and res_y(f, h) of every "
+                                                "pair (15 resultants) in one batch",
+                                    "sets": sets}
 
     if not args.no_sqfree:
         progress("square-free factorisation")

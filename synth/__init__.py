@@ -231,6 +231,16 @@ def bigcoef_curve(rng, d: int, bits: int):
     return f, g
 
 
+def random_curve_set(rng, d: int, bits: int, ncurves: int = 5):
+    """The resultants of the projection phase of an arrangement of `ncurves`
+    random dense curves of total degree d with `bits`-bit coefficients:
+    res_y(f, f_y) of every curve, then res_y(f, h) of every pair."""
+    curves = [bigcoef_curve(rng, d, bits) for _ in range(ncurves)]
+    pairs = [(f, fy) for f, fy in curves]
+    pairs += [(curves[i][0], curves[j][0]) for i in range(ncurves) for j in range(i + 1, ncurves)]
+    return pairs
+
+
 def sqfree_request(rng, degs=(120, 60, 30), bits=8, content=-6):
     """Square-free factorisation input a = content * prod_i f_i^i with monic
     random f_i of the given degrees (coefficients uniform signed `bits`-bit),

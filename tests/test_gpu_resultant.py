@@ -243,3 +243,18 @@ def test_multilimb_curves(snc, d, bits, pair):
     for _ in range(2):
         batch.run()
         assert batch.results()[0] == r
+
+
+def test_random_curve_set_batch(snc):
+    """Projection phase of five random degree-9, 512-bit curves in one batch:
+    each curve with its y-derivative and every pair; every result matches the
+    single call and the oracle's determinant at sampled points."""
+    pairs = synth.random_curve_set(np.random.default_rng(7), 9, 512)
+    batch = snc.ResultantBatch(pairs)
+    batch.run()
+    got = batch.results()
+    rs = random.Random(9)
+    for (f, g), r in zip(pairs, got):
+        assert r == snc.resultant_y(f, g)
+        x0 = rs.randrange(Q61)
+        assert zx.evaluate(r, x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
