@@ -827,7 +827,7 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
                         emins[i], ws, (int64_t)p.wv, (int64_t)p.uv, (int64_t)p.vv, stream);
       CrtTables tb{(const PrimeC*)(ws + p.primes), ws + p.garner, ws + p.wtab, ws + p.ptab, ks, p.lg};
       const int64_t* pd = (const int64_t*)(h + p.prefd);
-      launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefd), 3, pd[3], ks, ws, stream);
+      launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefd), 3, pd[3], ws, stream);
       launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefc), 3, pd[3], ks, ws, stream);
     }
     HIPCHK(hipGetLastError());

@@ -71,11 +71,13 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
 constexpr int RED_THREADS = 256;
 
 // signed coefficient of nl two's-complement limbs -> canonical Montgomery residue
-__device__ __forceinline__ uint32_t reduce_limbs(const uint32_t* limbs, int nl, const PrimeC& c) {
-  const uint32_t mask = (limbs[nl - 1] >> 31) ? 0xffffffffu : 0u;
+// limb l of the coefficient at limbs[l stride] (limb-major: neighbouring
+// lanes read neighbouring words)
+__device__ __forceinline__ uint32_t reduce_limbs(const uint32_t* limbs, int nl, int64_t stride, const PrimeC& c) {
+  const uint32_t mask = (limbs[(nl - 1) * stride] >> 31) ? 0xffffffffu : 0u;
   uint32_t acc = 0;
   for (int l = nl - 1; l >= 0; --l) {
-    uint64_t v = (uint64_t)acc * c.r2 + (uint64_t)(limbs[l] ^ mask) * c.r2;
+    uint64_t v = (uint64_t)acc * c.r2 + (uint64_t)(limbs[l * stride] ^ mask) * c.r2;
     acc = redc(v, c.p, c.pinv);
   }
   acc = canon(acc, c.p);
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const ResJob* jobs, cons
   const int t = (int)(lb % nb) * RED_THREADS + threadIdx.x;
   if (t >= J.T) return;
   const PrimeC c = g_primes[pi];
-  wsw[J.res_off + (int64_t)pi * J.T + t] = reduce_limbs(ws + J.coef_off + (int64_t)t * J.nl, J.nl, c);
+  wsw[J.res_off + (int64_t)pi * J.T + t] = reduce_limbs(ws + J.coef_off + t, J.nl, J.T, c);
 }
 
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
       uint32_t* rg = ws + J.res_off + (int64_t)pi * J.T;
       const bool store = lb % npb == 0;
       for (int x = threadIdx.x; x < J.T; x += EE_BLOCK) {
-        const uint32_t v = reduce_limbs(ws + J.coef_off + (int64_t)x * J.nl, J.nl, c);
+        const uint32_t v = reduce_limbs(ws + J.coef_off + x, J.nl, J.T, c);
         er[x] = v;
         if (store) rg[x] = v;
       }
@@ -822,24 +824,26 @@ void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 // ---------------------------------------------------------------------------
 // (5) Chinese remaindering per coefficient.
 //   digits: Garner's mixed-radix digits y_j, X = sum_j y_j P_j, with
-//     y_i = (r_i - sum_{j<i} y_j P_j) (P_i)^-1 mod p_i.  One wavefront per
-//     coefficient; lane l owns primes l, l+64, ...; digit j is broadcast
-//     from its owner lane and every later prime folds it in.
+//     y_i = (r_i - S_i) (P_i)^-1 mod p_i,  S_i = sum_{j<i} y_j P_j mod p_i.
+//     One wavefront per coefficient, primes in blocks of 64 (lane l holds
+//     prime 64 s + l of block s).  In block s the digits come one after
+//     another: digit q is broadcast from lane q and folded into the later
+//     primes of the block.  The finished block then goes to every later
+//     block s2 at once, S_i += sum_q y_{64s+q} (P_{64s+q} mod p_i), four
+//     products per reduction.  S_i waits in digit slot i until digit i is
+//     written there.  The 64 x 64 tiles of W = (P_j mod p_i) are staged in
+//     LDS, double-buffered and shared by the block's wavefronts.
 //   combine: X in binary by Horner over the digits; the balanced value is
 //     X - M when X > (M-1)/2, decided on the digits ((M-1)/2 has digits
 //     (p_j - 1)/2), written as L two's-complement limbs.
 // ---------------------------------------------------------------------------
-constexpr int CRT_WCH = 8192;  // words of W table rows staged in LDS at a time
-static_assert(KMAX <= CRT_WCH, "one row of W fits the staging buffer");
+constexpr int CRT_TILE = 64 * 64;                          // words of one W tile
+constexpr int CRT_PRE = CRT_TILE / (64 * CRT_COEF_PER_BLOCK);  // tile words fetched per thread
 
-// NS: prime slots per lane (k <= 64 NS)
-template <int NS>
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTables tb, const ResJob* jobs,
                                                                         const int64_t* prefix,
                                                                         int njobs, uint32_t* ws) {
-  constexpr int CRT_SLOTS = NS;
-  __shared__ uint32_t wrows[CRT_WCH];  // rows j0..j0+ch-1 of W, columns 0..k-1
-  __shared__ uint2 lp[64 * NS];        // (p, pinv) of the k primes
+  __shared__ uint32_t wt[2][CRT_TILE];  // tile (s, s2): [q][l] = W[64 s + q][64 s2 + l]
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
@@ -847,103 +851,132 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
   const int t = (int)(b - prefix[jj]) * CRT_COEF_PER_BLOCK + wave;
   const bool active = t <= J.D;  // the block's waves share one job; idle ones still meet the barriers
   const int k = J.k;
-  const int ch = min(64, max(1, CRT_WCH / k));
+  const int nsl = (k + 63) >> 6;
   const int n1 = J.D + 1;
   const uint32_t* V = ws + J.val_off;
   uint32_t* dig = ws + J.dig_off + (int64_t)(active ? t : 0) * k;
-  for (int i = threadIdx.x; i < k; i += 64 * CRT_COEF_PER_BLOCK) lp[i] = make_uint2(tb.primes[i].p, tb.primes[i].pinv);
-  uint32_t r[CRT_SLOTS], S[CRT_SLOTS];
+  if (active)
+    for (int i = lane; i < k; i += 64) dig[i] = 0;  // the partial sums S_i start at zero
+  uint32_t pre[CRT_PRE];
+  auto fetch = [&](int s, int s2) {
 #pragma unroll
-  for (int s = 0; s < CRT_SLOTS; ++s) {
-    const int i = lane + 64 * s;
-    r[s] = 0; S[s] = 0;
-    if (active && 64 * s < k && i < k) r[s] = V[(int64_t)i * n1 + t];
-  }
-#pragma unroll
-  for (int s = 0; s < CRT_SLOTS; ++s) {
-    if (64 * s >= k) break;
-    const PrimeC c0 = tb.primes[lane + 64 * s < k ? lane + 64 * s : 0];
-    const uint32_t g0 = tb.garner[lane + 64 * s < k ? lane + 64 * s : 0];
-    for (int q = 0; q < 64; ++q) {
-      const int j = 64 * s + q;
-      if (j >= k) break;
-      const int jr = j % ch;
-      if (jr == 0) {  // stage rows j .. j+ch-1
-        __syncthreads();
-        const int nrow = min(ch, k - j);
-        for (int x = threadIdx.x; x < nrow * k; x += 64 * CRT_COEF_PER_BLOCK) {
-          const int row = x / k, col = x - row * k;
-          wrows[x] = tb.wtab[(int64_t)(j + row) * tb.wstride + col];
-        }
-        __syncthreads();
-      }
-      const uint32_t cand = canon(redc((uint64_t)msub(r[s], S[s], c0.p) * g0, c0.p, c0.pinv), c0.p);
-      const uint32_t y = __builtin_amdgcn_readlane(cand, q);
-      if (active && lane == q) dig[j] = y;
-      const uint32_t* wr = wrows + jr * k;
-#pragma unroll
-      for (int s2 = 0; s2 < CRT_SLOTS; ++s2) {
-        if (64 * s2 >= k) break;
-        if (64 * s2 + 63 <= j) continue;
-        const int i = lane + 64 * s2;
-        if (i > j && i < k) {
-          const uint2 ci = lp[i];
-          S[s2] = madd(S[s2], canon(redc((uint64_t)y * wr[i], ci.x, ci.y), ci.x), ci.x);
-        }
-      }
+    for (int e = 0; e < CRT_PRE; ++e) {
+      const int x = threadIdx.x + e * 64 * CRT_COEF_PER_BLOCK;
+      const int row = 64 * s + (x >> 6), col = 64 * s2 + (x & 63);
+      pre[e] = (row < k && col < k) ? tb.wtab[(int64_t)row * tb.wstride + col] : 0u;
     }
+  };
+  fetch(0, 0);
+  uint32_t ymine = 0;  // digit 64 s + lane of the current block
+  const int ntiles = nsl * (nsl + 1) / 2;
+  int s = 0, s2 = 0;
+  for (int tau = 0; tau < ntiles; ++tau) {
+    uint32_t* w = wt[tau & 1];
+#pragma unroll
+    for (int e = 0; e < CRT_PRE; ++e) w[threadIdx.x + e * 64 * CRT_COEF_PER_BLOCK] = pre[e];
+    __syncthreads();
+    int ns = s, ns2 = s2 + 1;  // the next tile, fetched while this one is worked on
+    if (ns2 == nsl) { ++ns; ns2 = ns; }
+    if (tau + 1 < ntiles) fetch(ns, ns2);
+    const int i = 64 * s2 + lane;
+    const bool ok = active && i < k;
+    const PrimeC c = tb.primes[i < k ? i : 0];
+    if (s2 == s) {  // digits of block s
+      const int nq = min(64, k - 64 * s);
+      const uint32_t g = tb.garner[i < k ? i : 0];
+      const uint32_t r = ok ? V[(int64_t)i * n1 + t] : 0u;
+      uint32_t S = ok ? dig[i] : 0u;
+      for (int q = 0; q < nq; ++q) {
+        const uint32_t cand = canon(redc((uint64_t)msub(r, S, c.p) * g, c.p, c.pinv), c.p);
+        const uint32_t y = __builtin_amdgcn_readlane(cand, q);
+        if (lane == q) ymine = cand;
+        if (lane > q) S = madd(S, canon(redc((uint64_t)y * w[q * 64 + lane], c.p, c.pinv), c.p), c.p);
+      }
+      if (ok) dig[i] = ymine;
+    } else {  // block s into block s2 > s (s is not the last block: 64 digits)
+      uint32_t acc = ok ? dig[i] : 0u;  // < 2p from here on
+#pragma unroll 4
+      for (int q = 0; q < 64; q += 4) {
+        // four products y < 2^30 times W < p stay below p 2^32: REDC gives < 2p
+        const uint64_t sum = (uint64_t)__builtin_amdgcn_readlane(ymine, q) * w[q * 64 + lane] +
+                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 1) * w[(q + 1) * 64 + lane] +
+                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 2) * w[(q + 2) * 64 + lane] +
+                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 3) * w[(q + 3) * 64 + lane];
+        acc += redc(sum, c.p, c.pinv);
+        const uint32_t a2 = acc - 2 * c.p;
+        acc = a2 < acc ? a2 : acc;  // [0, 4p) -> [0, 2p)
+      }
+      if (ok) dig[i] = canon(acc, c.p);
+    }
+    s = ns;
+    s2 = ns2;
   }
 }
 
-// X = sum_j y_j P_j with one wavefront per coefficient and lanes over limbs:
-// limb l accumulates sum_j y_j P_j[l] (< 2^72) as lo (64 bits) + hi; its low
+// X = sum_j y_j P_j for the block's CRT_COEF_PER_BLOCK coefficients, lanes
+// over limbs: wavefront w takes limbs 64 w + 64 CRT_COEF_PER_BLOCK i + lane of
+// every coefficient of the block, so each limb of P_j is read once per block.
+// Limb l accumulates sum_j y_j P_j[l] (< 2^72) as lo (64 bits) + hi; its low
 // word stays at limb l and the rest, a carry below 2^41, goes to limb l+1.
-// One lane then propagates the carries, subtracts M = P_k when
-// X > (M-1)/2 (decided on the digits: (M-1)/2 has digits (p_j - 1)/2) and
-// writes L two's-complement limbs.
+// Lane 0 of wavefront c then propagates the carries of coefficient c,
+// subtracts M = P_k when X > (M-1)/2 (decided on the digits: (M-1)/2 has
+// digits (p_j - 1)/2) and writes L two's-complement limbs.
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTables tb, const ResJob* jobs,
                                                                          const int64_t* prefix, int njobs,
                                                                          int lx_max, uint32_t* ws) {
+  constexpr int C = CRT_COEF_PER_BLOCK;
   extern __shared__ uint32_t csm[];
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[jj];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int t = (int)(b - prefix[jj]) * CRT_COEF_PER_BLOCK + wave;
-  if (t > J.D) return;
+  const int t0 = (int)(b - prefix[jj]) * C;
+  const int nc = min(C, J.D + 1 - t0);  // coefficients of this block (>= 1)
   const int k = J.k;
   const int lx = lx_of(k);
-  const uint32_t* d = ws + J.dig_off + (int64_t)t * k;
-  uint32_t* Xlo = csm + wave * 3 * lx_max;  // [lx] low words, then [2 lx] 64-bit carries as word pairs
-  uint32_t* Xc = Xlo + lx_max;
-  for (int l0 = 0; l0 < lx; l0 += 64) {
+  const uint32_t* d0 = ws + J.dig_off + (int64_t)t0 * k;  // digits of coefficient t0 + c at d0[c k + j]
+  for (int l0 = 64 * wave; l0 < lx; l0 += 64 * C) {
     const int l = l0 + lane;
-    uint64_t lo = 0;
-    uint32_t hi = 0;
+    uint64_t lo[C];
+    uint32_t hi[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) { lo[c] = 0; hi[c] = 0; }
     // P_j has at most 30 j / 32 + 1 limbs, so limbs >= l0 need j >= 32 l0 / 30 - 1
     int j0 = (32 * l0) / 30 - 1;
     if (j0 < 0) j0 = 0;
 #pragma unroll 8
-    for (int j = j0; j < k; ++j) {
+    for (int j = j0; j < k; ++j) {  // eight limb loads in flight per wavefront
       const uint32_t pl = l < tb.pstride ? tb.ptab[(int64_t)j * tb.pstride + l] : 0u;
-      const uint64_t pr = (uint64_t)d[j] * pl;
-      lo += pr;
-      hi += lo < pr ? 1u : 0u;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const uint64_t pr = (uint64_t)(c < nc ? d0[c * k + j] : 0u) * pl;
+        lo[c] += pr;
+        hi[c] += lo[c] < pr ? 1u : 0u;
+      }
     }
     if (l < lx) {
-      Xlo[l] = (uint32_t)lo;
-      const uint64_t cl = (lo >> 32) | ((uint64_t)hi << 32);
-      Xc[2 * l] = (uint32_t)cl;
-      Xc[2 * l + 1] = (uint32_t)(cl >> 32);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        uint32_t* Xl = csm + c * 3 * lx_max;  // [lx] low words, then [2 lx] 64-bit carries as word pairs
+        Xl[l] = (uint32_t)lo[c];
+        const uint64_t cl = (lo[c] >> 32) | ((uint64_t)hi[c] << 32);
+        Xl[lx_max + 2 * l] = (uint32_t)cl;
+        Xl[lx_max + 2 * l + 1] = (uint32_t)(cl >> 32);
+      }
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
+  if (wave >= nc) return;
+  const int t = t0 + wave;
+  const uint32_t* d = d0 + (int64_t)wave * k;
+  const uint32_t* Xlo = csm + wave * 3 * lx_max;
+  const uint32_t* Xc = Xlo + lx_max;
   if (lane != 0) return;
+  const uint32_t* dt = d;
   int cmp = 0;
   for (int j = k - 1; j >= 0; --j) {
     const uint32_t h = (tb.primes[j].p - 1) >> 1;
-    if (d[j] != h) { cmp = d[j] > h ? 1 : -1; break; }
+    if (dt[j] != h) { cmp = dt[j] > h ? 1 : -1; break; }
   }
   const bool sub = cmp > 0;
   const uint32_t* M = tb.ptab + (int64_t)k * tb.pstride;
@@ -965,18 +998,10 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
 }
 
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
+                       int64_t nblocks, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
-  static_assert(KMAX <= 64 * 48, "the largest slot variant covers the table");
-  const dim3 g((unsigned)nblocks), b(64 * CRT_COEF_PER_BLOCK);
-  if (kmax <= 64)
-    hipLaunchKernelGGL(k_crt_digits<1>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
-  else if (kmax <= 256)
-    hipLaunchKernelGGL(k_crt_digits<4>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
-  else if (kmax <= 1024)
-    hipLaunchKernelGGL(k_crt_digits<16>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
-  else
-    hipLaunchKernelGGL(k_crt_digits<48>, g, b, 0, s, tb, jobs_d, prefix_d, njobs, ws);
+  hipLaunchKernelGGL(k_crt_digits, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), 0, s, tb,
+                     jobs_d, prefix_d, njobs, ws);
 }
 
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,

@@ -219,7 +219,7 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   }
   if (part == PIPE_TO_INTERP) return;
   const CrtTables tb = global_crt_tables();
-  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, lay.max_k, wsw, s);
+  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
   if (tm) tm->mark("crt_digits", 1);
   launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, lay.max_k, wsw, s);
   if (tm) tm->mark("crt_combine", 1);
@@ -271,15 +271,15 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
         rd[g].off = off; rd[g].len = ml;
         for (int kx = 0; kx < ml; ++kx) {
           for (int q = 0; q < ROWGRP; ++q) {
-            uint32_t* dst = coef + cw + (size_t)(off + ROWGRP * kx + q) * P.nl;
+            uint32_t* dst = coef + cw + (size_t)(off + ROWGRP * kx + q);  // limb l at dst[l T]
             const int row = deg - t0 - q;
             if (t0 + q > deg || kx > O.rowdeg[row]) {
-              for (int l = 0; l < P.nl; ++l) dst[l] = 0u;
+              for (int l = 0; l < P.nl; ++l) dst[(size_t)l * P.T] = 0u;
               continue;
             }
             const uint32_t* src = O.limbs + ((size_t)row * (O.dx + 1) + kx) * O.nl;
             const uint32_t ext = (src[O.nl - 1] >> 31) ? 0xffffffffu : 0u;
-            for (int l = 0; l < P.nl; ++l) dst[l] = l < O.nl ? src[l] : ext;
+            for (int l = 0; l < P.nl; ++l) dst[(size_t)l * P.T] = l < O.nl ? src[l] : ext;
           }
         }
         off += ROWGRP * ml;

@@ -31,7 +31,7 @@ struct ResJob {
   int32_t nl;          // limbs per input coefficient
   int32_t rows_off;    // first RowDesc of A (rstride groups), then those of B
   int32_t rstride;     // row groups per operand: ceil((width + 1) / 4), width = register class or m
-  int64_t coef_off;    // input limbs [T][nl] (uint32 index)
+  int64_t coef_off;    // input limbs, limb-major [nl][T] (uint32 index)
   int64_t res_off;     // residues [k][T] (uint32 index)
   int64_t val_off;     // coefficients mod p: [k][D+1]
   int64_t pts_off;     // values at the points: [k][D+1]
@@ -141,9 +141,8 @@ void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
 // the interpolation launches also clear zero_word (the abnormal-instance counter)
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s);
-// kmax: the largest prime count among the jobs (sizes the per-lane digit slots)
 void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
+                       int64_t nblocks, uint32_t* ws, hipStream_t s);
 void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
                         int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
