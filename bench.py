@@ -366,6 +366,22 @@ def main():
                                                 "pair (15 resultants) in one batch",
                                     "sets": sets}
 
+    if not args.no_curve_sets:
+        progress("content in y")
+        hx = [-1, 3, 1]  # x^2 + 3x - 1: the vertical lines at its two real roots
+        fh = [synth.univariate_product(hx, [int(c) for c in row]) for row in f]
+        got = snc.content_y(fh, ctx)  # warm-up (workspace)
+        torch.cuda.synchronize()
+        nrep = 5
+        t0 = time.perf_counter()
+        for _ in range(nrep):
+            got = snc.content_y(fh, ctx)
+        torch.cuda.synchronize()
+        ct = (time.perf_counter() - t0) / nrep
+        out["content_y"] = {"workload": "content in y of (x^2 + 3x - 1) f for the step's curve f (25 rows of "
+                                        "degree up to 26): row gcds in a tree of batched modular gcds",
+                            "ms": round(ct * 1e3, 3), "parity_ok": got == hx}
+
     if not args.no_sqfree:
         progress("square-free factorisation")
         a, want = synth.sqfree_request(np.random.default_rng(2024))

@@ -179,6 +179,20 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
                uint32_t* content, uint32_t* limbs, int32_t cap_coefs, int32_t* degs, int32_t* mults,
                int32_t max_factors, int32_t* nfactors);
 
+/* Content of f in y (Section 3: a curve's rows share a content h whose real
+ * roots are vertical lines; the analysis divides it out first):
+ *   h = gcd(f_0, f_1, ..., f_dy) in Z[x], f = sum_i f_i(x) y^i,
+ * normalised to a positive leading coefficient (integer content included);
+ * the zero polynomial (deg -1) for f = 0, the row itself (sign normalised)
+ * when f has one non-zero row.  The rows are paired and their gcds taken in
+ * one batched modular gcd (snc_gcd_z_batch) per level of a binary tree.
+ * plan: deg_bound = the least row degree, out_nlimbs bounds h (Mignotte),
+ *   workspace_bytes = the first level's batch.
+ * run: out as for snc_gcd_z; SNC_ENOMEM if a later level needs more
+ *   workspace (the message says how much). */
+int snc_content_y_plan(const snc_bipoly* f, snc_plan* out);
+int snc_content_y(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
+
 /* ---- gcd in Z[x] ---------------------------------------------------------
  * Modular (small primes) gcd: contents on the host, monic gcd and cofactors
  * mod each prime on the device, primes of minimal gcd degree kept, CRT, and

@@ -154,3 +154,14 @@ def sqfree_zx(a):
         if len(f) > 1:
             out.append((f, k))
     return c, out
+
+
+def content_y(f):
+    """Content of a bivariate f in y: the gcd in Z[x] of its rows f_i(x)
+    (f = sum_i f_i(x) y^i, rows ascending in x), normalised as gcd_zx.
+    Section 2.1 opens by dividing this content out of the curve: its real
+    roots are vertical lines of the curve.  [] for f = 0."""
+    h = []
+    for row in f:
+        h = gcd_zx(h, [int(c) for c in row])
+    return h

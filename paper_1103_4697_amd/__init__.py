@@ -87,6 +87,8 @@ def lib():
                 "snc_prepared_run_sqfree": (C.c_int, [VP, VP, SZ, VP, P(Upoly), P(Upoly)]),
                 "snc_gcd_z_batch": (C.c_int, [VP, I32, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
+                "snc_content_y_plan": (C.c_int, [P(Bipoly), P(Plan)]),
+                "snc_content_y": (C.c_int, [VP, P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_sqfree_plan": (C.c_int, [P(Upoly), P(Plan)]),
                 "snc_sqfree": (C.c_int, [VP, P(Upoly), VP, SZ, VP, I32, P(C.c_uint32), P(C.c_uint32), I32,
                                          P(I32), P(I32), I32, P(I32)]),
@@ -546,6 +548,29 @@ def gcd_z_deriv(a, ctx: Context | None = None, stream=None) -> list:
                                                         C.c_size_t(ws.numel()), sh, C.byref(u)),
                     lambda p: lib().snc_gcd_z_deriv_plan(C.byref(ua), C.byref(p)))
     return limbs_to_ints(rows) if len(rows) else []
+
+
+def content_y(f, ctx: Context | None = None, stream=None) -> list:
+    """Content of f in y (snc_content_y): gcd of its rows f_i(x) in Z[x] with
+    a positive leading coefficient, as an ascending list of Python ints
+    ([] for f = 0)."""
+    ctx = ctx or default_context()
+    keep = []
+    bf = _as_bipoly(f, keep)
+    p = Plan()
+    ctx.check(lib().snc_content_y_plan(C.byref(bf), C.byref(p)), "snc_content_y_plan")
+    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
+    sh = ctx.stream_handle(stream)
+    need = p.workspace_bytes
+    for _ in range(3):
+        ws = ctx.workspace(need)
+        st = lib().snc_content_y(ctx.h, C.byref(bf), C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()), sh,
+                                 C.byref(u))
+        if st != SNC_ENOMEM:
+            break
+        need = 4 * max(need, ws.numel())
+    ctx.check(st, "snc_content_y")
+    return _read_upoly(u, buf)
 
 
 def sqfree_factor(a, ctx: Context | None = None, stream=None):

@@ -1267,6 +1267,107 @@ static int gcd_with_cofactors(snc_ctx* ctx, const UPoly& a, const UPoly& b, void
   return parse_upoly(&uo, g, nl, ctx->err);
 }
 
+// ---- content in y: h = gcd(f_0, f_1, ...) of the rows of f in Z[x] ----
+// The rows are paired and their gcds taken in one batch per level of a
+// binary tree (a level of constants finishes on the host).
+static int bipoly_rows(const snc_bipoly* f, std::vector<UPoly>& rows, std::string& err) {
+  rows.clear();
+  if (!f) { err = "null polynomial"; return SNC_EINVAL; }
+  if (f->dy < 0) return SNC_OK;
+  if (f->dx < 0 || f->nlimbs < 1 || !f->limbs) { err = "bivariate polynomial: bad sizes"; return SNC_EINVAL; }
+  for (int i = 0; i <= f->dy; ++i) {
+    snc_upoly v{const_cast<uint32_t*>(f->limbs) + (size_t)i * (f->dx + 1) * f->nlimbs, f->dx, f->nlimbs};
+    UPoly r;
+    int nl = 1;
+    const int st = parse_upoly(&v, r, nl, err);
+    if (st) return st;
+    if (!r.c.empty()) rows.push_back(std::move(r));
+  }
+  return SNC_OK;
+}
+
+// one level: the gcds of rows 2i and 2i+1 (an odd last row is carried)
+static int content_level(snc_ctx* ctx, const std::vector<UPoly>& rows, void* d_ws, size_t ws_bytes,
+                         hipStream_t stream, std::vector<UPoly>* next, size_t* ws_need) {
+  const int np = (int)rows.size() / 2;
+  std::vector<std::vector<uint32_t>> la(np), lb(np), lo(np);
+  std::vector<snc_upoly> ua(np), ub(np), uo(np);
+  for (int i = 0; i < np; ++i) {
+    to_limbs(rows[2 * i], la[i], ua[i]);
+    to_limbs(rows[2 * i + 1], lb[i], ub[i]);
+  }
+  std::vector<snc_plan> each(np);
+  snc_plan tot{};
+  int st = gcd_plan(np, ua.data(), ub.data(), false, each.data(), &tot);
+  if (st) return st;
+  if (ws_need) *ws_need = tot.workspace_bytes;
+  if (!next) return SNC_OK;
+  if (tot.workspace_bytes > ws_bytes) {
+    ctx->err = "content_y: a level of the row gcds needs " + std::to_string(tot.workspace_bytes) +
+               " bytes of workspace";
+    return SNC_ENOMEM;
+  }
+  for (int i = 0; i < np; ++i) {
+    lo[i].assign((size_t)(std::max(each[i].deg_bound, 0) + 1) * each[i].out_nlimbs, 0u);
+    uo[i] = snc_upoly{lo[i].data(), each[i].deg_bound, each[i].out_nlimbs};
+  }
+  st = gcd_run(ctx, np, ua.data(), ub.data(), false, d_ws, ws_bytes, stream, uo.data());
+  if (st) return st;
+  next->assign(np, UPoly());
+  for (int i = 0; i < np; ++i) {
+    int nl = 1;
+    st = parse_upoly(&uo[i], (*next)[i], nl, ctx->err);
+    if (st) return st;
+  }
+  if (rows.size() % 2) next->push_back(rows.back());
+  return SNC_OK;
+}
+
+static int content_y_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                         UPoly& h) {
+  std::vector<UPoly> rows;
+  int st = bipoly_rows(f, rows, ctx->err);
+  if (st) return st;
+  h = UPoly();
+  if (rows.empty()) return SNC_OK;  // f = 0
+  while (rows.size() > 1) {
+    std::vector<UPoly> next;
+    st = content_level(ctx, rows, d_ws, ws_bytes, stream, &next, nullptr);
+    if (st) return st;
+    rows.swap(next);
+  }
+  h = std::move(rows[0]);
+  if (h.c.back().neg)
+    for (auto& x : h.c) x = -x;
+  return SNC_OK;
+}
+
+// degree and size bounds of the content and the workspace of the first level
+static int content_y_plan(const snc_bipoly* f, snc_plan* out) {
+  std::string err;
+  std::vector<UPoly> rows;
+  int st = bipoly_rows(f, rows, err);
+  if (st) return st;
+  *out = snc_plan{};
+  out->out_nlimbs = 1;
+  if (rows.empty()) return SNC_OK;
+  // h divides the row of least degree: Mignotte bounds its coefficients by 2^deg ||row||_1
+  size_t best = 0;
+  for (size_t i = 1; i < rows.size(); ++i)
+    if (rows[i].deg() < rows[best].deg()) best = i;
+  int nl = 1;
+  for (const auto& x : rows[best].c) nl = std::max(nl, x.twos_limbs());
+  out->deg_bound = rows[best].deg();
+  out->out_nlimbs = nl + (out->deg_bound + (int)std::ceil(std::log2(out->deg_bound + 2.0))) / 32 + 1;
+  size_t need = 0;
+  if (rows.size() > 1) {
+    st = content_level(nullptr, rows, nullptr, 0, nullptr, nullptr, &need);
+    if (st) return st;
+  }
+  out->workspace_bytes = need;
+  return SNC_OK;
+}
+
 struct SqfResult {
   BigInt content;
   std::vector<UPoly> f;
@@ -1408,6 +1509,24 @@ int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, v
 int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
   if (!out || !a) return SNC_EINVAL;
   return gcd_plan(1, a, nullptr, true, nullptr, out);
+}
+
+int snc_content_y_plan(const snc_bipoly* f, snc_plan* out) {
+  if (!f || !out) return SNC_EINVAL;
+  return content_y_plan(f, out);
+}
+
+int snc_content_y(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {
+  if (!ctx || !f || !out) return SNC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  UPoly h;
+  const int st = content_y_run(ctx, f, d_ws, ws_bytes, (hipStream_t)stream, h);
+  if (st) return st;
+  if (h.c.empty()) {
+    out->deg = -1;
+    return SNC_OK;
+  }
+  return write_upoly(h, out, ctx->err);
 }
 
 int snc_sqfree_plan(const snc_upoly* a, snc_plan* out) {

@@ -218,3 +218,17 @@ def test_gcd_degree_limit(snc):
     assert snc.lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)) == snc.SNC_EINVAL
     ua = snc._as_upoly([1] * 13001, keep)       # degree 13000
     assert snc.lib().snc_gcd_z_plan(C.byref(ua), C.byref(ub), C.byref(p)) == 0
+
+
+def test_content_plan(snc):
+    """Planning the content in y needs no device: the degree bound is the
+    least row degree, and the zero polynomial needs nothing."""
+    import ctypes as C
+    keep = []
+    p = snc.Plan()
+    f = [[1, 2, 3], [0], [5, 0, 0, 0, 7], [2, 1]]
+    assert snc.lib().snc_content_y_plan(C.byref(snc._as_bipoly(f, keep)), C.byref(p)) == snc.SNC_OK
+    assert p.deg_bound == 1 and p.out_nlimbs >= 1 and p.workspace_bytes > 0
+    assert snc.lib().snc_content_y_plan(C.byref(snc._as_bipoly([[0]], keep)), C.byref(p)) == snc.SNC_OK
+    assert p.deg_bound == 0 and p.workspace_bytes == 0
+    assert snc.lib().snc_content_y_plan(None, C.byref(p)) == snc.SNC_EINVAL

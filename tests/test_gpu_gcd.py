@@ -359,3 +359,42 @@ def test_sqfree_factor_large_by_construction(snc):
     c, got = snc.sqfree_factor(a)
     assert c == -6
     assert got == [(fs[0], 1), (fs[1], 2), (fs[2], 3)]
+
+
+def _content_cases():
+    rng = np.random.default_rng(31)
+    pr = random.Random(31)
+    cases = []
+    # random dense curves: content 1
+    for d, bits in [(9, 10), (12, 128), (6, 512)]:
+        f, _ = synth.bigcoef_curve(rng, d, bits)
+        cases.append((f"random_d{d}_b{bits}", f))
+    # a non-trivial content h times a curve, with an odd number of rows
+    h = [pr.randrange(-50, 50) for _ in range(4)] + [3]
+    g, _ = synth.bigcoef_curve(rng, 6, 16)
+    cases.append(("h_times_curve", [zx.mul(h, [int(c) for c in row]) for row in g]))
+    # integer content only; a zero row in between; rows of mixed degree
+    cases.append(("integer", [[6, 12, 18], [0], [30, -6], [12]]))
+    # one non-zero row (negative leading coefficient)
+    cases.append(("one_row", [[0], [5, -3, 0, -7]]))
+    # the content of a product curve (x^2 + 1)^2 (y^2 - x) at 300 bits
+    big = (1 << 300) + 12345
+    h2 = zx.scale(zx.mul([1, 0, 1], [1, 0, 1]), big)
+    cases.append(("big_content", [zx.scale(h2, -1), [0], [int(c) for c in h2]]))
+    return cases
+
+
+@pytest.mark.parametrize("name,f", _content_cases(), ids=[c[0] for c in _content_cases()])
+def test_content_y(snc, name, f):
+    """Content in y on the device (a tree of batched row gcds) against the
+    oracle's fold of exact gcds; the content divides every row."""
+    got = snc.content_y(f)
+    want = G.content_y(f)
+    assert got == want
+    for row in f:
+        if any(int(c) for c in row):
+            assert zx.divides(got, [int(c) for c in row])
+
+
+def test_content_y_zero(snc):
+    assert snc.content_y([[0, 0], [0]]) == []
