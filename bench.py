@@ -382,6 +382,20 @@ def main():
                                         "degree up to 26): row gcds in a tree of batched modular gcds",
                             "ms": round(ct * 1e3, 3), "parity_ok": got == hx}
 
+    if not args.no_curve_sets:
+        progress("FastLift Q")
+        q = snc.fastlift_q(f, ctx)  # warm-up
+        torch.cuda.synchronize()
+        nrep = 5
+        t0 = time.perf_counter()
+        for _ in range(nrep):
+            q = snc.fastlift_q(f, ctx)
+        torch.cuda.synchronize()
+        qt = (time.perf_counter() - t0) / nrep
+        out["fastlift_q"] = {"workload": "Q = res_y(f_x / h, f_y / h), h = gcd(f_x, f_y), for the step's curve f: "
+                                         "h certified constant in y and in x mod p on the host, then one resultant",
+                             "ms": round(qt * 1e3, 3), "deg_Q": len(q) - 1}
+
     if not args.no_sqfree:
         progress("square-free factorisation")
         a, want = synth.sqfree_request(np.random.default_rng(2024))

@@ -55,7 +55,8 @@ typedef enum {
   SNC_ENOMEM = -3,    /* workspace (or server pool) smaller than the plan requires */
   SNC_EDEVICE = -4,   /* HIP runtime error; see snc_last_error */
   SNC_EAGAIN = -5,    /* server: request not finished yet */
-  SNC_EINTERNAL = -6  /* an internal consistency check failed (a bug) */
+  SNC_EINTERNAL = -6, /* an internal consistency check failed (a bug) */
+  SNC_ENOTSUP = -7    /* the input needs a path this library does not have (the message says which) */
 } snc_status;
 
 /* f = sum_{i<=dy} sum_{k<=dx} c_{i,k} x^k y^i, coefficient c_{i,k} at
@@ -192,6 +193,24 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
  *   workspace (the message says how much). */
 int snc_content_y_plan(const snc_bipoly* f, snc_plan* out);
 int snc_content_y(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
+
+/* FastLift's second resultant (Section 2.2): with h = gcd(f_x, f_y) in
+ * Z[x, y], Q = res_y(f_x / h, f_y / h).  mult(Q, alpha) bounds the number of
+ * distinct complex roots of f(alpha, y): m*_alpha = deg_y f - mult(R, alpha)
+ * + mult(Q, alpha).  Built for h constant in y, the usual case: a prime p
+ * and a point x0 where gcd(f_x(x0, y), f_y(x0, y)) mod p is constant (and
+ * neither leading coefficient in y vanishes) certify that deg_y h = 0; then
+ * h is the gcd of all rows of f_x and f_y in Z[x] (snc_content_y's tree of
+ * batched gcds), normalised to a positive leading coefficient, the rows are
+ * divided by h exactly on the host, and Q comes from snc_resultant_y.  When
+ * four (p, x0) leave a non-constant gcd, h depends on y: SNC_ENOTSUP (a
+ * bivariate gcd is not built).
+ * plan: the plan of res_y(f_x, f_y), an upper bound when h = +-1; a
+ *   non-trivial h may need more (SNC_ENOMEM / SNC_ERANGE with sizes, as for
+ *   snc_resultant_y).
+ * run: out as for snc_resultant_y. */
+int snc_fastlift_q_plan(const snc_bipoly* f, snc_plan* out);
+int snc_fastlift_q(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
 
 /* ---- gcd in Z[x] ---------------------------------------------------------
  * Modular (small primes) gcd: contents on the host, monic gcd and cofactors

@@ -22,6 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsnc.so")
 
 SNC_OK, SNC_EINVAL, SNC_ERANGE, SNC_ENOMEM, SNC_EDEVICE, SNC_EAGAIN, SNC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+SNC_ENOTSUP = -7
 
 
 class SncError(RuntimeError):
@@ -87,6 +88,8 @@ def lib():
                 "snc_prepared_run_sqfree": (C.c_int, [VP, VP, SZ, VP, P(Upoly), P(Upoly)]),
                 "snc_gcd_z_batch": (C.c_int, [VP, I32, P(Upoly), P(Upoly), VP, SZ, VP, P(Upoly)]),
                 "snc_gcd_z_deriv": (C.c_int, [VP, P(Upoly), VP, SZ, VP, P(Upoly)]),
+                "snc_fastlift_q_plan": (C.c_int, [P(Bipoly), P(Plan)]),
+                "snc_fastlift_q": (C.c_int, [VP, P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_content_y_plan": (C.c_int, [P(Bipoly), P(Plan)]),
                 "snc_content_y": (C.c_int, [VP, P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_sqfree_plan": (C.c_int, [P(Upoly), P(Plan)]),
@@ -570,6 +573,32 @@ def content_y(f, ctx: Context | None = None, stream=None) -> list:
             break
         need = 4 * max(need, ws.numel())
     ctx.check(st, "snc_content_y")
+    return _read_upoly(u, buf)
+
+
+def fastlift_q(f, ctx: Context | None = None, stream=None) -> list:
+    """FastLift's Q = res_y(f_x / h, f_y / h), h = gcd(f_x, f_y)
+    (snc_fastlift_q), as an ascending list of Python ints; raises SncError
+    with SNC_ENOTSUP when h depends on y."""
+    ctx = ctx or default_context()
+    keep = []
+    bf = _as_bipoly(f, keep)
+    p = Plan()
+    ctx.check(lib().snc_fastlift_q_plan(C.byref(bf), C.byref(p)), "snc_fastlift_q_plan")
+    deg, nl, need = p.deg_bound, p.out_nlimbs, p.workspace_bytes
+    sh = ctx.stream_handle(stream)
+    for _ in range(3):
+        u, buf = _out_upoly(deg, nl, keep)
+        ws = ctx.workspace(need)
+        st = lib().snc_fastlift_q(ctx.h, C.byref(bf), C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()), sh,
+                                  C.byref(u))
+        if st == SNC_ERANGE:
+            deg, nl = max(deg, u.deg), max(nl, u.nlimbs)
+        elif st == SNC_ENOMEM:
+            need = 4 * max(need, ws.numel())
+        else:
+            break
+    ctx.check(st, "snc_fastlift_q")
     return _read_upoly(u, buf)
 
 

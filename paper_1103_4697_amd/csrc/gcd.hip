@@ -1323,11 +1323,10 @@ static int content_level(snc_ctx* ctx, const std::vector<UPoly>& rows, void* d_w
   return SNC_OK;
 }
 
-static int content_y_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
-                         UPoly& h) {
-  std::vector<UPoly> rows;
-  int st = bipoly_rows(f, rows, ctx->err);
-  if (st) return st;
+// gcd of the non-zero polynomials in rows (consumed), positive leading coefficient
+static int content_rows(snc_ctx* ctx, std::vector<UPoly>& rows, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                        UPoly& h) {
+  int st = SNC_OK;
   h = UPoly();
   if (rows.empty()) return SNC_OK;  // f = 0
   while (rows.size() > 1) {
@@ -1340,6 +1339,14 @@ static int content_y_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t w
   if (h.c.back().neg)
     for (auto& x : h.c) x = -x;
   return SNC_OK;
+}
+
+static int content_y_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                         UPoly& h) {
+  std::vector<UPoly> rows;
+  const int st = bipoly_rows(f, rows, ctx->err);
+  if (st) return st;
+  return content_rows(ctx, rows, d_ws, ws_bytes, stream, h);
 }
 
 // degree and size bounds of the content and the workspace of the first level
@@ -1365,6 +1372,211 @@ static int content_y_plan(const snc_bipoly* f, snc_plan* out) {
     if (st) return st;
   }
   out->workspace_bytes = need;
+  return SNC_OK;
+}
+
+// ---- FastLift's Q = res_y(f_x / h, f_y / h), h = gcd(f_x, f_y) ----------
+// rows of f in y with their positions (zero rows kept, trailing ones dropped)
+static int bipoly_all_rows(const snc_bipoly* f, std::vector<UPoly>& rows, std::string& err) {
+  rows.clear();
+  if (!f) { err = "null polynomial"; return SNC_EINVAL; }
+  if (f->dy < 0) return SNC_OK;
+  if (f->dx < 0 || f->nlimbs < 1 || !f->limbs) { err = "bivariate polynomial: bad sizes"; return SNC_EINVAL; }
+  rows.resize(f->dy + 1);
+  for (int i = 0; i <= f->dy; ++i) {
+    snc_upoly v{const_cast<uint32_t*>(f->limbs) + (size_t)i * (f->dx + 1) * f->nlimbs, f->dx, f->nlimbs};
+    int nl = 1;
+    const int st = parse_upoly(&v, rows[i], nl, err);
+    if (st) return st;
+  }
+  while (!rows.empty() && rows.back().c.empty()) rows.pop_back();
+  return SNC_OK;
+}
+
+static void partials(const std::vector<UPoly>& f, std::vector<UPoly>& fx, std::vector<UPoly>& fy) {
+  fx.assign(f.size(), UPoly());
+  for (size_t i = 0; i < f.size(); ++i) derivative(f[i], fx[i]);
+  while (!fx.empty() && fx.back().c.empty()) fx.pop_back();
+  fy.assign(f.size() > 1 ? f.size() - 1 : 0, UPoly());
+  for (size_t i = 1; i < f.size(); ++i)
+    for (const auto& x : f[i].c) fy[i - 1].c.push_back(x.mul_small((uint32_t)i));
+}
+
+// degree in y of gcd(a(x0, y), b(x0, y)) mod p, or -1 when a leading
+// coefficient in y vanishes at x0 mod p (the point says nothing)
+static int ygcd_degree_mod(const std::vector<UPoly>& a, const std::vector<UPoly>& b, uint32_t p, uint32_t x0) {
+  auto at = [&](const std::vector<UPoly>& f) {
+    std::vector<uint64_t> v(f.size(), 0);
+    for (size_t i = 0; i < f.size(); ++i) {
+      uint64_t acc = 0;
+      for (size_t k = f[i].c.size(); k-- > 0;) acc = (acc * x0 + f[i].c[k].smod(p)) % p;
+      v[i] = acc;
+    }
+    return v;
+  };
+  std::vector<uint64_t> A = at(a), B = at(b);
+  if (A.empty() || B.empty() || A.back() == 0 || B.back() == 0) return -1;
+  auto inv = [&](uint64_t x) {
+    uint64_t r = 1, e = p - 2;
+    while (e) { if (e & 1) r = r * x % p; x = x * x % p; e >>= 1; }
+    return r;
+  };
+  while (!B.empty()) {
+    while (A.size() >= B.size()) {  // A <- A mod B
+      const uint64_t q = A.back() * inv(B.back()) % p;
+      const size_t s = A.size() - B.size();
+      for (size_t i = 0; i < B.size(); ++i) A[s + i] = (A[s + i] + p - q * B[i] % p) % p;
+      while (!A.empty() && A.back() == 0) A.pop_back();
+      if (A.empty()) break;
+    }
+    std::swap(A, B);
+  }
+  return (int)A.size() - 1;
+}
+
+// degree of gcd(a mod p, b mod p), or -1 when a leading coefficient vanishes mod p
+static int gcd_degree_mod(const UPoly& a, const UPoly& b, uint32_t p) {
+  auto red = [&](const UPoly& f) {
+    std::vector<uint64_t> v(f.c.size());
+    for (size_t k = 0; k < f.c.size(); ++k) v[k] = f.c[k].smod(p);
+    return v;
+  };
+  std::vector<uint64_t> A = red(a), B = red(b);
+  if (A.empty() || B.empty() || A.back() == 0 || B.back() == 0) return -1;
+  auto inv = [&](uint64_t x) {
+    uint64_t r = 1, e = p - 2;
+    while (e) { if (e & 1) r = r * x % p; x = x * x % p; e >>= 1; }
+    return r;
+  };
+  while (!B.empty()) {
+    while (A.size() >= B.size()) {
+      const uint64_t q = A.back() * inv(B.back()) % p;
+      const size_t s = A.size() - B.size();
+      for (size_t i = 0; i < B.size(); ++i) A[s + i] = (A[s + i] + p - q * B[i] % p) % p;
+      while (!A.empty() && A.back() == 0) A.pop_back();
+      if (A.empty()) break;
+    }
+    std::swap(A, B);
+  }
+  return (int)A.size() - 1;
+}
+
+// exact quotient of polynomials in Z[x]; false if h does not divide a
+static bool poly_divexact(const UPoly& a, const UPoly& h, UPoly& q) {
+  q.c.assign(a.c.size() >= h.c.size() ? a.c.size() - h.c.size() + 1 : 0, BigInt());
+  UPoly r = a;
+  while (r.c.size() >= h.c.size() && !r.c.empty()) {
+    const size_t s = r.c.size() - h.c.size();
+    BigInt c;
+    if (!div_exact(r.c.back(), h.c.back(), c)) return false;
+    q.c[s] = c;
+    for (size_t i = 0; i < h.c.size(); ++i) r.c[s + i] = r.c[s + i] - c * h.c[i];
+    trim(r);
+  }
+  trim(q);
+  return r.c.empty();
+}
+
+// rows -> limbs of a snc_bipoly view (buf keeps the limbs)
+static snc_bipoly bipoly_of(const std::vector<UPoly>& rows, std::vector<uint32_t>& buf) {
+  if (rows.empty()) return snc_bipoly{nullptr, -1, 0, 1};
+  int nl = 1, dx = 0;
+  for (const auto& r : rows) {
+    dx = std::max(dx, r.deg());
+    for (const auto& x : r.c) nl = std::max(nl, x.twos_limbs());
+  }
+  buf.assign(rows.size() * (size_t)(dx + 1) * nl, 0u);
+  for (size_t i = 0; i < rows.size(); ++i)
+    for (size_t k = 0; k < rows[i].c.size(); ++k)
+      (void)rows[i].c[k].to_twos(buf.data() + (i * (size_t)(dx + 1) + k) * nl, nl);
+  return snc_bipoly{buf.data(), (int32_t)rows.size() - 1, dx, nl};
+}
+
+static int fastlift_q_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                          snc_upoly* out) {
+  std::vector<UPoly> rows, fx, fy;
+  int st = bipoly_all_rows(f, rows, ctx->err);
+  if (st) return st;
+  partials(rows, fx, fy);
+  if (fx.empty() || fy.empty()) {  // f_x = 0 or f_y = 0: h = the other one, Q of a constant (or 0)
+    ctx->err = "fastlift Q: f_x or f_y is zero (f constant in x or in y)";
+    return SNC_ENOTSUP;
+  }
+  // certify deg_y gcd(f_x, f_y) = 0 at a (prime, point)
+  const Tables& T = tables();
+  bool ydeg0 = false;
+  for (int a = 0, tries = 0; a < 64 && tries < 4 && !ydeg0; ++a) {
+    const int d = ygcd_degree_mod(fx, fy, T.p[a], (uint32_t)(a + 2));
+    if (d < 0) continue;
+    ++tries;
+    ydeg0 = d == 0;
+  }
+  if (!ydeg0) {
+    ctx->err = "fastlift Q: gcd(f_x, f_y) depends on y (no bivariate gcd in this library)";
+    return SNC_ENOTSUP;
+  }
+  // h in Z[x]: the gcd of every row of f_x and f_y
+  std::vector<UPoly> all;
+  for (const auto* v : {&fx, &fy})
+    for (const auto& r : *v)
+      if (!r.c.empty()) all.push_back(r);
+  // two rows with a constant gcd mod p make h an integer: the gcd of all coefficients
+  bool integer_h = false;
+  if (all.size() >= 2)
+    for (int a = 0, tries = 0; a < 16 && tries < 3 && !integer_h; ++a) {
+      const int d = gcd_degree_mod(all[0], all[1], T.p[a]);
+      if (d < 0) continue;
+      ++tries;
+      integer_h = d == 0;
+    }
+  UPoly h;
+  if (integer_h) {
+    BigInt g;
+    for (const auto& r : all)
+      for (const auto& x : r.c) g = BigInt::gcd(g, x);
+    g.neg = false;
+    h.c = {g};
+  } else {
+    st = content_rows(ctx, all, d_ws, ws_bytes, stream, h);
+    if (st) return st;
+  }
+  const bool unit = h.deg() == 0 && h.c[0].mag.size() == 1 && h.c[0].mag[0] == 1;
+  if (!unit) {
+    for (auto* v : {&fx, &fy})
+      for (auto& r : *v) {
+        UPoly q;
+        if (!poly_divexact(r, h, q)) { ctx->err = "fastlift Q: content does not divide a row"; return SNC_EINTERNAL; }
+        r = std::move(q);
+      }
+  }
+  std::vector<uint32_t> bx, by;
+  const snc_bipoly px = bipoly_of(fx, bx), py = bipoly_of(fy, by);
+  return snc_resultant_y(ctx, &px, &py, d_ws, ws_bytes, stream, out);
+}
+
+static int fastlift_q_plan(const snc_bipoly* f, snc_plan* out) {
+  std::string err;
+  std::vector<UPoly> rows, fx, fy;
+  int st = bipoly_all_rows(f, rows, err);
+  if (st) return st;
+  partials(rows, fx, fy);
+  *out = snc_plan{};
+  out->out_nlimbs = 1;
+  if (fx.empty() || fy.empty()) return SNC_OK;
+  std::vector<uint32_t> bx, by;
+  const snc_bipoly px = bipoly_of(fx, bx), py = bipoly_of(fy, by);
+  st = snc_resultant_y_plan(&px, &py, out);
+  if (st) return st;
+  std::vector<UPoly> all;
+  for (const auto* v : {&fx, &fy})
+    for (const auto& r : *v)
+      if (!r.c.empty()) all.push_back(r);
+  size_t need = 0;
+  if (all.size() > 1) {
+    st = content_level(nullptr, all, nullptr, 0, nullptr, nullptr, &need);
+    if (st) return st;
+  }
+  out->workspace_bytes = std::max(out->workspace_bytes, need);
   return SNC_OK;
 }
 
@@ -1509,6 +1721,17 @@ int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, v
 int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {
   if (!out || !a) return SNC_EINVAL;
   return gcd_plan(1, a, nullptr, true, nullptr, out);
+}
+
+int snc_fastlift_q_plan(const snc_bipoly* f, snc_plan* out) {
+  if (!f || !out) return SNC_EINVAL;
+  return fastlift_q_plan(f, out);
+}
+
+int snc_fastlift_q(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out) {
+  if (!ctx || !f || !out) return SNC_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  return fastlift_q_run(ctx, f, d_ws, ws_bytes, (hipStream_t)stream, out);
 }
 
 int snc_content_y_plan(const snc_bipoly* f, snc_plan* out) {

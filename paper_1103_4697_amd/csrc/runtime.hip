@@ -254,6 +254,7 @@ const char* snc_status_str(int s) {
     case SNC_EDEVICE: return "device error";
     case SNC_EAGAIN: return "not finished";
     case SNC_EINTERNAL: return "internal error";
+    case SNC_ENOTSUP: return "not supported";
     default: return "unknown status";
   }
 }

@@ -398,3 +398,39 @@ def test_content_y(snc, name, f):
 
 def test_content_y_zero(snc):
     assert snc.content_y([[0, 0], [0]]) == []
+
+
+def _fastlift_cases():
+    rng = np.random.default_rng(41)
+    cases = []
+    for d, bits in [(4, 8), (6, 16), (7, 6), (5, 128)]:  # the oracle's gcd (pseudo-remainders) limits the degree
+        f, _ = synth.bigcoef_curve(rng, d, bits)
+        cases.append((f"random_d{d}_b{bits}", [[int(c) for c in row] for row in f]))
+    # f = 5 + x^2 C(x, y): f_x and f_y share x
+    C, _ = synth.bigcoef_curve(rng, 4, 6)
+    rows = [zx.mul([0, 0, 1], [int(c) for c in r]) for r in C]
+    rows[0] = zx.add(rows[0], [5])
+    cases.append(("shared_x", rows))
+    # every coefficient of f_x and f_y even: h = 2
+    f, _ = synth.bigcoef_curve(rng, 5, 8)
+    cases.append(("even", [[2 * int(c) for c in row] for row in f]))
+    return cases
+
+
+@pytest.mark.parametrize("name,f", _fastlift_cases(), ids=[c[0] for c in _fastlift_cases()])
+def test_fastlift_q(snc, name, f):
+    """Q = res_y(f_x / h, f_y / h) on the device against the oracle (its own
+    bivariate gcd by pseudo-remainders and Bareiss over Z[x])."""
+    from oracle import fastlift as FL
+    want, h = FL.fastlift_q(f)
+    assert len(h) == 1  # these inputs have h constant in y
+    assert snc.fastlift_q(f) == want
+
+
+def test_fastlift_q_y_factor_unsupported(snc):
+    """f = (y - x)^2 (y + 1): f_x and f_y share y - x; the library reports the
+    bivariate gcd it does not have instead of a wrong Q."""
+    f = [[0, 0, 1], [0, -2, 1], [1, -2], [1]]  # (y^2 - 2xy + x^2)(y + 1), rows in y
+    with pytest.raises(snc.SncError) as e:
+        snc.fastlift_q(f)
+    assert e.value.status == snc.SNC_ENOTSUP
