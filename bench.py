@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
+    ap.add_argument("--profile-curve-set", default="",
+                    help="D:B -- only run the five-curve set of degree D and B-bit coefficients five times "
+                         "(for a profiler) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many resultant+gcd steps (for profilers) and exit")
     args = ap.parse_args()
@@ -218,6 +221,14 @@ def main():
         G = batch.gbufs[0][: batch.gout[0].deg + 1]
         return d, G
 
+    if args.profile_curve_set:
+        d, bits = (int(v) for v in args.profile_curve_set.split(":"))
+        bs = snc.ResultantBatch(synth.random_curve_set(np.random.default_rng(100 * d + bits), d, bits), ctx)
+        for _ in range(5):
+            bs.run()
+        torch.cuda.synchronize()
+        progress(f"profile run: curve set degree {d}, {bits} bits, 5 runs done")
+        return
     if args.profile_steps:
         for _ in range(args.profile_steps):
             step()
