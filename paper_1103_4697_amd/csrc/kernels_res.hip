@@ -944,8 +944,8 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
     // P_j has at most 30 j / 32 + 1 limbs, so limbs >= l0 need j >= 32 l0 / 30 - 1
     int j0 = (32 * l0) / 30 - 1;
     if (j0 < 0) j0 = 0;
-#pragma unroll 8
-    for (int j = j0; j < k; ++j) {  // eight limb loads in flight per wavefront
+#pragma unroll 16
+    for (int j = j0; j < k; ++j) {  // sixteen limb loads in flight per wavefront
       const uint32_t pl = l < tb.pstride ? tb.ptab[(int64_t)j * tb.pstride + l] : 0u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
