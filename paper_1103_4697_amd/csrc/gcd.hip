@@ -620,7 +620,7 @@ static BigInt stage_crt(GcdProb& p, const std::vector<int32_t>& sel, int emin, c
     jb[t].nq_off = 0;
     jb[t].out_off = (int64_t)(p.outw + t * p.nmax * p.lg);
     pd[t + 1] = pd[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-    pcb[t + 1] = pcb[t] + (lens[t] + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+    pcb[t + 1] = pcb[t] + (lens[t] + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
   }
   int32_t* hsel = (int32_t*)(h + p.sel);
   uint32_t* hsc = h + p.scales;
@@ -828,7 +828,8 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
       CrtTables tb{(const PrimeC*)(ws + p.primes), ws + p.garner, ws + p.wtab, ws + p.ptab, ks, p.lg};
       const int64_t* pd = (const int64_t*)(h + p.prefd);
       launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefd), 3, pd[3], ws, stream);
-      launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefc), 3, pd[3], ks, ws, stream);
+      const int64_t* pc = (const int64_t*)(h + p.prefc);
+      launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefc), 3, pc[3], ks, ws, stream);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync((uint8_t*)ctx->h_out + (L.out_begin - L.e_begin) * 4, ws + L.out_begin,

@@ -27,7 +27,7 @@ hipError_t configure_kernels() {
                                      160 * 1024);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_crt_combine, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(CRT_COEF_PER_BLOCK * 3 * lx_of(KMAX) * sizeof(uint32_t)));
+                             (int)(CRT_COMB_PER_BLOCK * 3 * lx_of(KMAX) * sizeof(uint32_t)));
 }
 
 void upload_tables(const PrimeC* primes, const uint32_t* garner_c, const uint32_t* wtab,
@@ -913,9 +913,10 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
   }
 }
 
-// X = sum_j y_j P_j for the block's CRT_COEF_PER_BLOCK coefficients, lanes
-// over limbs: wavefront w takes limbs 64 w + 64 CRT_COEF_PER_BLOCK i + lane of
-// every coefficient of the block, so each limb of P_j is read once per block.
+// X = sum_j y_j P_j for the workgroup's CRT_COMB_PER_BLOCK coefficients,
+// lanes over limbs: wavefront w of the CRT_COEF_PER_BLOCK takes limbs
+// 64 w + 64 CRT_COEF_PER_BLOCK i + lane of every coefficient of the workgroup,
+// so each limb of P_j is read once per workgroup.
 // Limb l accumulates sum_j y_j P_j[l] (< 2^72) as lo (64 bits) + hi; its low
 // word stays at limb l and the rest, a carry below 2^41, goes to limb l+1.
 // Lane 0 of wavefront c then propagates the carries of coefficient c,
@@ -924,7 +925,7 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTables tb, const ResJob* jobs,
                                                                          const int64_t* prefix, int njobs,
                                                                          int lx_max, uint32_t* ws) {
-  constexpr int C = CRT_COEF_PER_BLOCK;
+  constexpr int C = CRT_COMB_PER_BLOCK;
   extern __shared__ uint32_t csm[];
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
@@ -935,7 +936,7 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
   const int k = J.k;
   const int lx = lx_of(k);
   const uint32_t* d0 = ws + J.dig_off + (int64_t)t0 * k;  // digits of coefficient t0 + c at d0[c k + j]
-  for (int l0 = 64 * wave; l0 < lx; l0 += 64 * C) {
+  for (int l0 = 64 * wave; l0 < lx; l0 += 64 * CRT_COEF_PER_BLOCK) {
     const int l = l0 + lane;
     uint64_t lo[C];
     uint32_t hi[C];
@@ -1008,8 +1009,8 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t
                         int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
   const int lxm = lx_of(kmax);
-  const size_t shmem = (size_t)CRT_COEF_PER_BLOCK * 3 * lxm * sizeof(uint32_t);
-  static_assert((size_t)CRT_COEF_PER_BLOCK * 3 * ((30 * KMAX + 31) / 32 + 2) * 4 <= 160 * 1024,
+  const size_t shmem = (size_t)CRT_COMB_PER_BLOCK * 3 * lxm * sizeof(uint32_t);
+  static_assert((size_t)CRT_COMB_PER_BLOCK * 3 * ((30 * KMAX + 31) / 32 + 2) * 4 <= 160 * 1024,
                 "combination buffers for the whole table fit the LDS of a CU");
   hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), shmem, s, tb, jobs_d,
                      prefix_d, njobs, lxm, ws);

@@ -111,7 +111,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.nb_interp += P.k;
     lay.nb_interp_blk += (int64_t)P.k * ((n1 + 63) / 64);
     lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
-    lay.nb_crtc += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
+    lay.nb_crtc += (int64_t)((n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK);
     lay.max_k = std::max(lay.max_k, P.k);
     if (P.cls >= 0) {
       lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
@@ -293,7 +293,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     pi[j + 1] = pi[j] + P.k;
     pib[j + 1] = pib[j] + (int64_t)P.k * ((P.D + 1 + 63) / 64);
     pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-    pc[j + 1] = pc[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+    pc[j + 1] = pc[j] + (n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
     if (P.cls >= 0) {
       const int c = P.cls;
       le[c][ne[c]] = j;

@@ -15,7 +15,8 @@ constexpr int EE_WAVES = 1;       // wavefronts per eval_elim workgroup
 constexpr int EE_BLOCK = 64 * EE_WAVES;
 constexpr int INTERP_THREADS = 1024;
 constexpr int MAX_D = 10000;     // largest degree bound: interpolation keeps 4(D+1)+O(1) words in LDS
-constexpr int CRT_COEF_PER_BLOCK = 4;   // one wavefront per coefficient
+constexpr int CRT_COEF_PER_BLOCK = 4;   // one wavefront per coefficient (digits)
+constexpr int CRT_COMB_PER_BLOCK = 2;   // coefficients per combination workgroup (four wavefronts over limbs)
 constexpr int GCD_THREADS = 256;
 
 // One resultant res_y(f, g).  A is the operand of larger y-degree (m >= n);
