@@ -829,7 +829,7 @@ void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 //     prime 64 s + l of block s).  In block s the digits come one after
 //     another: digit q is broadcast from lane q and folded into the later
 //     primes of the block.  The finished block then goes to every later
-//     block s2 at once, S_i += sum_q y_{64s+q} (P_{64s+q} mod p_i), four
+//     block s2 at once, S_i += sum_q y_{64s+q} (P_{64s+q} mod p_i), sixteen
 //     products per reduction.  S_i waits in digit slot i until digit i is
 //     written there.  The 64 x 64 tiles of W = (P_j mod p_i) are staged in
 //     LDS, double-buffered and shared by the block's wavefronts.
@@ -895,14 +895,29 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
       if (ok) dig[i] = ymine;
     } else {  // block s into block s2 > s (s is not the last block: 64 digits)
       uint32_t acc = ok ? dig[i] : 0u;  // < 2p from here on
-#pragma unroll 4
-      for (int q = 0; q < 64; q += 4) {
-        // four products y < 2^30 times W < p stay below p 2^32: REDC gives < 2p
-        const uint64_t sum = (uint64_t)__builtin_amdgcn_readlane(ymine, q) * w[q * 64 + lane] +
-                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 1) * w[(q + 1) * 64 + lane] +
-                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 2) * w[(q + 2) * 64 + lane] +
-                             (uint64_t)__builtin_amdgcn_readlane(ymine, q + 3) * w[(q + 3) * 64 + lane];
-        acc += redc(sum, c.p, c.pinv);
+#pragma unroll
+      for (int q = 0; q < 64; q += 16) {
+        // sixteen products y < 2^30 times W < p stay below 2^34 p < 2^64 (four
+        // partial sums); with sum = hi 2^32 + lo, sum 2^-32 = hi + lo 2^-32,
+        // where hi < 4p and the REDC of lo alone is at most p
+        uint64_t part[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          part[u] = 0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int qq = q + 4 * u + v;
+            part[u] += (uint64_t)__builtin_amdgcn_readlane(ymine, qq) * w[qq * 64 + lane];
+          }
+        }
+        const uint64_t sum = (part[0] + part[1]) + (part[2] + part[3]);
+        uint32_t hi = (uint32_t)(sum >> 32);
+        const uint32_t h2 = hi - 2 * c.p;
+        hi = h2 < hi ? h2 : hi;  // [0, 4p) -> [0, 2p)
+        uint32_t t = hi + redc((uint64_t)(uint32_t)sum, c.p, c.pinv);  // < 3p + 1
+        const uint32_t t2 = t - 2 * c.p;
+        t = t2 < t ? t2 : t;  // -> [0, 2p)
+        acc += t;
         const uint32_t a2 = acc - 2 * c.p;
         acc = a2 < acc ? a2 : acc;  // [0, 4p) -> [0, 2p)
       }
