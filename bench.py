@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--profile-curve-set", default="",
                     help="D:B -- only run the five-curve set of degree D and B-bit coefficients five times "
                          "(for a profiler) and exit")
+    ap.add_argument("--profile-batch", type=int, default=0,
+                    help="only replay the 512-pair batched workload this many times (for profilers) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many resultant+gcd steps (for profilers) and exit")
     args = ap.parse_args()
@@ -228,6 +230,14 @@ def main():
             bs.run()
         torch.cuda.synchronize()
         progress(f"profile run: curve set degree {d}, {bits} bits, 5 runs done")
+        return
+    if args.profile_batch:
+        pairs, _common = synth.config2()
+        bb = snc.ResultantBatch(pairs, ctx)
+        for _ in range(args.profile_batch):
+            bb.run()
+        torch.cuda.synchronize()
+        progress(f"profile run: 512-pair batch, {args.profile_batch} runs done")
         return
     if args.profile_steps:
         for _ in range(args.profile_steps):

@@ -180,8 +180,8 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
                uint32_t* content, uint32_t* limbs, int32_t cap_coefs, int32_t* degs, int32_t* mults,
                int32_t max_factors, int32_t* nfactors);
 
-/* Content of f in y (Section 3: a curve's rows share a content h whose real
- * roots are vertical lines; the analysis divides it out first):
+/* Content of f in y (opening of Section 2.1: a curve's rows share a content h
+ * whose real roots are vertical lines; the analysis divides it out first):
  *   h = gcd(f_0, f_1, ..., f_dy) in Z[x], f = sum_i f_i(x) y^i,
  * normalised to a positive leading coefficient (integer content included);
  * the zero polynomial (deg -1) for f = 0, the row itself (sign normalised)
@@ -194,7 +194,8 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
 int snc_content_y_plan(const snc_bipoly* f, snc_plan* out);
 int snc_content_y(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
 
-/* FastLift's second resultant (Section 2.2): with h = gcd(f_x, f_y) in
+/* FastLift's second resultant (Section 2.1, "Lifting Phase", the bound
+ * m*_alpha): with h = gcd(f_x, f_y) in
  * Z[x, y], Q = res_y(f_x / h, f_y / h).  mult(Q, alpha) bounds the number of
  * distinct complex roots of f(alpha, y): m*_alpha = deg_y f - mult(R, alpha)
  * + mult(Q, alpha).  Built for h constant in y, the usual case: a prime p

@@ -1,6 +1,6 @@
 """Oracle for FastLift's resultant Q (test infrastructure only).
 
-Section 2.2 (the FastLift remark on the number of arcs): with
+Section 2.1, "Lifting Phase" (the bound m*_alpha of FastLift): with
 h = gcd(f_x, f_y) in Z[x, y], f_x* = f_x / h and f_y* = f_y / h,
 
     Q(x) = res(f_x*, f_y*, y),

@@ -1,5 +1,5 @@
 """Pins of the oracle for FastLift's Q = res_y(f_x / h, f_y / h) with
-h = gcd(f_x, f_y) (Section 2.2): the bivariate gcd against sympy and
+h = gcd(f_x, f_y) (Section 2.1, "Lifting Phase"): the bivariate gcd against sympy and
 planted factors, the exact bivariate division, and the identity
 res(f_x, f_y) = h^(m + n) Q for h in Z[x] (m, n the y-degrees of f_x / h
 and f_y / h) against the independently pinned resultant oracle."""
