@@ -110,6 +110,24 @@ const char* snc_last_error(const snc_ctx* ctx);
 int snc_set_timing(snc_ctx* ctx, int enable);
 int snc_get_timing(const snc_ctx* ctx, const char** names, float* ms, int32_t* launches, int cap);
 
+/* Throughput ceiling of one integer operation on this context's device,
+ * measured (not a compute call of the method): eight independent chains per
+ * lane, sixteen wavefronts per CU, the best of three timed launches.  The
+ * modular kernels (Section 4, "Symbolic Speedups": problems over prime
+ * fields) are built from these operations, so their roofline is stated
+ * against these rates beside the nominal int32 VALU peak.
+ *   kind SNC_MB_MONTGOMERY: Montgomery products a*b*2^-32 mod p (p < 2^30);
+ *        SNC_MB_MUL_LO:     32-bit low multiplies;
+ *        SNC_MB_MAD_U64:    32x32+64-bit multiply-adds.
+ * iters: chain steps per lane (>= 1).  d_buf: device scratch of at least
+ * 64 * 16 * 4 bytes per CU, caller-owned, overwritten.  On SNC_OK
+ * *ops_per_s receives the operations per second over the whole device.
+ * Errors: SNC_EINVAL (bad kind, iters or NULL), SNC_ENOMEM (buffer too
+ * small), SNC_EDEVICE. */
+enum { SNC_MB_MONTGOMERY = 0, SNC_MB_MUL_LO = 1, SNC_MB_MAD_U64 = 2 };
+int snc_microbench(snc_ctx* ctx, int kind, int32_t iters, void* d_buf, size_t buf_bytes, void* stream,
+                   double* ops_per_s);
+
 /* ---- resultant res_y(f, g) in Z[x] --------------------------------------
  * Host-only planning: degree bound D (Sylvester weighted-degree bound),
  * Hadamard-type coefficient bound B, number of primes k with prod p > 2B,

@@ -65,6 +65,7 @@ def lib():
                 "snc_last_error": (C.c_char_p, [VP]),
                 "snc_set_timing": (C.c_int, [VP, C.c_int]),
                 "snc_get_timing": (C.c_int, [VP, P(C.c_char_p), P(C.c_float), P(I32), C.c_int]),
+                "snc_microbench": (C.c_int, [VP, C.c_int, I32, VP, SZ, VP, P(C.c_double)]),
                 "snc_prime": (C.c_uint32, [I32]),
                 "snc_resultant_y_plan": (C.c_int, [P(Bipoly), P(Bipoly), P(Plan)]),
                 "snc_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
@@ -257,6 +258,18 @@ class Context:
     def set_timing(self, on: bool):
         lib().snc_set_timing(self.h, 1 if on else 0)
 
+    def microbench(self, kind: str, iters: int = 4096) -> float:
+        """Measured operations/s of one integer operation over the whole
+        device: kind 'montgomery', 'mul_lo' or 'mad_u64' (snc_microbench)."""
+        kinds = {"montgomery": 0, "mul_lo": 1, "mad_u64": 2}
+        props = self._torch.cuda.get_device_properties(self.device)
+        ws = self.workspace(props.multi_processor_count * 64 * 16 * 4)
+        rate = C.c_double(0.0)
+        st = lib().snc_microbench(self.h, kinds[kind], iters, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()),
+                                  self.stream_handle(), C.byref(rate))
+        self.check(st, "snc_microbench")
+        return rate.value
+
     def timing(self):
         cap = 32
         names = (C.c_char_p * cap)()
@@ -397,6 +410,39 @@ class ResultantBatch:
             self.close()
         except Exception:
             pass
+
+
+class PlainResultants:
+    """The plain form of a list of resultants: one snc_resultant_y call per
+    pair (plan, upload, one pipeline of launches, download; synchronised per
+    pair, no graph, nothing shared between pairs).  Inputs are marshalled
+    and outputs sized once, so run() times only the library calls."""
+
+    def __init__(self, pairs, ctx: Context | None = None, stream=None):
+        self.ctx = ctx or default_context()
+        self.keep = []
+        self.args = []
+        need = 256
+        for f, g in pairs:
+            bf, bg = _as_bipoly(f, self.keep), _as_bipoly(g, self.keep)
+            p = Plan()
+            self.ctx.check(lib().snc_resultant_y_plan(C.byref(bf), C.byref(bg), C.byref(p)), "plan")
+            u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, self.keep)
+            self.args.append((bf, bg, u, buf, p.deg_bound, max(p.out_nlimbs, 1)))
+            need = max(need, p.workspace_bytes)
+        self.ws = self.ctx.workspace(need)
+        self.stream = self.ctx.stream_handle(stream)
+
+    def run(self):
+        L, h, wsp, wsn = lib(), self.ctx.h, C.c_void_p(self.ws.data_ptr()), C.c_size_t(self.ws.numel())
+        for bf, bg, u, _buf, d, nl in self.args:
+            u.deg, u.nlimbs = d, nl
+            st = L.snc_resultant_y(h, C.byref(bf), C.byref(bg), wsp, wsn, self.stream, C.byref(u))
+            if st != SNC_OK:
+                self.ctx.check(st, "snc_resultant_y")
+
+    def results(self):
+        return [_read_upoly(u, buf) for _bf, _bg, u, buf, _d, _nl in self.args]
 
 
 def resultant_y_batch(pairs, ctx: Context | None = None, stream=None) -> list:

@@ -196,8 +196,30 @@ __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* 
 // register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
 // above each degree zero).  Branch-free inside an elementary step.  Returns
 // lc(Y), canonical.
+// Lane state of the elimination: every remainder so far of its expected
+// degree (EL_NORMAL); the first remainder whose leading coefficient vanished
+// was zero altogether (EL_ZERO: the two polynomials share a factor of
+// positive degree at this point, so the resultant is 0); or it was a
+// non-zero remainder of lower degree (EL_ABN: the instance goes to the
+// general elimination).  Only the first event counts: after a degree drop
+// the uniform schedule no longer computes a remainder sequence.
+constexpr int EL_NORMAL = 0, EL_ZERO = 1, EL_ABN = 2;
+
+// Check of a new remainder X (entries 0..C, top-aligned) after a step.
+// Lanes whose leading coefficient vanished scan the rest of it; on a
+// normal step the test is one comparison.
 template <int N, int C>
-__device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, bool& ok,
+__device__ __forceinline__ void lead_check(const uint32_t (&X)[N + 1], int& st, const PrimeC& c) {
+  if (canon(X[0], c.p) == 0 && st == EL_NORMAL) {
+    uint32_t nz = 0;
+#pragma unroll
+    for (int i = 1; i <= C; ++i) nz |= canon(X[i], c.p);
+    st = nz ? EL_ABN : EL_ZERO;
+  }
+}
+
+template <int N, int C>
+__device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, int& st,
                                           const PrimeC& c) {
   const uint32_t lcY = canon(Y[0], c.p);
 #pragma nounroll
@@ -207,7 +229,7 @@ __device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (
     for (int i = 0; i < C; ++i) X[i] = mmul2(lcY, X[i + 1], nlX, Y[i + 1], c.p, c.pinv);
     X[C] = 0;
   }
-  if (canon(X[0], c.p) == 0) ok = false;
+  lead_check<N, C>(X, st, c);
   return lcY;
 }
 
@@ -218,7 +240,7 @@ __device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (
 // (entries above C read as zero): 3 products and one reduction per entry
 // instead of 4 and 2, the same residues.  Values stay below 4p.
 template <int N, int C>
-__device__ __forceinline__ uint32_t rem2_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], bool& ok,
+__device__ __forceinline__ uint32_t rem2_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int& st,
                                            const PrimeC& c) {
   const uint32_t q0 = canon(Y[0], c.p), p0 = canon(X[0], c.p);
   const uint32_t a = mmulc(q0, q0, c.p, c.pinv);
@@ -232,18 +254,18 @@ __device__ __forceinline__ uint32_t rem2_c(uint32_t (&X)[N + 1], const uint32_t 
     X[i] = mmul3(a, x2, b, y2, cc, Y[i + 1], c.p, c.pinv);
   }
   X[C] = 0;
-  if (canon(X[0], c.p) == 0) ok = false;
+  lead_check<N, C>(X, st, c);
   return q0;
 }
 
 // rem2_c on the narrowest width (a multiple of 8) that holds deg X = a
 template <int N, int C>
-__device__ __forceinline__ uint32_t rem2_fit(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, bool& ok,
+__device__ __forceinline__ uint32_t rem2_fit(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, int& st,
                                              const PrimeC& c) {
   if constexpr (C > 8) {
-    if (a <= C - 8) return rem2_fit<N, C - 8>(X, Y, a, ok, c);
+    if (a <= C - 8) return rem2_fit<N, C - 8>(X, Y, a, st, c);
   }
-  return rem2_c<N, C>(X, Y, ok, c);
+  return rem2_c<N, C>(X, Y, st, c);
 }
 
 // Scale factors of the normal steps.  A normal step with divisor degree b
@@ -262,16 +284,16 @@ __device__ __forceinline__ void scale_step(uint32_t y, int b, uint32_t& P, uint3
 // >= C - 8, on arrays of width C; then the next narrower phase.
 template <int N, int C>
 __device__ __forceinline__ void elim_phases(uint32_t (&A)[N + 1], uint32_t (&B)[N + 1], int& a,
-                                            int& bb, bool& ok, uint32_t& P, uint32_t& Q, int& sg,
+                                            int& bb, int& st, uint32_t& P, uint32_t& Q, int& sg,
                                             const PrimeC& c) {
 #pragma nounroll
   while (bb >= 2 && bb >= C - 8) {
-    scale_step(rem2_c<N, C>(B, A, ok, c), bb, P, Q, c);  // B <- prem(B, A), degree bb-1
+    scale_step(rem2_c<N, C>(B, A, st, c), bb, P, Q, c);  // B <- prem(B, A), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
-    scale_step(rem2_c<N, C>(A, B, ok, c), bb, P, Q, c);  // A <- prem(A, B), degree bb-1
+    scale_step(rem2_c<N, C>(A, B, st, c), bb, P, Q, c);  // A <- prem(A, B), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
   }
-  if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, ok, P, Q, sg, c);
+  if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, st, P, Q, sg, c);
 }
 
 // LDSROWS: the wavefront first copies its prime's residues into LDS
@@ -327,8 +349,9 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   eval_rows<N>(A, r, ra, X, c);
   eval_rows<N>(B, r, rb, X, c);
 
-  bool ok = canon(A[0], c.p) != 0;
-  if (J.n >= 1 && canon(B[0], c.p) == 0) ok = false;
+  // formal degrees attained at this point, else the general elimination
+  int st = canon(A[0], c.p) != 0 ? EL_NORMAL : EL_ABN;
+  if (J.n >= 1 && canon(B[0], c.p) == 0) st = EL_ABN;
   uint32_t den = c.r1;
   int sg = J.sign;
   int a = J.m, bb = J.n;
@@ -339,15 +362,15 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
     // first remainder: A <- prem(A, B) with s = m - n + 1 elementary steps,
     // scale lc(B)^{s (n - 1)}
     const int s0 = a - bb + 1;
-    const uint32_t y0 = s0 == 2 ? rem2_fit<N, N>(A, B, a, ok, c) : rem_c<N, N>(A, B, s0, ok, c);
+    const uint32_t y0 = s0 == 2 ? rem2_fit<N, N>(A, B, a, st, c) : rem_c<N, N>(A, B, s0, st, c);
     den = mpow(y0, (uint32_t)(s0 * (bb - 1)), c);
     sg ^= (a & bb & 1); a = bb; bb -= 1;
     // from here on: dividend B (degree a), divisor A (degree bb)
     uint32_t P = c.r1, Q = c.r1;
-    elim_phases<N, N>(A, B, a, bb, ok, P, Q, sg, c);
+    elim_phases<N, N>(A, B, a, bb, st, P, Q, sg, c);
     den = mmulc(den, mmulc(Q, Q, c.p, c.pinv), c.p, c.pinv);
     if (bb == 1) {  // last step: divisor of degree 1, scale y^0
-      rem2_c<N, 8>(B, A, ok, c);
+      rem2_c<N, 8>(B, A, st, c);
       sg ^= (a & bb & 1); a = bb; bb -= 1;
       res = mpow(B[0], (uint32_t)a, c);
     } else {
@@ -357,8 +380,10 @@ __global__ __launch_bounds__(EE_BLOCK) void k_eval_elim(const ResJob* jobs, cons
   res = mmulc(res, minv(den, c), c.p, c.pinv);
   if (sg) res = mneg(res, c.p);
   if (!live) return;
-  ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] = ok ? res : 0u;
-  if (!ok) {
+  // a zero remainder with a divisor of positive degree: res = 0; an
+  // abnormal instance leaves a marker (never a residue) for the general pass
+  ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] = st == EL_NORMAL ? res : st == EL_ZERO ? 0u : ABN_MARK;
+  if (st == EL_ABN) {
     uint32_t idx = atomicAdd(abn_count, 1u);
     if (idx < abn_cap) abn_list[idx] = AbnEntry{jid, pi, j, 0};
   }
@@ -455,13 +480,16 @@ __device__ uint32_t res_general(uint32_t* F, int m, uint32_t* G, int n, const Pr
   }
 }
 
+// MAXY: the largest y-degree of the instances this variant runs (the size
+// of the per-lane value arrays)
+template <int MAXY>
 __device__ void general_instance(const ResJob& J, const RowDesc* rows, uint32_t* ws, int pi, int j) {
   const PrimeC c = g_primes[pi];
   const uint32_t* r = ws + J.res_off + (int64_t)pi * J.T;
   const uint32_t X = to_mont((uint32_t)j, c);
   const RowDesc* ra = rows + J.rows_off;
   const RowDesc* rb = ra + J.rstride;
-  uint32_t F[MAXY_GEN + 1], G[MAXY_GEN + 1];
+  uint32_t F[MAXY + 1], G[MAXY + 1];
   for (int t = 0; t <= J.m; ++t) F[J.m - t] = canon(horner_grouped(r, ra[t / ROWGRP], t % ROWGRP, X, c), c.p);
   for (int t = 0; t <= J.n; ++t) G[J.n - t] = canon(horner_grouped(r, rb[t / ROWGRP], t % ROWGRP, X, c), c.p);
   uint32_t res = res_general(F, J.m, G, J.n, c);
@@ -469,22 +497,44 @@ __device__ void general_instance(const ResJob& J, const RowDesc* rows, uint32_t*
   ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] = res;
 }
 
+// The abnormal instances of the register-resident elimination (y-degrees up
+// to MAXY_FAST): from the list when it held them all, else every instance
+// of the batch whose value carries the marker (inst_prefix: instances per
+// job, prefix sums over the njobs jobs).
 __global__ void k_elim_general(const ResJob* jobs, const RowDesc* rows, uint32_t* ws,
-                               const uint32_t* abn_count, const AbnEntry* list) {
+                               const uint32_t* abn_count, const AbnEntry* list, uint32_t cap,
+                               const int64_t* inst_prefix, int njobs) {
   const uint32_t cnt = *abn_count;
-  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cnt; idx += gridDim.x * blockDim.x) {
-    const AbnEntry e = list[idx];
-    const ResJob J = jobs[e.job];
-    general_instance(J, rows, ws, e.prime, e.point);
+  if (cnt == 0) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cnt <= cap) {
+    for (int64_t idx = t0; idx < cnt; idx += stride) {
+      const AbnEntry e = list[idx];
+      const ResJob J = jobs[e.job];
+      general_instance<MAXY_FAST>(J, rows, ws, e.prime, e.point);
+    }
+    return;
+  }
+  const int64_t ninst = inst_prefix[njobs];
+  for (int64_t idx = t0; idx < ninst; idx += stride) {
+    const int jj = find_job(inst_prefix, njobs, idx);
+    const ResJob J = jobs[jj];
+    const int64_t li = idx - inst_prefix[jj];
+    const int pi = (int)(li / (J.D + 1)), j = (int)(li % (J.D + 1));
+    if (J.m > MAXY_FAST) continue;  // computed whole by the general kernel, never marked
+    if (ws[J.pts_off + (int64_t)pi * (J.D + 1) + j] == ABN_MARK) general_instance<MAXY_FAST>(J, rows, ws, pi, j);
   }
 }
 
 void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,
-                         const uint32_t* abn_count, const AbnEntry* abn_list, int nthreads,
-                         hipStream_t s) {
-  int blocks = (nthreads + 63) / 64;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_elim_general, dim3(blocks), dim3(64), 0, s, jobs_d, rows_d, ws, abn_count, abn_list);
+                         const uint32_t* abn_count, const AbnEntry* abn_list, uint32_t cap,
+                         const int64_t* inst_prefix_d, int njobs, hipStream_t s) {
+  // enough lanes for a full list, at most 16 wavefronts per CU (grid-stride beyond)
+  int64_t blocks = ((int64_t)cap + 63) / 64;
+  blocks = blocks < 1 ? 1 : blocks > 256 * 16 ? 256 * 16 : blocks;
+  hipLaunchKernelGGL(k_elim_general, dim3((unsigned)blocks), dim3(64), 0, s, jobs_d, rows_d, ws, abn_count, abn_list,
+                     cap, inst_prefix_d, njobs);
 }
 
 __global__ void k_elim_general_all(const ResJob* jobs, const int32_t* job_list,
@@ -495,7 +545,7 @@ __global__ void k_elim_general_all(const ResJob* jobs, const int32_t* job_list,
     const int jj = find_job(prefix, njobs, idx);
     const ResJob J = jobs[job_list[jj]];
     const int64_t li = idx - prefix[jj];
-    general_instance(J, rows, ws, (int)(li / (J.D + 1)), (int)(li % (J.D + 1)));
+    general_instance<MAXY_GEN>(J, rows, ws, (int)(li / (J.D + 1)), (int)(li % (J.D + 1)));
   }
 }
 

@@ -70,6 +70,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   lay.pref_interp_blk = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtd = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtc = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_inst = off; off = align256(off + 8 * (NJ + 1));
   for (int j = 0; j < NJ; ++j) {
     const ResPlan& P = plans[lay.dev[j]];
     if (P.cls >= 0) lay.n_ee_jobs[P.cls]++; else lay.n_gen_jobs++;
@@ -128,8 +129,8 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     if (lay.n_ee_jobs[c] && !eval_elim_in_lds(lay.max_T_ee[c])) lay.reduce_in_eval = false;
   lay.abn_count_off = w * 4; w += 64;
   lay.abn_list_off = w * 4;
-  lay.abn_cap = (uint32_t)std::min<int64_t>(lay.total_inst, 0x7fffffff);
-  w += align_words((size_t)lay.total_inst * (sizeof(AbnEntry) / 4));
+  lay.abn_cap = abn_list_cap(lay.total_inst);
+  w += align_words((size_t)lay.abn_cap * (sizeof(AbnEntry) / 4));
   lay.out_off = w * 4;
   size_t ow = 0;
   for (int j = 0; j < NJ; ++j) {
@@ -194,22 +195,24 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   // the counter is cleared by the previous run's interpolation (and at preparation)
   if (!lay.reduce_in_eval) launch_reduce(jobs, (const int64_t*)(ws + lay.pref_red), NJ, lay.nb_red, wsw, wsw, abn_count, s);
   if (tm) tm->mark("reduce", lay.reduce_in_eval ? 0 : 1);
-  int nee = 0;
+  // one stage per register class (names: eval_elim_<width>), then the
+  // jobs above the register classes
+  static const char* const kEEStage[NCLS] = {"eval_elim_8", "eval_elim_16", "eval_elim_32", "eval_elim_48",
+                                             "eval_elim_64"};
   for (int c = 0; c < NCLS; ++c) {
     if (!lay.n_ee_jobs[c]) continue;
     launch_eval_elim(c, jobs, (const int32_t*)(ws + lay.list_ee[c]), (const int64_t*)(ws + lay.pref_ee[c]),
                      lay.n_ee_jobs[c], lay.nb_ee[c], lay.max_T_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap,
                      lay.reduce_in_eval, s);
-    ++nee;
+    if (tm) tm->mark(kEEStage[c], 1);
   }
   if (lay.n_gen_jobs) {
     launch_elim_general_all(jobs, (const int32_t*)(ws + lay.list_gen), (const int64_t*)(ws + lay.pref_gen),
                             lay.n_gen_jobs, lay.n_gen_inst, rows, wsw, s);
-    ++nee;
+    if (tm) tm->mark("eval_elim_general", 1);
   }
-  if (tm) tm->mark("eval_elim", nee);
-  launch_elim_general(jobs, rows, wsw, abn_count, abn_list,
-                      (int)std::min<int64_t>(std::max<int64_t>(lay.total_inst, 64), 16384), s);
+  launch_elim_general(jobs, rows, wsw, abn_count, abn_list, lay.abn_cap, (const int64_t*)(ws + lay.pref_inst), NJ,
+                      s);
   if (tm) tm->mark("elim_general", 1);
   if (lay.interp_blk)
     launch_interp_blk(jobs, (const int64_t*)(ws + lay.pref_interp_blk), NJ, lay.nb_interp_blk, wsw, abn_count, s);
@@ -238,6 +241,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   int64_t* pib = (int64_t*)(h + lay.pref_interp_blk);
   int64_t* pd = (int64_t*)(h + lay.pref_crtd);
   int64_t* pc = (int64_t*)(h + lay.pref_crtc);
+  int64_t* pn = (int64_t*)(h + lay.pref_inst);
   int64_t* pe[NCLS];
   int32_t* le[NCLS];
   int ne[NCLS] = {0};
@@ -250,7 +254,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   int32_t* lg = (int32_t*)(h + lay.list_gen);
   int ng = 0;
   pg[0] = 0;
-  pr[0] = pi[0] = pib[0] = pd[0] = pc[0] = 0;
+  pr[0] = pi[0] = pib[0] = pd[0] = pc[0] = pn[0] = 0;
   size_t cw = 0;
   for (int j = 0; j < NJ; ++j) {
     const int idx = lay.dev[j];
@@ -294,6 +298,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     pib[j + 1] = pib[j] + (int64_t)P.k * ((P.D + 1 + 63) / 64);
     pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
     pc[j + 1] = pc[j] + (n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
+    pn[j + 1] = pn[j] + (int64_t)P.k * n1;
     if (P.cls >= 0) {
       const int c = P.cls;
       le[c][ne[c]] = j;
@@ -322,6 +327,7 @@ void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& ke
   key.push_back(lay.n_gen_jobs);
   key.push_back((int64_t)lay.abn_count_off); key.push_back((int64_t)lay.abn_list_off);
   for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_interp_blk, lay.pref_crtd, lay.pref_crtc,
+                   lay.pref_inst,
                    lay.pref_gen, lay.list_gen})
     key.push_back((int64_t)o);
   for (int c = 0; c < NCLS; ++c) { key.push_back((int64_t)lay.pref_ee[c]); key.push_back((int64_t)lay.list_ee[c]); }
@@ -415,7 +421,9 @@ static bool prepared_outputs(snc_prepared* pr, snc_upoly* out) {
 static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer& tm) {
   const int part = PIPE_ALL;
   snc_ctx* c = pr->c;
-  if (!pr->use_graph) {
+  // with timing on, the same launches go straight to the stream between
+  // events (a replayed graph cannot be timed per stage)
+  if (!pr->use_graph || tm.on) {
     launch_pipeline(pr->lay, pr->ws, stream, tm.on ? &tm : nullptr, part);
     HIPCHK(hipGetLastError());
     return SNC_OK;
@@ -432,7 +440,6 @@ static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer&
     if (e != hipSuccess) { gx = nullptr; c->err = std::string("graph instantiate: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   }
   HIPCHK(hipGraphLaunch(gx, stream));
-  if (tm.on) tm.mark("pipeline", 1);
   return SNC_OK;
 }
 
@@ -465,7 +472,7 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   if (!prepared_outputs(pr, out)) return SNC_ERANGE;
   if (pr->lay.dev.empty()) return SNC_OK;
   HIPCHK(hipSetDevice(c->device));
-  StageTimer tm{c, stream, c->timing && !pr->use_graph};
+  StageTimer tm{c, stream, c->timing};
   tm.start();
   int st = launch_prepared_all(pr, stream, tm);
   if (st) return st;

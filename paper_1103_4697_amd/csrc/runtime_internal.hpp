@@ -50,6 +50,7 @@ struct BatchLayout {
   size_t jobs_off = 0, rows_off = 0, coef_off = 0;        // bytes
   size_t pref_red = 0, pref_interp = 0, pref_crtd = 0, pref_crtc = 0, pref_gen = 0;  // bytes
   size_t pref_interp_blk = 0;        // bytes: block prefix of the block-parallel interpolation
+  size_t pref_inst = 0;              // bytes: instance prefix k (D+1) over the jobs
   bool interp_blk = false;           // every job fits the block-parallel interpolation
   bool reduce_in_eval = false;       // the evaluation kernel reduces the inputs (no reduction launch)
   size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes

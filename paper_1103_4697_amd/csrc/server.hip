@@ -111,10 +111,50 @@ struct snc_server {
 namespace snc {
 namespace {
 
+size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Device bytes of a batch of requests of one kind: its joint workspace.
+size_t batch_bytes(const std::vector<Request*>& batch, int kind, size_t fallback) {
+  if (kind == 1) {
+    std::vector<snc_upoly> as(batch.size()), bs(batch.size());
+    for (size_t i = 0; i < batch.size(); ++i) { as[i] = batch[i]->a; bs[i] = batch[i]->b; }
+    snc_plan tot{};
+    if (snc_gcd_z_batch_plan((int32_t)batch.size(), as.data(), bs.data(), nullptr, &tot) != SNC_OK) return fallback;
+    return std::max<size_t>(tot.workspace_bytes, 256);
+  }
+  std::vector<ResPlan> plans(batch.size());
+  std::string err;
+  for (size_t i = 0; i < batch.size(); ++i) {
+    Operand F, G;
+    parse_bipoly(&batch[i]->f, F, err);
+    parse_bipoly(&batch[i]->g, G, err);
+    plan_resultant(F, G, plans[i], err);
+  }
+  BatchLayout lay;
+  layout_batch(plans, lay);
+  return std::max<size_t>(lay.total_bytes, 256);
+}
+
+// Finish a request that cannot run (lock held).
+void fail_request(snc_server* s, Request* r, int status, const std::string& msg) {
+  const auto now = Clock::now();
+  r->status = status;
+  r->err = msg;
+  r->t_done = now;
+  s->times[r->ticket] = {secs(r->t_submit), secs(now)};
+  s->completed += 1;
+}
+
 // Take work for one worker: a batch of admitted requests of one kind.
 // Called with the lock held; returns false if nothing could be admitted.
-bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t& bytes) {
+// The head request is probed with its own footprint (a batch of one needs
+// no more), later ones with headroom for the joint header; a batch whose
+// joint workspace does not fit shrinks to its head request, which waits
+// only while other work holds pool bytes (it fits an empty pool, else it
+// fails with SNC_ENOMEM).
+bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t& bytes, bool& failed) {
   batch.clear();
+  failed = false;
   if (s->queue.empty() || s->slots_used >= s->max_slots) return false;
   const int kind = s->reqs[s->queue.front()]->kind;
   // grow a batch of the first request's kind while the summed footprint and the slots allow
@@ -124,7 +164,7 @@ bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t&
     if (r->kind != kind) { ++it; continue; }
     if (s->slots_used + (int)batch.size() >= s->max_slots) break;
     size_t probe = 0;
-    const size_t want = total + r->footprint + 65536;  // headroom for the batch header
+    const size_t want = batch.empty() ? r->footprint : total + r->footprint + 65536;
     if (!s->alloc.alloc(want, probe)) break;
     s->alloc.release(probe, want);
     total += r->footprint;
@@ -132,28 +172,22 @@ bool take_work(snc_server* s, std::vector<Request*>& batch, size_t& off, size_t&
     it = s->queue.erase(it);
   }
   if (batch.empty()) return false;
-  // the batch's real workspace is computed from its joint layout
-  if (kind == 1) {
-    std::vector<snc_upoly> as(batch.size()), bs(batch.size());
-    for (size_t i = 0; i < batch.size(); ++i) { as[i] = batch[i]->a; bs[i] = batch[i]->b; }
-    snc_plan tot{};
-    if (snc_gcd_z_batch_plan((int32_t)batch.size(), as.data(), bs.data(), nullptr, &tot) != SNC_OK) tot.workspace_bytes = total;
-    bytes = std::max<size_t>(tot.workspace_bytes, 256);
-  } else {
-    std::vector<ResPlan> plans(batch.size());
-    std::string err;
-    for (size_t i = 0; i < batch.size(); ++i) {
-      Operand F, G;
-      parse_bipoly(&batch[i]->f, F, err);
-      parse_bipoly(&batch[i]->g, G, err);
-      plan_resultant(F, G, plans[i], err);
+  while (true) {
+    bytes = batch_bytes(batch, kind, total);
+    if (s->alloc.alloc(bytes, off)) break;
+    if (batch.size() > 1) {
+      // give back all but the head, in their order
+      for (size_t i = batch.size() - 1; i >= 1; --i) s->queue.push_front(batch[i]->ticket);
+      batch.resize(1);
+      continue;
     }
-    BatchLayout lay;
-    layout_batch(plans, lay);
-    bytes = std::max<size_t>(lay.total_bytes, 256);
-  }
-  if (!s->alloc.alloc(bytes, off)) {
-    for (auto it = batch.rbegin(); it != batch.rend(); ++it) s->queue.push_front((*it)->ticket);
+    if (round256(bytes) > s->pool_bytes) {
+      fail_request(s, batch[0], SNC_ENOMEM, "request workspace of " + std::to_string(bytes) +
+                                                 " bytes exceeds the pool of " + std::to_string(s->pool_bytes));
+      failed = true;
+    } else {
+      s->queue.push_front(batch[0]->ticket);  // in-flight work frees pool bytes and notifies
+    }
     batch.clear();
     return false;
   }
@@ -174,7 +208,15 @@ void worker_main(snc_server* s) {
     size_t off = 0, bytes = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv.wait(lk, [&] { return s->stop || take_work(s, batch, off, bytes); });
+      bool failed = false;
+      s->cv.wait(lk, [&] {
+        if (s->stop) return true;
+        while (true) {  // after a request failed, the next one may be admitted
+          if (take_work(s, batch, off, bytes, failed)) return true;
+          if (!failed) return false;
+          s->cv_done.notify_all();
+        }
+      });
       if (batch.empty() && s->stop) break;
     }
     void* ws = s->pool + off;
@@ -265,7 +307,7 @@ int snc_server_create(snc_ctx* ctx, void* d_pool, size_t pool_bytes, int32_t max
 
 static int submit(snc_server* s, Request* r, uint64_t* ticket) {
   std::lock_guard<std::mutex> lk(s->mu);
-  if (r->footprint > s->pool_bytes) { delete r; return SNC_ENOMEM; }
+  if (round256(r->footprint) > s->pool_bytes) { delete r; return SNC_ENOMEM; }
   r->ticket = s->next_ticket++;
   r->t_submit = Clock::now();
   s->reqs[r->ticket] = r;

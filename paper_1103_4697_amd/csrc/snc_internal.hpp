@@ -105,6 +105,13 @@ constexpr int32_t GCD_SLOT_UNUSABLE = -2;
 struct AbnEntry {
   int32_t job, prime, point, pad;
 };
+// value left at an abnormal instance's point until the general pass (no residue is >= 2^30)
+constexpr uint32_t ABN_MARK = 0xffffffffu;
+// capacity of the abnormal-instance list of a batch of ninst instances
+inline uint32_t abn_list_cap(int64_t ninst) {
+  const int64_t c = ninst / 16 > 4096 ? ninst / 16 : 4096;
+  return (uint32_t)(c < ninst ? c : ninst);
+}
 
 __host__ __device__ inline int lx_of(int k) { return (30 * k + 31) / 32 + 2; }
 
@@ -133,9 +140,11 @@ void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
                       const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
                       uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
                       bool reduce_in, hipStream_t s);
+// abnormal instances: the list when count <= cap, else a scan of every
+// instance for ABN_MARK (inst_prefix: prefix sums of k (D+1) over the jobs)
 void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,
-                         const uint32_t* abn_count, const AbnEntry* abn_list, int nthreads,
-                         hipStream_t s);
+                         const uint32_t* abn_count, const AbnEntry* abn_list, uint32_t cap,
+                         const int64_t* inst_prefix_d, int njobs, hipStream_t s);
 void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
                              const int64_t* inst_prefix_d, int njobs, int64_t ninst,
                              const RowDesc* rows_d, uint32_t* ws, hipStream_t s);

@@ -118,6 +118,40 @@ def test_edge_cases(snc):
     check(snc, f4, g4)
 
 
+def sparse_abnormal_pair(rng, dx1, dx2, bits):
+    """f = y^4 + c1(x), g = y^2 + c2(x): at every point the first remainder
+    f rem g = c1 + c2^2 is a constant where a linear one is expected, so
+    every (prime, point) instance takes the general elimination.  With g's
+    roots +-sqrt(-c2), res_y(f, g) = (c1 + c2^2)^2."""
+    lim = 1 << (bits - 1)
+    c1 = [int(v) for v in rng.integers(-lim, lim, size=dx1 + 1)]
+    c2 = [int(v) for v in rng.integers(-lim, lim, size=dx2 + 1)]
+    f = [c1, [0], [0], [0], [1]]
+    g = [c2, [0], [1]]
+    s = zx.add(c1, zx.mul(c2, c2))
+    return f, g, zx.mul(s, s)
+
+
+def test_abnormal_instances_list_and_scan(snc):
+    """Abnormal instances within the list's capacity (list mode) and beyond
+    it (scan of the values for the marker), alone and beside normal pairs
+    and a common-factor pair."""
+    rng = np.random.default_rng(41)
+    small = sparse_abnormal_pair(rng, 20, 10, 8)       # few instances: list
+    large = sparse_abnormal_pair(rng, 200, 100, 32)    # k (D+1) > 4096: scan
+    assert snc.resultant_plan(*large[:2]).nprimes * (snc.resultant_plan(*large[:2]).deg_bound + 1) > 4096
+    for f, g, want in (small, large):
+        assert snc.resultant_y(f, g) == want == R.resultant_y(f, g)
+    h = [[1, 1], [2], [1]]
+    fa = synth.bivariate_product(h, [[3], [1, 1]])
+    gb = synth.bivariate_product(h, [[-1, 2], [0, 0, 1], [1]])
+    a, b = rand_pair(rng, 6, 5, 4, 4, 16)
+    pairs = [(a, b), large[:2], (fa, gb), small[:2], (b, a)]
+    got = snc.resultant_y_batch(pairs)
+    assert got[1] == large[2] and got[3] == small[2] and got[2] == []
+    assert got[0] == R.resultant_y(a, b) and got[4] == R.resultant_y(b, a)
+
+
 def test_general_path_above_register_classes(snc):
     rng = np.random.default_rng(11)
     f, g = rand_pair(rng, 70, 3, 1, 2, 12)
@@ -194,6 +228,34 @@ def test_batch_matches_plain_and_oracle(snc):
     first = b.results()
     b.run()
     assert b.results() == first == batch
+
+
+def test_config2_full_draw(snc):
+    """The batched workload exactly as it is timed: all 512 pairs of the
+    seeded draw in one prepared batch.  The 51 planted common-factor pairs
+    are exactly 0 and no other pair is; every pair equals its plain run;
+    every pair agrees with the oracle's determinant modulo a 61-bit prime at
+    a random point; the three cheapest pairs equal the oracle's resultant
+    coefficient by coefficient."""
+    pairs, common = synth.config2()
+    assert len(pairs) == 512 and len(common) == 51
+    b = snc.ResultantBatch(pairs)
+    b.run()
+    got = b.results()
+    for i in range(len(pairs)):
+        assert (got[i] == []) == (i in common), i
+    plain = snc.PlainResultants(pairs)
+    plain.run()
+    assert plain.results() == got
+    rng = random.Random(512)
+    for i, (f, g) in enumerate(pairs):
+        x0 = rng.randrange(Q61)
+        assert zx.evaluate(got[i], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61), i
+    cost = sorted(range(len(pairs)), key=lambda i: (b.each[i].deg_bound + 1) * len(pairs[i][0]) ** 3)
+    for i in cost[:3]:
+        assert got[i] == R.resultant_y_by_points(*pairs[i], processes=1), i
+    b.run()
+    assert b.results() == got   # a second replay of the captured graph
 
 
 @pytest.mark.parametrize("da,db", [(63, 20), (64, 32), (1000, 500), (1023, 300), (1024, 512)])

@@ -80,3 +80,23 @@ def test_oversized_request_refused(snc):
     with pytest.raises(snc.SncError):
         srv.submit_resultant(f, g)
     srv.close()
+
+
+def test_pool_just_above_one_request(snc):
+    """A pool a little larger than one request's own workspace (less than
+    the headroom a joint batch reserves): the request is admitted alone and
+    finishes, requests behind it follow one at a time, and a request larger
+    than the pool is refused at submission -- nothing waits forever."""
+    rng = np.random.default_rng(21)
+    f, g = synth.random_pair(rng, 8, 7, 16, 16)
+    need = snc.resultant_plan(f, g).workspace_bytes
+    pool = (need + 255) // 256 * 256 + 1024
+    srv = snc.Server(pool_bytes=pool, max_slots=4, nstreams=2)
+    t = [srv.submit_resultant(f, g) for _ in range(3)]
+    assert srv.wait(3, 30.0)
+    want = snc.resultant_y(f, g)
+    assert all(srv.poll(x) == want for x in t)
+    big = synth.random_pair(rng, 20, 20, 32, 32)
+    with pytest.raises(snc.SncError):
+        srv.submit_resultant(*big)
+    srv.close()
