@@ -284,23 +284,21 @@ def batch_stage_roofline(snc, pairs, plans, stages, ceilings, workload_tag):
         crt_ops += crt_lane_ops(k, L) * (D + 1)
         ee_bytes += 4 * nl * T + 4 * k * T + 4 * k * (D + 1)      # limbs in, residues kept, values out
         ip_bytes += 12 * k * (D + 1)                               # values, 1/t! table, coefficients
-        crd_bytes += 8 * k * (D + 1) + 2 * k * k                   # coefficients in, digits out, W tiles
-        crc_bytes += 4 * k * (D + 1) + 4 * (D + 1) * L + 4 * k * L  # digits, output limbs, prefix products
+        crd_bytes += 4 * k * (D + 1) + 2 * k * k                   # coefficients mod p in, constants P_j mod p_i
+        crc_bytes += 4 * (D + 1) * L + 4 * k * L                    # output limbs, prefix products P_j
     ee_ms = sum(v for kk, v in stages.items() if kk.startswith("eval_elim"))
+    crt_ms = sum(v for kk, v in stages.items() if kk.startswith("crt"))
     src_res = "paper_1103_4697_amd/csrc/kernels_res.hip"
     recs = {
         "eval_elim": roof("eval_elim (all register classes)", ee_ops, ee_ms,
                           profiled_traffic("eval_elim", src_res, workload_tag), ceilings, ee_bytes),
         "interp": roof("interp", ip_ops, stages.get("interp", float("nan")),
                        profiled_traffic("interp", src_res, workload_tag), ceilings, ip_bytes),
-        "crt": roof("crt_digits + crt_combine", crt_ops,
-                    stages.get("crt_digits", float("nan")) + stages.get("crt_combine", float("nan")),
-                    None, ceilings, crd_bytes + crc_bytes),
+        "crt": roof("crt (all launches: digits and binary value)", crt_ops, crt_ms,
+                    profiled_traffic("crt", src_res, workload_tag), ceilings, crd_bytes + crc_bytes),
     }
     hbm = {"eval_elim": recs["eval_elim"]["hbm_gbps"], "interp": recs["interp"]["hbm_gbps"],
-           "crt_digits": round(crd_bytes / (stages.get("crt_digits", float("nan")) * 1e-3) / 1e9, 2),
-           "crt_combine": round(crc_bytes / (stages.get("crt_combine", float("nan")) * 1e-3) / 1e9, 2),
-           "peak": PEAK_HBM_GBPS}
+           "crt": recs["crt"]["hbm_gbps"], "peak": PEAK_HBM_GBPS}
     return recs, hbm, ee_ms
 
 

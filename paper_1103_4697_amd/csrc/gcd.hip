@@ -827,9 +827,10 @@ static int gcd_batch(snc_ctx* ctx, GcdTimer& tm, std::vector<GcdProb>& P, void* 
                         emins[i], ws, (int64_t)p.wv, (int64_t)p.uv, (int64_t)p.vv, stream);
       CrtTables tb{(const PrimeC*)(ws + p.primes), ws + p.garner, ws + p.wtab, ws + p.ptab, ks, p.lg};
       const int64_t* pd = (const int64_t*)(h + p.prefd);
-      launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefd), 3, pd[3], ws, stream);
+      launch_crt_digits(tb, (const ResJob*)(ws + p.jobs), nullptr, (const int64_t*)(ws + p.prefd), 3, pd[3], ws, stream);
       const int64_t* pc = (const int64_t*)(h + p.prefc);
-      launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), (const int64_t*)(ws + p.prefc), 3, pc[3], ks, ws, stream);
+      launch_crt_combine(tb, (const ResJob*)(ws + p.jobs), nullptr, (const int64_t*)(ws + p.prefc), 3, pc[3], ks, ws,
+                         stream);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync((uint8_t*)ctx->h_out + (L.out_begin - L.e_begin) * 4, ws + L.out_begin,

@@ -19,8 +19,8 @@ __device__ uint32_t g_ptab[(KMAX + 1) * LPS];  // row j: P_j = prod_{l<j} p_l, l
 __global__ void k_interp(const ResJob* jobs, const int64_t* prefix, int njobs, uint32_t* ws, uint32_t* zero_word);
 
 // per-device kernel attributes (called once per device before any launch)
-__global__ void k_crt_combine(CrtTables tb, const ResJob* jobs, const int64_t* prefix, int njobs, int lx_max,
-                              uint32_t* ws);
+__global__ void k_crt_combine(CrtTables tb, const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
+                              int njobs, int lx_max, uint32_t* ws);
 
 hipError_t configure_kernels() {
   hipError_t e = hipFuncSetAttribute((const void*)k_interp, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -891,12 +891,13 @@ constexpr int CRT_TILE = 64 * 64;                          // words of one W til
 constexpr int CRT_PRE = CRT_TILE / (64 * CRT_COEF_PER_BLOCK);  // tile words fetched per thread
 
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTables tb, const ResJob* jobs,
+                                                                        const int32_t* job_list,
                                                                         const int64_t* prefix,
                                                                         int njobs, uint32_t* ws) {
   __shared__ uint32_t wt[2][CRT_TILE];  // tile (s, s2): [q][l] = W[64 s + q][64 s2 + l]
   const int64_t b = xcd_block(blockIdx.x, gridDim.x);
   const int jj = find_job(prefix, njobs, b);
-  const ResJob J = jobs[jj];
+  const ResJob J = jobs[job_list ? job_list[jj] : jj];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t = (int)(b - prefix[jj]) * CRT_COEF_PER_BLOCK + wave;
   const bool active = t <= J.D;  // the block's waves share one job; idle ones still meet the barriers
@@ -988,13 +989,14 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_digits(CrtTable
 // subtracts M = P_k when X > (M-1)/2 (decided on the digits: (M-1)/2 has
 // digits (p_j - 1)/2) and writes L two's-complement limbs.
 __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTables tb, const ResJob* jobs,
+                                                                         const int32_t* job_list,
                                                                          const int64_t* prefix, int njobs,
                                                                          int lx_max, uint32_t* ws) {
   constexpr int C = CRT_COMB_PER_BLOCK;
   extern __shared__ uint32_t csm[];
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
-  const ResJob J = jobs[jj];
+  const ResJob J = jobs[job_list ? job_list[jj] : jj];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int t0 = (int)(b - prefix[jj]) * C;
   const int nc = min(C, J.D + 1 - t0);  // coefficients of this block (>= 1)
@@ -1063,22 +1065,147 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
   for (int l = lx; l < J.L; ++l) out[l] = sub ? 0xffffffffu : 0u;
 }
 
-void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, uint32_t* ws, hipStream_t s) {
-  if (nblocks <= 0) return;
-  hipLaunchKernelGGL(k_crt_digits, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), 0, s, tb,
-                     jobs_d, prefix_d, njobs, ws);
+// Chinese remaindering with few primes (k <= KC <= CRT_KS), the usual case of
+// batched resultants: one lane per coefficient, so that every table constant
+// is uniform across the wavefront (scalar loads) and no lane idles on a
+// short prime list.
+//   digits (Garner): y_i = (r_i - S_i) (P_i mod p_i)^-1 mod p_i with
+//     S_i = sum_{j<i} y_j (P_j mod p_i), summed sixteen products per
+//     reduction; the lane's digits wait in LDS (digit j at yl[64 j + lane]).
+//   binary value: Horner's rule X <- X p_j + y_j from the top digit down in
+//     LC registers, the multiply-add chain touching only the limbs X can
+//     occupy so far (after digit j, X < P_k / P_j < 2^(30 (k - j))).
+//   balanced result: X - M when X > (M-1)/2, decided on the digits on the
+//     way down ((M-1)/2 has digits (p_j - 1)/2); L two's-complement limbs.
+constexpr int CRT_KS = 128;                 // largest prime count of this path
+__device__ uint32_t g_wts[CRT_KS * CRT_KS];  // [i][j] = Montgomery form of P_j mod p_i for j < i, else 0
+
+__global__ void k_crt_small_init() {
+  const int i = blockIdx.x;
+  for (int j = threadIdx.x; j < CRT_KS; j += blockDim.x)
+    g_wts[i * CRT_KS + j] = j < i ? g_wtab[(int64_t)j * KMAX + i] : 0u;
 }
 
-void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                        int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
+void launch_crt_small_init(hipStream_t s) {
+  static_assert(CRT_KS <= KMAX, "small-path primes come from the table");
+  hipLaunchKernelGGL(k_crt_small_init, dim3(CRT_KS), dim3(64), 0, s);
+}
+
+template <int KC>
+__global__ __launch_bounds__(64) void k_crt_small(const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
+                                                  int njobs, uint32_t* ws) {
+  static_assert(KC <= CRT_KS, "prime capacity of the small path");
+  constexpr int LC = (30 * KC + 31) / 32 + 2;  // limbs of X (as lx_of)
+  __shared__ uint32_t yl[KC * 64];
+  const int64_t b = blockIdx.x;
+  const int jj = find_job(prefix, njobs, b);
+  const ResJob J = jobs[job_list[jj]];
+  const int lane = threadIdx.x;
+  const int t0 = (int)(b - prefix[jj]) * 64 + lane;
+  const bool live = t0 <= J.D;
+  const int t = live ? t0 : J.D;  // lanes past the last coefficient repeat it and store nothing
+  const int k = J.k, n1 = J.D + 1;
+  const uint32_t* V = ws + J.val_off + t;
+  for (int i = 0; i < k; ++i) {
+    const PrimeC c = g_primes[i];
+    const uint32_t* w = g_wts + i * CRT_KS;
+    uint32_t S = 0;  // < 2p
+    for (int j0 = 0; j0 < i; j0 += 16) {
+      // y_j < p and W < p: sixteen products stay below 2^64 (four partial
+      // sums); sum 2^-32 = hi + REDC(lo), hi < 4p, REDC(lo) <= p
+      uint64_t part[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int j = j0 + u;
+        const bool in = j < i;  // uniform
+        const uint32_t y = in ? yl[64 * (in ? j : 0) + lane] : 0u;
+        const uint32_t wv = in ? w[in ? j : 0] : 0u;
+        part[u & 3] += (uint64_t)y * wv;
+      }
+      const uint64_t sum = (part[0] + part[1]) + (part[2] + part[3]);
+      uint32_t hi = (uint32_t)(sum >> 32);
+      const uint32_t h2 = hi - 2 * c.p;
+      hi = h2 < hi ? h2 : hi;                                         // [0, 2p)
+      uint32_t v = hi + redc((uint64_t)(uint32_t)sum, c.p, c.pinv);  // < 3p + 1
+      const uint32_t v2 = v - 2 * c.p;
+      v = v2 < v ? v2 : v;  // [0, 2p)
+      S += v;
+      const uint32_t s2 = S - 2 * c.p;
+      S = s2 < S ? s2 : S;  // [0, 2p)
+    }
+    const uint32_t r = V[(int64_t)i * n1];
+    yl[64 * i + lane] = canon(redc((uint64_t)msub(r, canon2(S, c.p), c.p) * g_garner[i], c.p, c.pinv), c.p);
+  }
+  uint32_t X[LC];
+#pragma unroll
+  for (int l = 0; l < LC; ++l) X[l] = 0;
+  int cmp = 0;  // sign of X - (M-1)/2, from the top digit down
+  for (int j = k - 1; j >= 0; --j) {
+    const uint32_t p = g_primes[j].p;
+    const uint32_t y = yl[64 * j + lane];
+    const uint32_t h = (p - 1) >> 1;
+    if (cmp == 0 && y != h) cmp = y > h ? 1 : -1;
+    const int len = (30 * (k - j) + 31) / 32 + 1;  // limbs X can occupy after this step (uniform)
+    uint64_t carry = y;
+#pragma unroll
+    for (int l0 = 0; l0 < LC; l0 += 8) {
+      if (l0 < len) {  // uniform: chunks above X's length are skipped (they hold zeros)
+#pragma unroll
+        for (int l = l0; l < l0 + 8 && l < LC; ++l) {
+          const uint64_t v = (uint64_t)X[l] * p + carry;
+          X[l] = (uint32_t)v;
+          carry = v >> 32;
+        }
+      }
+    }
+  }
+  const bool sub = cmp > 0;
+  if (sub) {  // X - M, M = P_k (uniform limbs), two's complement over LC limbs
+    const uint32_t* M = g_ptab + (int64_t)k * LPS;
+    uint32_t borrow = 0;
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+      const uint64_t d = (uint64_t)X[l] - M[l] - borrow;
+      X[l] = (uint32_t)d;
+      borrow = (uint32_t)(d >> 63);
+    }
+  }
+  if (!live) return;
+  uint32_t* out = ws + J.out_off + (int64_t)t * J.L;
+  const int L = J.L;
+#pragma unroll
+  for (int l = 0; l < LC; ++l)
+    if (l < L) out[l] = X[l];
+  for (int l = LC; l < L; ++l) out[l] = sub ? 0xffffffffu : 0u;
+}
+
+void launch_crt_small(int cls, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
+                      int64_t nblocks, uint32_t* ws, hipStream_t s) {
+  if (nblocks <= 0) return;
+  const dim3 g((unsigned)nblocks), blk(64);
+  switch (CRT_SMALL_K[cls]) {
+    case 32: hipLaunchKernelGGL(k_crt_small<32>, g, blk, 0, s, jobs_d, job_list_d, prefix_d, njobs, ws); break;
+    case 64: hipLaunchKernelGGL(k_crt_small<64>, g, blk, 0, s, jobs_d, job_list_d, prefix_d, njobs, ws); break;
+    default: hipLaunchKernelGGL(k_crt_small<128>, g, blk, 0, s, jobs_d, job_list_d, prefix_d, njobs, ws); break;
+  }
+}
+
+void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d,
+                       int njobs, int64_t nblocks, uint32_t* ws, hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_crt_digits, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), 0, s, tb,
+                     jobs_d, job_list_d, prefix_d, njobs, ws);
+}
+
+void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d,
+                        int njobs, int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s) {
   if (nblocks <= 0) return;
   const int lxm = lx_of(kmax);
   const size_t shmem = (size_t)CRT_COMB_PER_BLOCK * 3 * lxm * sizeof(uint32_t);
   static_assert((size_t)CRT_COMB_PER_BLOCK * 3 * ((30 * KMAX + 31) / 32 + 2) * 4 <= 160 * 1024,
                 "combination buffers for the whole table fit the LDS of a CU");
   hipLaunchKernelGGL(k_crt_combine, dim3((unsigned)nblocks), dim3(64 * CRT_COEF_PER_BLOCK), shmem, s, tb, jobs_d,
-                     prefix_d, njobs, lxm, ws);
+                     job_list_d, prefix_d, njobs, lxm, ws);
 }
 
 CrtTables global_crt_tables() {

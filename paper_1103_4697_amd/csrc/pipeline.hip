@@ -3,7 +3,9 @@
 // the batched call (one captured HIP graph per batch shape, replayed).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <functional>
+#include <thread>
 
 #include <algorithm>
 #include <cstring>
@@ -70,6 +72,15 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   lay.pref_interp_blk = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtd = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtc = off; off = align256(off + 8 * (NJ + 1));
+  for (int j = 0; j < NJ; ++j) {
+    const int cc = crt_small_class(plans[lay.dev[j]].k);
+    if (cc >= 0) lay.n_crts_jobs[cc]++; else lay.n_crtb_jobs++;
+  }
+  for (int c = 0; c < NCRT_SMALL; ++c) {
+    lay.pref_crts[c] = off; off = align256(off + 8 * (lay.n_crts_jobs[c] + 1));
+    lay.list_crts[c] = off; off = align256(off + 4 * std::max(lay.n_crts_jobs[c], 1));
+  }
+  lay.list_crtb = off; off = align256(off + 4 * std::max(lay.n_crtb_jobs, 1));
   lay.pref_inst = off; off = align256(off + 8 * (NJ + 1));
   for (int j = 0; j < NJ; ++j) {
     const ResPlan& P = plans[lay.dev[j]];
@@ -111,8 +122,13 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.nb_red += (int64_t)P.k * ((P.T + 255) / 256);
     lay.nb_interp += P.k;
     lay.nb_interp_blk += (int64_t)P.k * ((n1 + 63) / 64);
-    lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
-    lay.nb_crtc += (int64_t)((n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK);
+    const int cc = crt_small_class(P.k);
+    if (cc >= 0) {
+      lay.nb_crts[cc] += (int64_t)((n1 + 63) / 64);
+    } else {
+      lay.nb_crtd += (int64_t)((n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
+      lay.nb_crtc += (int64_t)((n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK);
+    }
     lay.max_k = std::max(lay.max_k, P.k);
     if (P.cls >= 0) {
       lay.nb_ee[P.cls] += (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
@@ -148,8 +164,6 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   w += lay.sq_words;
   lay.total_bytes = w * 4;
 }
-
-namespace {
 
 struct StageTimer {
   snc_ctx* c;
@@ -221,11 +235,22 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   if (tm) tm->mark("interp", 1);
   }
   if (part == PIPE_TO_INTERP) return;
-  const CrtTables tb = global_crt_tables();
-  launch_crt_digits(tb, jobs, (const int64_t*)(ws + lay.pref_crtd), NJ, lay.nb_crtd, wsw, s);
-  if (tm) tm->mark("crt_digits", 1);
-  launch_crt_combine(tb, jobs, (const int64_t*)(ws + lay.pref_crtc), NJ, lay.nb_crtc, lay.max_k, wsw, s);
-  if (tm) tm->mark("crt_combine", 1);
+  static const char* const kCrtStage[NCRT_SMALL] = {"crt_small_32", "crt_small_64", "crt_small_128"};
+  for (int c = 0; c < NCRT_SMALL; ++c) {
+    if (!lay.n_crts_jobs[c]) continue;
+    launch_crt_small(c, jobs, (const int32_t*)(ws + lay.list_crts[c]), (const int64_t*)(ws + lay.pref_crts[c]),
+                     lay.n_crts_jobs[c], lay.nb_crts[c], wsw, s);
+    if (tm) tm->mark(kCrtStage[c], 1);
+  }
+  if (lay.n_crtb_jobs) {
+    const CrtTables tb = global_crt_tables();
+    const int32_t* lb = (const int32_t*)(ws + lay.list_crtb);
+    launch_crt_digits(tb, jobs, lb, (const int64_t*)(ws + lay.pref_crtd), lay.n_crtb_jobs, lay.nb_crtd, wsw, s);
+    if (tm) tm->mark("crt_digits", 1);
+    launch_crt_combine(tb, jobs, lb, (const int64_t*)(ws + lay.pref_crtc), lay.n_crtb_jobs, lay.nb_crtc, lay.max_k,
+                       wsw, s);
+    if (tm) tm->mark("crt_combine", 1);
+  }
 }
 
 // Fill the upload block: job descriptors, row descriptors, block prefixes,
@@ -250,6 +275,16 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     le[c] = (int32_t*)(h + lay.list_ee[c]);
     pe[c][0] = 0;
   }
+  int64_t* ps[NCRT_SMALL];
+  int32_t* ls[NCRT_SMALL];
+  int ns[NCRT_SMALL] = {0};
+  for (int c = 0; c < NCRT_SMALL; ++c) {
+    ps[c] = (int64_t*)(h + lay.pref_crts[c]);
+    ls[c] = (int32_t*)(h + lay.list_crts[c]);
+    ps[c][0] = 0;
+  }
+  int32_t* lbig = (int32_t*)(h + lay.list_crtb);
+  int nbig = 0;
   int64_t* pg = (int64_t*)(h + lay.pref_gen);
   int32_t* lg = (int32_t*)(h + lay.list_gen);
   int ng = 0;
@@ -296,8 +331,17 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     pr[j + 1] = pr[j] + (int64_t)P.k * ((P.T + 255) / 256);
     pi[j + 1] = pi[j] + P.k;
     pib[j + 1] = pib[j] + (int64_t)P.k * ((P.D + 1 + 63) / 64);
-    pd[j + 1] = pd[j] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
-    pc[j + 1] = pc[j] + (n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
+    const int cc = crt_small_class(P.k);
+    if (cc >= 0) {
+      ls[cc][ns[cc]] = j;
+      ps[cc][ns[cc] + 1] = ps[cc][ns[cc]] + (n1 + 63) / 64;
+      ns[cc]++;
+    } else {
+      lbig[nbig] = j;
+      pd[nbig + 1] = pd[nbig] + (n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK;
+      pc[nbig + 1] = pc[nbig] + (n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
+      nbig++;
+    }
     pn[j + 1] = pn[j] + (int64_t)P.k * n1;
     if (P.cls >= 0) {
       const int c = P.cls;
@@ -312,28 +356,6 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   }
 }
 
-void launch_key(const BatchLayout& lay, const void* ws, std::vector<int64_t>& key) {
-  key.clear();
-  key.push_back((int64_t)(intptr_t)ws);
-  key.push_back((int64_t)lay.total_bytes);
-  key.push_back((int64_t)lay.jobs.size());
-  key.push_back(lay.nb_red); key.push_back(lay.nb_interp); key.push_back(lay.nb_crtd);
-  key.push_back(lay.nb_interp_blk); key.push_back(lay.interp_blk ? 1 : 0); key.push_back(lay.reduce_in_eval ? 1 : 0);
-  key.push_back(lay.nb_crtc); key.push_back(lay.n_gen_inst); key.push_back(lay.max_D);
-  key.push_back(lay.total_inst);
-  for (int c = 0; c < NCLS; ++c) {
-    key.push_back(lay.nb_ee[c]); key.push_back(lay.n_ee_jobs[c]); key.push_back(lay.max_T_ee[c]);
-  }
-  key.push_back(lay.n_gen_jobs);
-  key.push_back((int64_t)lay.abn_count_off); key.push_back((int64_t)lay.abn_list_off);
-  for (size_t o : {lay.jobs_off, lay.rows_off, lay.pref_red, lay.pref_interp, lay.pref_interp_blk, lay.pref_crtd, lay.pref_crtc,
-                   lay.pref_inst,
-                   lay.pref_gen, lay.list_gen})
-    key.push_back((int64_t)o);
-  for (int c = 0; c < NCLS; ++c) { key.push_back((int64_t)lay.pref_ee[c]); key.push_back((int64_t)lay.list_ee[c]); }
-}
-
-}  // namespace
 
 #define HIPCHK(x)                                                                     \
   do {                                                                                \
@@ -443,12 +465,12 @@ static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer&
   return SNC_OK;
 }
 
-// results from the staged output block into out
-static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
+// results of jobs j0 .. j1-1 with j = tid mod nthr from the staged output block into out
+static void collect_jobs(const snc_prepared* pr, snc_upoly* out, int j0, int j1, int tid, int nthr) {
   const BatchLayout& lay = pr->lay;
   const uint32_t* ho = (const uint32_t*)pr->h_out;
   const size_t base = lay.out_off / 4;
-  for (int j = 0; j < (int)lay.dev.size(); ++j) {
+  for (int j = j0 + tid; j < j1; j += nthr) {
     const int i = lay.dev[j];
     const ResJob& J = lay.jobs[j];
     const uint32_t* src = ho + (J.out_off - base);
@@ -457,14 +479,80 @@ static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
       for (int l = 0; l < J.L; ++l)
         if (src[(size_t)t * J.L + l]) { deg = t; break; }
     const int stride = out[i].nlimbs;
-    for (int t = 0; t <= deg; ++t) {
-      const uint32_t* s = src + (size_t)t * J.L;
-      uint32_t* d = out[i].limbs + (size_t)t * stride;
-      const uint32_t ext = (s[J.L - 1] >> 31) ? 0xffffffffu : 0u;
-      for (int l = 0; l < stride; ++l) d[l] = l < J.L ? s[l] : ext;
+    if (stride == J.L) {
+      std::memcpy(out[i].limbs, src, sizeof(uint32_t) * (size_t)(deg + 1) * J.L);
+    } else {
+      for (int t = 0; t <= deg; ++t) {
+        const uint32_t* s = src + (size_t)t * J.L;
+        uint32_t* d = out[i].limbs + (size_t)t * stride;
+        const uint32_t ext = (s[J.L - 1] >> 31) ? 0xffffffffu : 0u;
+        for (int l = 0; l < stride; ++l) d[l] = l < J.L ? s[l] : ext;
+      }
     }
     out[i].deg = deg;
   }
+}
+
+static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
+  collect_jobs(pr, out, 0, (int)pr->lay.dev.size(), 0, 1);
+}
+
+// Download and collection of a large output block in chunks: the copy of
+// chunk c+1 runs while host threads widen chunk c into the caller's buffers.
+constexpr size_t COLLECT_CHUNKED_WORDS = (size_t)1 << 20;
+constexpr int COLLECT_CHUNKS = 8;
+
+static int download_collect_chunked(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  const BatchLayout& lay = pr->lay;
+  const int NJ = (int)lay.dev.size();
+  // job ranges of about equal output words (the jobs' output regions are consecutive)
+  std::vector<int> bnd{0};
+  const size_t per = (lay.out_words + COLLECT_CHUNKS - 1) / COLLECT_CHUNKS;
+  size_t acc = 0;
+  for (int j = 0; j < NJ; ++j) {
+    acc += (size_t)(lay.jobs[j].D + 1) * lay.jobs[j].L;
+    if (acc >= per * bnd.size() && j + 1 < NJ && (int)bnd.size() < COLLECT_CHUNKS) bnd.push_back(j + 1);
+  }
+  bnd.push_back(NJ);
+  const int nch = (int)bnd.size() - 1;
+  while ((int)pr->d2h_ev.size() < nch) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pr->d2h_ev.push_back(e);
+  }
+  const size_t base = lay.out_off / 4;
+  for (int ch = 0; ch < nch; ++ch) {
+    const size_t w0 = lay.jobs[bnd[ch]].out_off - base;
+    const size_t w1 = bnd[ch + 1] < NJ ? lay.jobs[bnd[ch + 1]].out_off - base : lay.out_words;
+    HIPCHK(hipMemcpyAsync((uint32_t*)pr->h_out + w0, pr->ws + lay.out_off + w0 * 4, (w1 - w0) * 4,
+                          hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipEventRecord(pr->d2h_ev[ch], stream));
+  }
+  const unsigned hc = std::thread::hardware_concurrency();
+  const int nthr = (int)std::max(1u, std::min(8u, hc / 2));
+  std::atomic<int> ready{0};
+  std::vector<std::thread> workers;
+  for (int t = 1; t < nthr; ++t)
+    workers.emplace_back([&, t] {
+      for (int ch = 0; ch < nch; ++ch) {
+        while (ready.load(std::memory_order_acquire) <= ch) {
+          if (ready.load(std::memory_order_acquire) < 0) return;
+          std::this_thread::yield();
+        }
+        collect_jobs(pr, out, bnd[ch], bnd[ch + 1], t, nthr);
+      }
+    });
+  hipError_t err = hipSuccess;
+  for (int ch = 0; ch < nch; ++ch) {
+    err = hipEventSynchronize(pr->d2h_ev[ch]);
+    if (err != hipSuccess) { ready.store(-1, std::memory_order_release); break; }
+    ready.store(ch + 1, std::memory_order_release);
+    collect_jobs(pr, out, bnd[ch], bnd[ch + 1], 0, nthr);
+  }
+  for (auto& w : workers) w.join();
+  if (err != hipSuccess) { c->err = std::string("result download: ") + hipGetErrorString(err); return SNC_EDEVICE; }
+  return SNC_OK;
 }
 
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
@@ -476,6 +564,7 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   tm.start();
   int st = launch_prepared_all(pr, stream, tm);
   if (st) return st;
+  if (!tm.on && pr->lay.out_words >= COLLECT_CHUNKED_WORDS) return download_collect_chunked(pr, stream, out);
   HIPCHK(hipMemcpyAsync(pr->h_out, pr->ws + pr->lay.out_off, pr->lay.out_words * 4, hipMemcpyDeviceToHost, stream));
   tm.mark("d2h", 1);
   HIPCHK(hipStreamSynchronize(stream));
@@ -530,6 +619,7 @@ void destroy_prepared(snc_prepared* pr) {
   if (pr->gexec) (void)hipGraphExecDestroy(pr->gexec);
   if (pr->h_out) (void)hipHostFree(pr->h_out);
   if (pr->h_ed) (void)hipHostFree(pr->h_ed);
+  for (hipEvent_t e : pr->d2h_ev) (void)hipEventDestroy(e);
   delete pr;
 }
 

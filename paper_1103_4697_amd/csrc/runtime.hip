@@ -107,6 +107,7 @@ int ensure_device_tables(int device, std::string& err) {
   if (e != hipSuccess) { err = std::string("kernel attributes: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   upload_tables(T.pc.data(), T.garner.data(), T.wtab.data(), T.ptab.data(), nullptr);
   launch_ifact_init(nullptr);
+  launch_crt_small_init(nullptr);
   e = hipDeviceSynchronize();
   if (e != hipSuccess) { err = std::string("table upload: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   (void)global_crt_tables();

@@ -54,6 +54,11 @@ struct BatchLayout {
   bool interp_blk = false;           // every job fits the block-parallel interpolation
   bool reduce_in_eval = false;       // the evaluation kernel reduces the inputs (no reduction launch)
   size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes
+  // Chinese remaindering: the small-prime classes (one lane per coefficient)
+  // and the jobs with more primes (pref_crtd / pref_crtc over list_crtb)
+  size_t pref_crts[NCRT_SMALL] = {0}, list_crts[NCRT_SMALL] = {0}, list_crtb = 0;  // bytes
+  int64_t nb_crts[NCRT_SMALL] = {0};
+  int n_crts_jobs[NCRT_SMALL] = {0}, n_crtb_jobs = 0;
   size_t header_bytes = 0;
   size_t abn_count_off = 0, abn_list_off = 0;              // bytes
   uint32_t abn_cap = 0;
@@ -112,6 +117,7 @@ struct snc_prepared {
   uint8_t* ws = nullptr;
   void* h_out = nullptr;
   hipGraphExec_t gexec = nullptr;    // whole pipeline
+  std::vector<hipEvent_t> d2h_ev;    // chunks of the result download (large batches)
   // projection step (resultant and gcd(R, R')): the Euclid descriptors are
   // uploaded into the workspace on the first run
   void* h_ed = nullptr;              // mapped pinned memory the Euclid writes e and d to
@@ -122,6 +128,13 @@ struct snc_prepared {
 
 namespace snc {
 enum { PIPE_ALL = 0, PIPE_TO_INTERP = 1, PIPE_CRT = 2 };
+struct StageTimer;
+// upload block of a laid-out batch: job and row descriptors, block
+// prefixes, class job lists and the packed input limbs (header_bytes)
+void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, const std::vector<Operand>& F,
+                 const std::vector<Operand>& G, uint8_t* h);
+// device launch sequence of a laid-out batch whose header is in ws (tm may be null)
+void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part);
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);

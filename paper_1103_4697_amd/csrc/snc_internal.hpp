@@ -151,10 +151,24 @@ void launch_elim_general_all(const ResJob* jobs_d, const int32_t* job_list_d,
 // the interpolation launches also clear zero_word (the abnormal-instance counter)
 void launch_interp(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s);
-void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                       int64_t nblocks, uint32_t* ws, hipStream_t s);
-void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int64_t* prefix_d, int njobs,
-                        int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
+// job_list_d: the jobs of the launch (block prefix over them), or null for jobs 0..njobs-1
+void launch_crt_digits(const CrtTables& tb, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d,
+                       int njobs, int64_t nblocks, uint32_t* ws, hipStream_t s);
+void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d,
+                        int njobs, int64_t nblocks, int kmax, uint32_t* ws, hipStream_t s);
+// Chinese remaindering of a resultant with at most CRT_SMALL_K[cls] primes of
+// the modulus table: one lane per coefficient (digits and binary value in one
+// kernel); blocks of 64 coefficients, prefix over the launch's jobs
+constexpr int NCRT_SMALL = 3;
+constexpr int CRT_SMALL_K[NCRT_SMALL] = {32, 64, 128};
+inline int crt_small_class(int k) {
+  for (int c = 0; c < NCRT_SMALL; ++c)
+    if (k <= CRT_SMALL_K[c]) return c;
+  return -1;
+}
+void launch_crt_small(int cls, const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
+                      int64_t nblocks, uint32_t* ws, hipStream_t s);
+void launch_crt_small_init(hipStream_t s);  // transposed table of P_j mod p_i (once per device)
 CrtTables global_crt_tables();  // the resident tables of the modulus table (after upload)
 
 // gcd work items are (problem, slot) pairs indexing a device array of GcdDesc
