@@ -160,6 +160,26 @@ int snc_resultant_y_prepare(snc_ctx* ctx, int32_t n, const snc_bipoly* f, const 
 int snc_prepared_run(snc_prepared* prep, void* stream, snc_upoly* out);
 int snc_prepared_destroy(snc_prepared* prep);
 
+/* One resultant with no allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation of snc_resultant_y with its device workspace
+ * in a fixed module array of SNC_NOALLOC_SCRATCH_BYTES per device (held from
+ * the library's first use on the device until the process ends), its upload
+ * block in a fixed host array, and the results downloaded into out.  The
+ * call makes no device or pinned-host allocation and creates no stream,
+ * event or graph (host-side planning uses a few small heap vectors, as every
+ * call does).  Arguments and results as for snc_resultant_y.  Errors: a pair
+ * whose plan needs more than SNC_NOALLOC_SCRATCH_BYTES (its workspace_bytes
+ * from snc_resultant_y_plan) gives SNC_ENOMEM before any device work, with
+ * the sizes in the message; SNC_ERANGE as for snc_resultant_y.  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * race (the host part is serialised, device work on different streams is
+ * not).  The array keeps the last call's contents; the call clears what must
+ * start at zero. */
+#define SNC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int snc_resultant_y_noalloc(snc_ctx* ctx, const snc_bipoly* f, const snc_bipoly* g, void* stream,
+                            snc_upoly* out);
+
 /* Resultant and square-free gcd in one pass: the projection step of the
  * curve analysis (Section 2.1) needs R = res_y(f, g) and gcd(R, R') (R / gcd
  * is the square-free part).  One run of the prepared pipeline computes both:

@@ -69,6 +69,7 @@ def lib():
                 "snc_prime": (C.c_uint32, [I32]),
                 "snc_resultant_y_plan": (C.c_int, [P(Bipoly), P(Bipoly), P(Plan)]),
                 "snc_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
+                "snc_resultant_y_noalloc": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, P(Upoly)]),
                 "snc_resultant_y_batch_plan": (C.c_int, [I32, P(Bipoly), P(Bipoly), P(Plan), P(Plan)]),
                 "snc_resultant_y_batch": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_resultant_y_prepare": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(VP)]),
@@ -315,6 +316,23 @@ def resultant_y(f, g, ctx: Context | None = None, stream=None) -> list:
                                C.c_size_t(ws.numel()), ctx.stream_handle(stream), C.byref(u))
     ctx.check(st, "snc_resultant_y")
     return _read_upoly(u, buf)
+
+
+def resultant_y_noalloc(f, g, ctx: Context | None = None, stream=None) -> list:
+    """res_y(f, g) through snc_resultant_y_noalloc: the library's fixed
+    device scratch array instead of a workspace (no device allocation)."""
+    ctx = ctx or default_context()
+    keep = []
+    bf, bg = _as_bipoly(f, keep), _as_bipoly(g, keep)
+    p = Plan()
+    ctx.check(lib().snc_resultant_y_plan(C.byref(bf), C.byref(bg), C.byref(p)), "plan")
+    u, buf = _out_upoly(p.deg_bound, p.out_nlimbs, keep)
+    st = lib().snc_resultant_y_noalloc(ctx.h, C.byref(bf), C.byref(bg), ctx.stream_handle(stream), C.byref(u))
+    ctx.check(st, "snc_resultant_y_noalloc")
+    return _read_upoly(u, buf)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SNC_NOALLOC_SCRATCH_BYTES of snc.h
 
 
 class ResultantBatch:

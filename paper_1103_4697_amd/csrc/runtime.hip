@@ -105,6 +105,8 @@ int ensure_device_tables(int device, std::string& err) {
   hipError_t e = configure_kernels();
   if (e == hipSuccess) e = configure_gcd_kernels();
   if (e != hipSuccess) { err = std::string("kernel attributes: ") + hipGetErrorString(e); return SNC_EDEVICE; }
+  e = init_noalloc_scratch(device);
+  if (e != hipSuccess) { err = std::string("scratch address: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   upload_tables(T.pc.data(), T.garner.data(), T.wtab.data(), T.ptab.data(), nullptr);
   launch_ifact_init(nullptr);
   launch_crt_small_init(nullptr);

@@ -25,6 +25,9 @@ struct Tables {
 };
 const Tables& tables();
 int ensure_device_tables(int device, std::string& err);
+// device address of the fixed scratch array of snc_resultant_y_noalloc,
+// looked up once per device with that device current
+hipError_t init_noalloc_scratch(int device);
 
 struct Operand {
   int dy = -1, dx = -1, nl = 1;
