@@ -559,7 +559,10 @@ def main():
 
     progress("planning and uploading the 512-pair batch")
     pairs, common = synth.config2()
+    t_prep = time.perf_counter()
     batch = snc.ResultantBatch(pairs, ctx)
+    prep_s = time.perf_counter() - t_prep
+    tune_rep, tune_ms = ctx.tuning()
     if args.profile_batch:
         for _ in range(args.profile_batch):
             batch.run()
@@ -637,6 +640,9 @@ def main():
         "roofline_stages": recs,
         "hbm_gbps_algorithmic": hbm,
         "ceilings": ceilings,
+        "autotune": {"classes": tune_rep, "tuning_ms": round(tune_ms, 1),
+                     "prepare_s_including_tuning": round(prep_s, 3),
+                     "note": "one-time: variants chosen at preparation (measured, or read from the cache file)"},
     }
 
     if not args.no_extras:

@@ -128,6 +128,32 @@ enum { SNC_MB_MONTGOMERY = 0, SNC_MB_MUL_LO = 1, SNC_MB_MAD_U64 = 2 };
 int snc_microbench(snc_ctx* ctx, int kind, int32_t iters, void* d_buf, size_t buf_bytes, void* stream,
                    double* ops_per_s);
 
+/* Autotuner of the evaluation kernel (Section 4, "Symbolic Speedups": the
+ * problems over prime fields are distributed over the device).  For each
+ * register class of the fused evaluation + elimination kernel (largest
+ * y-degree 8, 16, 32, 48, 64) a batch uses, the launch variant is chosen:
+ * wpe = minimum wavefronts per SIMD the register allocation is held to
+ * (1 = unconstrained .. 4), chunk = 0 for one workgroup per block of 64
+ * points or the number of blocks a persistent workgroup takes at a time
+ * from a device work counter.  All variants give identical results.
+ * snc_set_tuning: mode 0 = no measurements (cached choices, else wpe 1,
+ *   chunk 0), 1 = measure the classes not yet tuned on this device (the
+ *   default; batched calls only: snc_resultant_y_prepare/_batch), 2 =
+ *   measure again.  Choices are kept per (class, LDS variant, log2 of the
+ *   class's block count) and appended to the cache file
+ *   $SNC_TUNE_DIR/eval_elim_<arch>_<CUs>cu.tune (default directory
+ *   $HOME/.cache/snc), read by later processes.
+ * snc_set_eval_variant: force (wpe, chunk) for every launch of the class
+ *   whose largest y-degree is class_cap on this context (wpe 0 clears).
+ * snc_get_tuning: the last batched preparation's choice per class used:
+ *   info[6 i ..] = class_cap, wpe, chunk, persistent grid, source (0
+ *   defaults, 1 measured, 2 cached, 3 forced), variants timed; ms[2 i ..] =
+ *   measured time of the chosen and of the default variant (source 1);
+ *   *tune_ms = host time the tuning took.  Returns the number of classes. */
+int snc_set_tuning(snc_ctx* ctx, int mode);
+int snc_set_eval_variant(snc_ctx* ctx, int32_t class_cap, int32_t wpe, int32_t chunk);
+int snc_get_tuning(const snc_ctx* ctx, int32_t* info, float* ms, int cap, float* tune_ms);
+
 /* ---- resultant res_y(f, g) in Z[x] --------------------------------------
  * Host-only planning: degree bound D (Sylvester weighted-degree bound),
  * Hadamard-type coefficient bound B, number of primes k with prod p > 2B,

@@ -66,6 +66,9 @@ def lib():
                 "snc_set_timing": (C.c_int, [VP, C.c_int]),
                 "snc_get_timing": (C.c_int, [VP, P(C.c_char_p), P(C.c_float), P(I32), C.c_int]),
                 "snc_microbench": (C.c_int, [VP, C.c_int, I32, VP, SZ, VP, P(C.c_double)]),
+                "snc_set_tuning": (C.c_int, [VP, C.c_int]),
+                "snc_set_eval_variant": (C.c_int, [VP, I32, I32, I32]),
+                "snc_get_tuning": (C.c_int, [VP, P(I32), P(C.c_float), C.c_int, P(C.c_float)]),
                 "snc_prime": (C.c_uint32, [I32]),
                 "snc_resultant_y_plan": (C.c_int, [P(Bipoly), P(Bipoly), P(Plan)]),
                 "snc_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
@@ -270,6 +273,29 @@ class Context:
                                   self.stream_handle(), C.byref(rate))
         self.check(st, "snc_microbench")
         return rate.value
+
+    def set_tuning(self, mode: int):
+        """Evaluation autotuner: 0 off, 1 tune untuned classes (default), 2 retune."""
+        self.check(lib().snc_set_tuning(self.h, mode), "snc_set_tuning")
+
+    def set_eval_variant(self, class_cap: int, wpe: int, chunk: int = 0):
+        """Force the evaluation kernel variant of a register class (wpe 0 clears)."""
+        self.check(lib().snc_set_eval_variant(self.h, class_cap, wpe, chunk), "snc_set_eval_variant")
+
+    def tuning(self):
+        """The last batched preparation's evaluation variants, one dict per class."""
+        cap = 8
+        info = (C.c_int32 * (6 * cap))()
+        ms = (C.c_float * (2 * cap))()
+        tms = C.c_float(0.0)
+        n = lib().snc_get_tuning(self.h, info, ms, cap, C.byref(tms))
+        src = {0: "default", 1: "measured", 2: "cached", 3: "forced"}
+        out = []
+        for i in range(min(n, cap)):
+            o = info[6 * i: 6 * i + 6]
+            out.append({"class": o[0], "wpe": o[1], "chunk": o[2], "grid": o[3], "source": src.get(o[4], o[4]),
+                        "candidates": o[5], "best_ms": round(ms[2 * i], 4), "default_ms": round(ms[2 * i + 1], 4)})
+        return out, float(tms.value)
 
     def timing(self):
         cap = 32

@@ -32,6 +32,19 @@ __device__ __forceinline__ uint32_t redc(uint64_t t, uint32_t p, uint32_t pinv) 
   return r;
 }
 
+// redc whose result is copied into a register of its own.  The reduction's
+// result is the high word of a 64-bit register pair; kernels that keep long
+// arrays of residues in registers would otherwise hold each residue in half
+// a pair (64-bit temporaries need aligned pairs), doubling their register
+// use.  One extra move per reduction.
+__device__ __forceinline__ uint32_t redc_mv(uint64_t t, uint32_t p, uint32_t pinv) {
+  const uint32_t m = (uint32_t)t * pinv;
+  const uint32_t r = (uint32_t)((t + (uint64_t)m * p) >> 32);
+  uint32_t rr;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(rr) : "v"(r));
+  return rr;
+}
+
 // a*b in Montgomery form, a,b in [0,3p) -> [0, 2p)
 __device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
   return redc((uint64_t)a * b, p, pinv);

@@ -144,6 +144,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   for (int c = 0; c < NCLS; ++c)
     if (lay.n_ee_jobs[c] && !eval_elim_in_lds(lay.max_T_ee[c])) lay.reduce_in_eval = false;
   lay.abn_count_off = w * 4; w += 64;
+  lay.ee_counter_off = w * 4; w += 64;
   lay.abn_list_off = w * 4;
   lay.abn_cap = abn_list_cap(lay.total_inst);
   w += align_words((size_t)lay.abn_cap * (sizeof(AbnEntry) / 4));
@@ -213,11 +214,15 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   // jobs above the register classes
   static const char* const kEEStage[NCLS] = {"eval_elim_8", "eval_elim_16", "eval_elim_32", "eval_elim_48",
                                              "eval_elim_64"};
+  uint32_t* ee_counters = (uint32_t*)(ws + lay.ee_counter_off);
+  bool persistent = false;
+  for (int c = 0; c < NCLS; ++c) persistent |= lay.n_ee_jobs[c] && lay.ee_var[c].chunk > 0;
+  if (persistent) launch_zero_u32(ee_counters, NCLS, s);  // a kernel, not a memset node
   for (int c = 0; c < NCLS; ++c) {
     if (!lay.n_ee_jobs[c]) continue;
-    launch_eval_elim(c, jobs, (const int32_t*)(ws + lay.list_ee[c]), (const int64_t*)(ws + lay.pref_ee[c]),
-                     lay.n_ee_jobs[c], lay.nb_ee[c], lay.max_T_ee[c], rows, wsw, abn_count, abn_list, lay.abn_cap,
-                     lay.reduce_in_eval, s);
+    launch_eval_elim(c, lay.ee_var[c], ee_counters + c, jobs, (const int32_t*)(ws + lay.list_ee[c]),
+                     (const int64_t*)(ws + lay.pref_ee[c]), lay.n_ee_jobs[c], lay.nb_ee[c], lay.max_T_ee[c], rows,
+                     wsw, abn_count, abn_list, lay.abn_cap, lay.reduce_in_eval, s);
     if (tm) tm->mark(kEEStage[c], 1);
   }
   if (lay.n_gen_jobs) {
@@ -253,6 +258,15 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   }
 }
 
+// Essential lane-operations of one evaluation block (64 instances): Horner
+// in x^4 (1.5 per coefficient), the fused remainder steps (5 per entry of
+// each remainder), the first remainder's elementary steps and the final
+// powers and inversion.
+static int64_t eval_block_cost(const ResPlan& P) {
+  const int64_t m = P.m, n = P.n;
+  return 3 * (int64_t)P.T / 2 + 5 * n * (n + 1) / 2 + 4 * n * std::max<int64_t>(m - n - 1, 0) + 300;
+}
+
 // Fill the upload block: job descriptors, row descriptors, block prefixes,
 // class job lists and the packed input coefficients.
 void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, const std::vector<Operand>& F,
@@ -285,6 +299,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
   }
   int32_t* lbig = (int32_t*)(h + lay.list_crtb);
   int nbig = 0;
+  std::vector<std::pair<int64_t, int>> by_cost[NCLS];  // (work per block, job) per register class
   int64_t* pg = (int64_t*)(h + lay.pref_gen);
   int32_t* lg = (int32_t*)(h + lay.list_gen);
   int ng = 0;
@@ -344,14 +359,23 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     }
     pn[j + 1] = pn[j] + (int64_t)P.k * n1;
     if (P.cls >= 0) {
-      const int c = P.cls;
-      le[c][ne[c]] = j;
-      pe[c][ne[c] + 1] = pe[c][ne[c]] + (int64_t)P.k * ((n1 + EE_BLOCK - 1) / EE_BLOCK);
-      ne[c]++;
+      by_cost[P.cls].push_back({eval_block_cost(P), j});
     } else {
       lg[ng] = j;
       pg[ng + 1] = pg[ng] + (int64_t)P.k * n1;
       ng++;
+    }
+  }
+  // a class's jobs most expensive first: a persistent launch hands out the
+  // cheapest blocks last (the order does not change any result)
+  for (int c = 0; c < NCLS; ++c) {
+    std::stable_sort(by_cost[c].begin(), by_cost[c].end(),
+                     [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) { return x.first > y.first; });
+    for (const auto& e : by_cost[c]) {
+      const ResJob& J = lay.jobs[e.second];
+      le[c][ne[c]] = e.second;
+      pe[c][ne[c] + 1] = pe[c][ne[c]] + (int64_t)J.k * ((J.D + 1 + EE_BLOCK - 1) / EE_BLOCK);
+      ne[c]++;
     }
   }
 }
@@ -402,12 +426,17 @@ int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly*
     StageTimer tm{c, stream, c->timing && !use_graph};
     tm.start();
     hipError_t e = hipMemcpyAsync(pr->ws, c->h_in, lay.header_bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+      // launch variants of the evaluation kernel: measured for a batched graph, looked up otherwise
+      const int st = choose_eval_variants(c, pr->lay, pr->ws, stream, use_graph);
+      if (st) { destroy_prepared(pr); return st; }
+    }
     if (e == hipSuccess) {  // the abnormal-instance counter starts at zero; each run's interpolation clears it
       launch_zero_u32((uint32_t*)(pr->ws + lay.abn_count_off), 1, stream);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) { c->err = std::string("input upload: ") + hipGetErrorString(e); delete pr; return SNC_EDEVICE; }
+    if (e != hipSuccess) { c->err = std::string("input upload: ") + hipGetErrorString(e); destroy_prepared(pr); return SNC_EDEVICE; }
   }
   *outp = pr;
   return SNC_OK;

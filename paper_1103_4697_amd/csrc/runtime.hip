@@ -308,6 +308,41 @@ int snc_get_timing(const snc_ctx* c, const char** names, float* ms, int32_t* lau
   return n;
 }
 
+int snc_set_tuning(snc_ctx* c, int mode) {
+  if (!c || mode < 0 || mode > 2) return SNC_EINVAL;
+  c->tune_mode = mode;
+  return SNC_OK;
+}
+
+int snc_set_eval_variant(snc_ctx* c, int32_t class_cap, int32_t wpe, int32_t chunk) {
+  if (!c) return SNC_EINVAL;
+  const int cls = fast_class_of(class_cap);
+  if (cls < 0 || fast_class_cap(cls) != class_cap || wpe < 0 || wpe > EE_WPE_MAX || chunk < 0 || chunk > 64)
+    return SNC_EINVAL;
+  c->forced[cls] = EEVariant();
+  c->forced[cls].wpe = 0;
+  if (wpe > 0) {
+    c->forced[cls].wpe = wpe;
+    c->forced[cls].chunk = chunk;
+  }
+  return SNC_OK;
+}
+
+int snc_get_tuning(const snc_ctx* c, int32_t* info, float* ms, int cap, float* tune_ms) {
+  if (!c) return SNC_EINVAL;
+  const int n = (int)c->tune_report.size();
+  for (int i = 0; i < n && i < cap; ++i) {
+    const EETuneReport& r = c->tune_report[i];
+    if (info) {
+      int32_t* o = info + 6 * i;
+      o[0] = r.cls_cap; o[1] = r.wpe; o[2] = r.chunk; o[3] = (int32_t)r.grid; o[4] = r.source; o[5] = r.candidates;
+    }
+    if (ms) { ms[2 * i] = r.best_ms; ms[2 * i + 1] = r.default_ms; }
+  }
+  if (tune_ms) *tune_ms = c->tune_ms;
+  return n;
+}
+
 int snc_resultant_y_plan(const snc_bipoly* f, const snc_bipoly* g, snc_plan* out) {
   if (!out) return SNC_EINVAL;
   std::string err;

@@ -62,6 +62,8 @@ struct BatchLayout {
   size_t pref_crts[NCRT_SMALL] = {0}, list_crts[NCRT_SMALL] = {0}, list_crtb = 0;  // bytes
   int64_t nb_crts[NCRT_SMALL] = {0};
   int n_crts_jobs[NCRT_SMALL] = {0}, n_crtb_jobs = 0;
+  EEVariant ee_var[NCLS];            // launch variant of each register class (autotuner, or the defaults)
+  size_t ee_counter_off = 0;         // bytes: the NCLS work counters of persistent evaluation launches
   size_t header_bytes = 0;
   size_t abn_count_off = 0, abn_list_off = 0;              // bytes
   uint32_t abn_cap = 0;
@@ -83,10 +85,26 @@ int plan_resultant(const Operand& F, const Operand& G, ResPlan& P, std::string& 
 
 }  // namespace snc
 
+// One register class's choice by the evaluation autotuner on a prepared batch.
+struct EETuneReport {
+  int32_t cls_cap = 0;       // register class (largest y-degree)
+  int32_t wpe = 1, chunk = 0;
+  int64_t grid = 0;          // persistent workgroups (chunk > 0)
+  int32_t source = 0;        // 0 defaults, 1 measured now, 2 from the cache, 3 forced
+  float best_ms = 0.f;       // measured time of the chosen variant (source 1)
+  float default_ms = 0.f;    // measured time of the default variant (source 1)
+  int32_t candidates = 0;    // variants timed
+};
+
 struct snc_ctx {
   int device = 0;
   std::string err;
   bool timing = false;
+  // evaluation autotuner: 0 off (defaults, cache lookups only), 1 tune classes the cache lacks, 2 retune
+  int tune_mode = 1;
+  snc::EEVariant forced[snc::NCLS];  // wpe > 0: variant forced for every launch of that class (0: none)
+  std::vector<EETuneReport> tune_report;  // the last batched preparation's choices
+  float tune_ms = 0.f;                    // host wall time spent tuning in that preparation
   std::vector<const char*> stage_names;
   std::vector<float> stage_ms;
   std::vector<int> stage_launches;
@@ -104,6 +122,9 @@ struct snc_ctx {
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_mid = nullptr;
 
+  snc_ctx() {
+    for (auto& f : forced) f.wpe = 0;
+  }
   int stage_in(size_t bytes);
   int stage_out(size_t bytes);
   void release();
@@ -138,6 +159,10 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
                  const std::vector<Operand>& G, uint8_t* h);
 // device launch sequence of a laid-out batch whose header is in ws (tm may be null)
 void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part);
+// launch variants of the evaluation kernel for a laid-out batch whose header is on the device:
+// forced variants, then (tune true) measured ones for the classes the cache lacks, else cached
+// choices or the defaults; fills lay.ee_var and the context's report
+int choose_eval_variants(snc_ctx* c, BatchLayout& lay, uint8_t* ws, hipStream_t s, bool tune);
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);

@@ -135,11 +135,23 @@ void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs,
 // the evaluation kernel stages a prime's residues in LDS up to this size
 constexpr int EE_LDS_MAX = 64 * 1024;
 inline bool eval_elim_in_lds(int max_T) { return (size_t)max_T * sizeof(uint32_t) <= (size_t)EE_LDS_MAX; }
+// Launch variant of the evaluation kernel for one register class:
+//   wpe: minimum wavefronts per SIMD the register allocation is held to (1..4, 1 = unconstrained);
+//   chunk: 0 = one workgroup per block; > 0 = persistent grid of `grid` workgroups taking `chunk`
+//          blocks at a time from a counter that is zero at launch.
+struct EEVariant {
+  int32_t wpe = 1;
+  int32_t chunk = 0;
+  int64_t grid = 0;
+};
+constexpr int EE_WPE_MAX = 4;
+// workgroups of a variant resident on the whole device (0 if the query fails)
+int eval_elim_grid(int cls, int wpe, int max_T);
 // reduce_in: the residues are reduced from the input limbs inside the kernel (LDS variant only)
-void launch_eval_elim(int cls, const ResJob* jobs_d, const int32_t* job_list_d,
-                      const int64_t* blk_prefix_d, int njobs, int64_t nblocks, int max_T, const RowDesc* rows_d,
-                      uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list, uint32_t abn_cap,
-                      bool reduce_in, hipStream_t s);
+void launch_eval_elim(int cls, const EEVariant& v, uint32_t* counter, const ResJob* jobs_d,
+                      const int32_t* job_list_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
+                      int max_T, const RowDesc* rows_d, uint32_t* ws, uint32_t* abn_count, AbnEntry* abn_list,
+                      uint32_t abn_cap, bool reduce_in, hipStream_t s);
 // abnormal instances: the list when count <= cap, else a scan of every
 // instance for ABN_MARK (inst_prefix: prefix sums of k (D+1) over the jobs)
 void launch_elim_general(const ResJob* jobs_d, const RowDesc* rows_d, uint32_t* ws,

@@ -320,3 +320,87 @@ def test_random_curve_set_batch(snc):
         assert r == snc.resultant_y(f, g)
         x0 = rs.randrange(Q61)
         assert zx.evaluate(r, x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
+
+
+def _class_spanning_pairs(seed):
+    """Pairs whose larger y-degree falls in every register class from 16 to
+    64, with ragged point tiles, small and multi-word coefficients and one
+    planted common factor (resultant 0)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(12, 10, 16, 20), (20, 17, 24, 12), (30, 26, 8, 32), (40, 36, 16, 16), (44, 50, 10, 12),
+              (60, 58, 8, 8)]
+    pairs = [synth.random_pair(rng, *sh) for sh in shapes]
+    pairs.append(synth.common_factor_pair(rng, 38, 35, 12, 12))
+    return pairs
+
+
+def test_eval_variants_identical(snc):
+    """Every launch variant of the evaluation kernel the autotuner can pick
+    (register budget for 1..4 wavefronts per SIMD; one workgroup per block
+    or a persistent grid taking 1 or 4 blocks at a time) gives the same
+    resultants; those equal the plain calls, and a pair checked against the
+    oracle mod a 61-bit prime at a random point."""
+    pairs = _class_spanning_pairs(8801)
+    ctx = snc.Context(0)
+    ctx.set_tuning(0)
+    ref = snc.resultant_y_batch(pairs, ctx)
+    assert ref[-1] == []
+    assert all(r != [] for r in ref[:-1])
+    for (f, g), r in zip(pairs[:3], ref):
+        assert snc.resultant_y(f, g, ctx) == r
+    rng = random.Random(8802)
+    f, g = pairs[3]
+    x0 = rng.randrange(Q61)
+    assert zx.evaluate(ref[3], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
+    for wpe in (1, 2, 3, 4):
+        for chunk in (0, 1, 4):
+            for cap in (16, 32, 48, 64):
+                ctx.set_eval_variant(cap, wpe, chunk)
+            got = snc.resultant_y_batch(pairs, ctx)
+            rep, _ = ctx.tuning()
+            assert {e["source"] for e in rep} == {"forced"}
+            assert all(e["wpe"] == wpe and e["chunk"] == chunk for e in rep)
+            assert got == ref, (wpe, chunk)
+    for cap in (16, 32, 48, 64):
+        ctx.set_eval_variant(cap, 0, 0)
+    # the prepared graph of a persistent variant replayed several times
+    for cap in (16, 32, 48, 64):
+        ctx.set_eval_variant(cap, 2, 1)
+    b = snc.ResultantBatch(pairs, ctx)
+    for _ in range(3):
+        b.run()
+        assert b.results() == ref
+    b.close()
+    for cap in (16, 32, 48, 64):
+        ctx.set_eval_variant(cap, 0, 0)
+
+
+def test_autotuner_measures_and_caches(snc):
+    """The autotuner times every candidate of each class the batch uses,
+    keeps one no slower than the default, and a later preparation of the
+    same shape reuses it from its table; results are unchanged."""
+    pairs = _class_spanning_pairs(8803)
+    ctx = snc.Context(0)
+    ctx.set_tuning(0)
+    ref = snc.resultant_y_batch(pairs, ctx)
+    ctx.set_tuning(2)
+    b = snc.ResultantBatch(pairs, ctx)
+    rep, tune_ms = ctx.tuning()
+    assert tune_ms > 0.0
+    assert {e["class"] for e in rep} == {16, 32, 48, 64}
+    for e in rep:
+        assert e["source"] == "measured"
+        assert e["candidates"] >= 4
+        assert 0.0 < e["best_ms"] <= e["default_ms"] + 1e-6
+        assert 1 <= e["wpe"] <= 4 and e["chunk"] in (0, 1, 4)
+    b.run()
+    assert b.results() == ref
+    b.close()
+    ctx.set_tuning(1)
+    b2 = snc.ResultantBatch(pairs, ctx)
+    rep2, _ = ctx.tuning()
+    assert {e["source"] for e in rep2} == {"cached"}
+    assert [(e["wpe"], e["chunk"]) for e in rep2] == [(e["wpe"], e["chunk"]) for e in rep]
+    b2.run()
+    assert b2.results() == ref
+    b2.close()
