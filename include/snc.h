@@ -258,21 +258,61 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
 int snc_content_y_plan(const snc_bipoly* f, snc_plan* out);
 int snc_content_y(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);
 
+/* Contents in y of n curves at once (opening of Section 2.1, for every curve
+ * of a set): one binary tree over all curves, each level pairing the rows
+ * of every curve and taking all pairs' gcds in one batched modular gcd
+ * submission.  out[i] as snc_content_y of curve i.  plan: out_each[i] bounds
+ * curve i's content (deg_bound, out_nlimbs), out_total the largest of them
+ * and workspace_bytes the first level's batch; a later level that needs
+ * more gives SNC_ENOMEM with the size in the message. */
+int snc_content_y_batch_plan(int32_t n, const snc_bipoly* f, snc_plan* out_each, snc_plan* out_total);
+int snc_content_y_batch(snc_ctx* ctx, int32_t n, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream,
+                        snc_upoly* out);
+
+/* Arrangement batch (Section 3: the projection phase of an arrangement of
+ * curves C_1..C_n needs R_C = res(f, f_y, y) of every curve, after its
+ * content in y is removed, and R_CD = res(f, g, y) of every pair).
+ * prepare: the contents h_i = cont_y(f_i) of all curves in one tree of
+ *   batched gcds (d_ws: workspace of snc_content_y_batch_plan), then on the
+ *   host the primitive parts p_i = f_i / h_i (exact division of the rows)
+ *   and their y-derivatives; the handle keeps them (inputs not retained).
+ * plan: content_each[i] = the exact size of h_i (n entries, or NULL);
+ *   res_each / res_total as snc_resultant_y_batch_plan for the n + n(n-1)/2
+ *   resultants, in this order: res_y(p_i, dp_i/dy) for i = 0..n-1, then
+ *   res_y(p_i, p_j) for i < j in lexicographic order.
+ * run: contents (n) and resultants (n + n(n-1)/2) as snc_upoly outputs; all
+ *   resultants run as one prepared batch (one graph replay), prepared on the
+ *   first run with d_ws (which must stay valid until the handle is
+ *   destroyed or a run with another workspace) and replayed afterwards. */
+typedef struct snc_arrangement snc_arrangement;
+int snc_arrangement_prepare(snc_ctx* ctx, int32_t n, const snc_bipoly* curves, void* d_ws, size_t ws_bytes,
+                            void* stream, snc_arrangement** out);
+int snc_arrangement_plan(const snc_arrangement* arr, snc_plan* content_each, snc_plan* res_each,
+                         snc_plan* res_total);
+int snc_arrangement_run(snc_arrangement* arr, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* contents,
+                        snc_upoly* resultants);
+int snc_arrangement_destroy(snc_arrangement* arr);
+
 /* FastLift's second resultant (Section 2.1, "Lifting Phase", the bound
- * m*_alpha): with h = gcd(f_x, f_y) in
- * Z[x, y], Q = res_y(f_x / h, f_y / h).  mult(Q, alpha) bounds the number of
- * distinct complex roots of f(alpha, y): m*_alpha = deg_y f - mult(R, alpha)
- * + mult(Q, alpha).  Built for h constant in y, the usual case: a prime p
- * and a point x0 where gcd(f_x(x0, y), f_y(x0, y)) mod p is constant (and
- * neither leading coefficient in y vanishes) certify that deg_y h = 0; then
- * h is the gcd of all rows of f_x and f_y in Z[x] (snc_content_y's tree of
- * batched gcds), normalised to a positive leading coefficient, the rows are
- * divided by h exactly on the host, and Q comes from snc_resultant_y.  When
- * four (p, x0) leave a non-constant gcd, h depends on y: SNC_ENOTSUP (a
- * bivariate gcd is not built).
- * plan: the plan of res_y(f_x, f_y), an upper bound when h = +-1; a
- *   non-trivial h may need more (SNC_ENOMEM / SNC_ERANGE with sizes, as for
- *   snc_resultant_y).
+ * m*_alpha): with h = gcd(f_x, f_y) in Z[x, y], Q = res_y(f_x / h, f_y / h).
+ * mult(Q, alpha) bounds the number of distinct complex roots of f(alpha, y):
+ * m*_alpha = deg_y f - mult(R, alpha) + mult(Q, alpha).  A prime p and a
+ * point x0 where gcd(f_x(x0, y), f_y(x0, y)) mod p is constant (and neither
+ * leading coefficient in y vanishes) certify that deg_y h = 0; then h is the
+ * gcd of all rows of f_x and f_y in Z[x] (snc_content_y's tree of batched
+ * gcds).  Otherwise h depends on y and comes from a bivariate modular gcd
+ * (Brown's dense method): contents in y and gamma = gcd of the leading
+ * coefficients in Z[x] by the batched gcd, then on the device, per (prime,
+ * point), gamma(x0) times the monic gcd in y of f_x(x0, y), f_y(x0, y)
+ * mod p, interpolated in x and combined over primes by the resultant's own
+ * kernels; the primitive part of the result, times the gcd of the
+ * contents, is h once it divides f_x and f_y exactly (otherwise more primes
+ * or other points are taken).  h is normalised to a positive leading
+ * coefficient (in y, then in x), f_x and f_y are divided by h exactly on
+ * the host, and Q comes from snc_resultant_y.
+ * plan: the plan of res_y(f_x, f_y), an upper bound when h = +-1, with the
+ *   workspace of the bivariate gcd's device pass; a non-trivial h may need
+ *   more (SNC_ENOMEM / SNC_ERANGE with sizes, as for snc_resultant_y).
  * run: out as for snc_resultant_y. */
 int snc_fastlift_q_plan(const snc_bipoly* f, snc_plan* out);
 int snc_fastlift_q(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* out);

@@ -96,6 +96,12 @@ def lib():
                 "snc_fastlift_q_plan": (C.c_int, [P(Bipoly), P(Plan)]),
                 "snc_fastlift_q": (C.c_int, [VP, P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_content_y_plan": (C.c_int, [P(Bipoly), P(Plan)]),
+                "snc_content_y_batch_plan": (C.c_int, [I32, P(Bipoly), P(Plan), P(Plan)]),
+                "snc_content_y_batch": (C.c_int, [VP, I32, P(Bipoly), VP, SZ, VP, P(Upoly)]),
+                "snc_arrangement_prepare": (C.c_int, [VP, I32, P(Bipoly), VP, SZ, VP, P(VP)]),
+                "snc_arrangement_plan": (C.c_int, [VP, P(Plan), P(Plan), P(Plan)]),
+                "snc_arrangement_run": (C.c_int, [VP, VP, SZ, VP, P(Upoly), P(Upoly)]),
+                "snc_arrangement_destroy": (C.c_int, [VP]),
                 "snc_content_y": (C.c_int, [VP, P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_sqfree_plan": (C.c_int, [P(Upoly), P(Plan)]),
                 "snc_sqfree": (C.c_int, [VP, P(Upoly), VP, SZ, VP, I32, P(C.c_uint32), P(C.c_uint32), I32,
@@ -664,6 +670,117 @@ def content_y(f, ctx: Context | None = None, stream=None) -> list:
         need = 4 * max(need, ws.numel())
     ctx.check(st, "snc_content_y")
     return _read_upoly(u, buf)
+
+
+def content_y_batch(curves, ctx: Context | None = None, stream=None) -> list:
+    """Contents in y of several curves (snc_content_y_batch): one tree of
+    batched row gcds over all curves; a list of ascending coefficient lists."""
+    ctx = ctx or default_context()
+    keep = []
+    n = len(curves)
+    F = (Bipoly * n)()
+    for i, f in enumerate(curves):
+        F[i] = _as_bipoly(f, keep)
+    each = (Plan * n)()
+    tot = Plan()
+    ctx.check(lib().snc_content_y_batch_plan(n, F, each, C.byref(tot)), "snc_content_y_batch_plan")
+    out = (Upoly * n)()
+    bufs = []
+    for i in range(n):
+        u, buf = _out_upoly(each[i].deg_bound, each[i].out_nlimbs, keep)
+        out[i] = u
+        bufs.append(buf)
+    sh = ctx.stream_handle(stream)
+    need = tot.workspace_bytes
+    for _ in range(3):
+        ws = ctx.workspace(need)
+        st = lib().snc_content_y_batch(ctx.h, n, F, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()), sh, out)
+        if st != SNC_ENOMEM:
+            break
+        need = 4 * max(need, ws.numel())
+    ctx.check(st, "snc_content_y_batch")
+    return [_read_upoly(out[i], bufs[i]) for i in range(n)]
+
+
+class Arrangement:
+    """The projection phase of an arrangement of curves (snc_arrangement_*):
+    contents of all curves in one tree of batched gcds and the primitive
+    parts at construction, then every res_y(p_i, dp_i/dy) and every
+    res_y(p_i, p_j), i < j, as one prepared batch per run()."""
+
+    def __init__(self, curves, ctx: Context | None = None, stream=None):
+        import torch
+        self.ctx = ctx or default_context()
+        self.keep = []
+        n = len(curves)
+        self.n = n
+        F = (Bipoly * n)()
+        for i, f in enumerate(curves):
+            F[i] = _as_bipoly(f, self.keep)
+        each = (Plan * n)()
+        tot = Plan()
+        self.ctx.check(lib().snc_content_y_batch_plan(n, F, each, C.byref(tot)), "snc_content_y_batch_plan")
+        sh = self.ctx.stream_handle(stream)
+        need = tot.workspace_bytes
+        h = C.c_void_p()
+        for _ in range(3):
+            cws = self.ctx.workspace(need)
+            st = lib().snc_arrangement_prepare(self.ctx.h, n, F, C.c_void_p(cws.data_ptr()), C.c_size_t(cws.numel()),
+                                               sh, C.byref(h))
+            if st != SNC_ENOMEM:
+                break
+            need = 4 * max(need, cws.numel())
+        self.ctx.check(st, "snc_arrangement_prepare")
+        self.h = h
+        npairs = n + n * (n - 1) // 2
+        self.npairs = npairs
+        ce = (Plan * n)()
+        re = (Plan * npairs)()
+        rt = Plan()
+        self.ctx.check(lib().snc_arrangement_plan(self.h, ce, re, C.byref(rt)), "snc_arrangement_plan")
+        self.cout = (Upoly * n)()
+        self.cbufs, self.ccaps = [], []
+        for i in range(n):
+            u, buf = _out_upoly(ce[i].deg_bound, ce[i].out_nlimbs, self.keep)
+            self.cout[i] = u
+            self.cbufs.append(buf)
+            self.ccaps.append((ce[i].deg_bound, ce[i].out_nlimbs))
+        self.rout = (Upoly * npairs)()
+        self.rbufs, self.rcaps = [], []
+        for i in range(npairs):
+            u, buf = _out_upoly(re[i].deg_bound, re[i].out_nlimbs, self.keep)
+            self.rout[i] = u
+            self.rbufs.append(buf)
+            self.rcaps.append((re[i].deg_bound, re[i].out_nlimbs))
+        self.plan = rt
+        self.ws = torch.empty(max(rt.workspace_bytes, 256), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+
+    def run(self, stream=None):
+        for u, (d, nl) in zip(self.cout, self.ccaps):
+            u.deg, u.nlimbs = d, nl
+        for u, (d, nl) in zip(self.rout, self.rcaps):
+            u.deg, u.nlimbs = d, nl
+        st = lib().snc_arrangement_run(self.h, C.c_void_p(self.ws.data_ptr()), C.c_size_t(self.ws.numel()),
+                                       self.ctx.stream_handle(stream), self.cout, self.rout)
+        self.ctx.check(st, "snc_arrangement_run")
+
+    def contents(self):
+        return [_read_upoly(self.cout[i], self.cbufs[i]) for i in range(self.n)]
+
+    def resultants(self):
+        """res_y(p_i, dp_i/dy) for each curve, then res_y(p_i, p_j) for i < j."""
+        return [_read_upoly(self.rout[i], self.rbufs[i]) for i in range(self.npairs)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snc_arrangement_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fastlift_q(f, ctx: Context | None = None, stream=None) -> list:

@@ -1494,6 +1494,327 @@ static snc_bipoly bipoly_of(const std::vector<UPoly>& rows, std::vector<uint32_t
   return snc_bipoly{buf.data(), (int32_t)rows.size() - 1, dx, nl};
 }
 
+static int content_rows_multi(snc_ctx* ctx, std::vector<std::vector<UPoly>>& rows, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream, std::vector<UPoly>& h, size_t* first_need);
+
+// ---- bivariate gcd in Z[x, y] (FastLift's h = gcd(f_x, f_y) when it depends on y) ----
+// Brown's dense modular method on the device (k_ygcd per (prime, point),
+// the interpolation and Chinese-remainder kernels of the resultant per
+// coefficient in y), certified by exact division on the host.
+static int poly_gcd1(snc_ctx* ctx, const UPoly& a, const UPoly& b, void* d_ws, size_t ws_bytes, hipStream_t stream,
+                     UPoly& g) {
+  if (a.c.empty() && b.c.empty()) { g = UPoly(); return SNC_OK; }
+  std::vector<uint32_t> la, lb;
+  snc_upoly ua, ub;
+  to_limbs(a, la, ua);
+  to_limbs(b, lb, ub);
+  snc_plan pl{};
+  int st = gcd_plan(1, &ua, &ub, false, nullptr, &pl);
+  if (st) return st;
+  if (pl.workspace_bytes > ws_bytes) { ctx->err = "bivariate gcd: a gcd in Z[x] needs " + std::to_string(pl.workspace_bytes) + " bytes of workspace"; return SNC_ENOMEM; }
+  std::vector<uint32_t> lo((size_t)(std::max(pl.deg_bound, 0) + 1) * pl.out_nlimbs, 0u);
+  snc_upoly uo{lo.data(), pl.deg_bound, pl.out_nlimbs};
+  st = gcd_run(ctx, 1, &ua, &ub, false, d_ws, ws_bytes, stream, &uo);
+  if (st) return st;
+  int nl = 1;
+  return parse_upoly(&uo, g, nl, ctx->err);
+}
+
+// a / h in Z[x][y] (rows in y): long division in y with exact divisions in Z[x]; false if inexact
+static bool bivariate_divexact(const std::vector<UPoly>& a, const std::vector<UPoly>& h, std::vector<UPoly>& q) {
+  std::vector<UPoly> r = a;
+  while (!r.empty() && r.back().c.empty()) r.pop_back();
+  const int dh = (int)h.size() - 1;
+  q.assign(r.size() >= h.size() ? r.size() - h.size() + 1 : 0, UPoly());
+  while (!r.empty() && (int)r.size() - 1 >= dh) {
+    const int sft = (int)r.size() - 1 - dh;
+    UPoly c;
+    if (!poly_divexact(r.back(), h.back(), c)) return false;
+    for (int i = 0; i <= dh; ++i) {
+      UPoly prod;
+      prod.c.assign(c.c.size() + h[i].c.size() - 1, BigInt());
+      if (c.c.empty() || h[i].c.empty()) prod.c.clear();
+      for (size_t u = 0; u < c.c.size(); ++u)
+        for (size_t v = 0; v < h[i].c.size(); ++v) prod.c[u + v] = prod.c[u + v] + c.c[u] * h[i].c[v];
+      trim(prod);
+      r[sft + i] = poly_sub(r[sft + i], prod);
+    }
+    q[sft] = std::move(c);
+    while (!r.empty() && r.back().c.empty()) r.pop_back();
+  }
+  while (!q.empty() && q.back().c.empty()) q.pop_back();
+  return r.empty();
+}
+
+// P(x) -> P(x - s)
+static void taylor_shift_back(UPoly& P, int64_t s) {
+  const int n = P.deg();
+  if (n < 1 || s == 0) return;
+  const uint32_t m = (uint32_t)(s < 0 ? -s : s);
+  for (int i = 0; i < n; ++i)
+    for (int j = n - 1; j >= i; --j) {
+      const BigInt t = P.c[j + 1].mul_small(m);
+      P.c[j] = s > 0 ? P.c[j] - t : P.c[j] + t;  // c_j += (-s) c_{j+1}
+    }
+}
+
+static uint64_t eval_mod(const UPoly& P, uint64_t x, uint32_t p) {
+  uint64_t acc = 0;
+  for (size_t k = P.c.size(); k-- > 0;) acc = (acc * x + P.c[k].smod(p)) % p;
+  return acc;
+}
+
+static int max_rowdeg(const std::vector<UPoly>& R) {
+  int d = 0;
+  for (const auto& r : R) d = std::max(d, r.deg());
+  return d;
+}
+
+// device part of one attempt: images at x = j + shift for the first k primes,
+// then (if the gcd degree e > 0 is the same at every image) W's coefficients
+// 0..e in x by interpolation and Chinese remaindering
+struct YgcdLayout {
+  size_t jr = 0, jobs = 0, pref_red = 0, pref_ip = 0, pref_crt = 0, pref_crt2 = 0, list_crt = 0, zero = 0, e_out = 0;
+  size_t coef = 0, res = 0, regions = 0, total = 0;
+  int64_t n1 = 0, L = 1, job_words = 0;
+};
+
+static void ygcd_layout(int k, int T, int nl, int Dx, int emax, YgcdLayout& Y) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  Y = YgcdLayout();
+  Y.n1 = Dx + 1;
+  Y.L = (30 * (int64_t)k + 31) / 32 + 1;
+  const int nj = emax + 1;
+  size_t off = 0;
+  Y.jr = off; off = al(off + sizeof(ResJob));
+  Y.jobs = off; off = al(off + sizeof(ResJob) * nj);
+  Y.pref_red = off; off = al(off + 16);
+  Y.pref_ip = off; off = al(off + 8 * (nj + 1));
+  Y.pref_crt = off; off = al(off + 8 * (nj + 1));
+  Y.pref_crt2 = off; off = al(off + 8 * (nj + 1));
+  Y.list_crt = off; off = al(off + 4 * nj);
+  Y.zero = off; off = al(off + 4);
+  Y.e_out = off; off = al(off + 4 * (size_t)k * Y.n1);
+  Y.coef = off; off = al(off + 4 * (size_t)T * nl);
+  Y.res = off; off = al(off + 4 * (size_t)T * k);
+  Y.regions = off;
+  const size_t nqw = (size_t)k * ((Y.n1 + 63) / 64) * 64;
+  Y.job_words = (int64_t)(align_words((size_t)k * Y.n1) * 2 + align_words(nqw) + align_words((size_t)Y.n1 * k) +
+                          align_words((size_t)Y.n1 * Y.L));
+  Y.total = Y.regions + 4 * (size_t)Y.job_words * nj;
+}
+
+static int bivariate_gcd_run(snc_ctx* ctx, const std::vector<UPoly>& A, const std::vector<UPoly>& B, void* d_ws,
+                             size_t ws_bytes, hipStream_t stream, std::vector<UPoly>& H) {
+  H.clear();
+  // contents in y and primitive parts
+  std::vector<std::vector<UPoly>> rows(2);
+  for (const auto& r : A) if (!r.c.empty()) rows[0].push_back(r);
+  for (const auto& r : B) if (!r.c.empty()) rows[1].push_back(r);
+  std::vector<UPoly> cont;
+  int st = content_rows_multi(ctx, rows, d_ws, ws_bytes, stream, cont, nullptr);
+  if (st) return st;
+  UPoly c;
+  st = poly_gcd1(ctx, cont[0], cont[1], d_ws, ws_bytes, stream, c);
+  if (st) return st;
+  std::vector<UPoly> Ap(A.size()), Bp(B.size());
+  for (size_t i = 0; i < A.size(); ++i)
+    if (!A[i].c.empty() && !poly_divexact(A[i], cont[0], Ap[i])) { ctx->err = "bivariate gcd: content"; return SNC_EINTERNAL; }
+  for (size_t i = 0; i < B.size(); ++i)
+    if (!B[i].c.empty() && !poly_divexact(B[i], cont[1], Bp[i])) { ctx->err = "bivariate gcd: content"; return SNC_EINTERNAL; }
+  const int mA = (int)Ap.size() - 1, mB = (int)Bp.size() - 1;
+  if (mA == 0 || mB == 0) { H = {c}; return SNC_OK; }  // a primitive part of y-degree 0 is 1
+  UPoly gam;
+  st = poly_gcd1(ctx, Ap.back(), Bp.back(), d_ws, ws_bytes, stream, gam);
+  if (st) return st;
+  const int dxA = max_rowdeg(Ap), dxB = max_rowdeg(Bp);
+  const int Dx = gam.deg() + std::min(dxA, dxB);
+  const int emax = std::min(mA, mB);
+  if (Dx > MAX_D || std::max(mA, mB) > MAXY_GEN) { ctx->err = "bivariate gcd: degrees beyond the supported range"; return SNC_ENOTSUP; }
+  // residues layout: A rows, B rows (dense rectangles), gamma
+  const int offA = 0, offB = (mA + 1) * (dxA + 1), offG = offB + (mB + 1) * (dxB + 1);
+  const int T = offG + gam.deg() + 1;
+  int nl = 1;
+  for (const auto* P : {&Ap, &Bp})
+    for (const auto& r : *P) for (const auto& x : r.c) nl = std::max(nl, x.twos_limbs());
+  for (const auto& x : gam.c) nl = std::max(nl, x.twos_limbs());
+  std::vector<uint32_t> coef((size_t)T * nl, 0u);  // limb-major [nl][T]
+  auto put = [&](int t, const BigInt& v) {
+    std::vector<uint32_t> tmp(nl);
+    (void)v.to_twos(tmp.data(), nl);
+    for (int l = 0; l < nl; ++l) coef[(size_t)l * T + t] = tmp[l];
+  };
+  for (int i = 0; i <= mA; ++i) for (size_t k2 = 0; k2 < Ap[i].c.size(); ++k2) put(offA + i * (dxA + 1) + (int)k2, Ap[i].c[k2]);
+  for (int i = 0; i <= mB; ++i) for (size_t k2 = 0; k2 < Bp[i].c.size(); ++k2) put(offB + i * (dxB + 1) + (int)k2, Bp[i].c[k2]);
+  for (size_t k2 = 0; k2 < gam.c.size(); ++k2) put(offG + (int)k2, gam.c[k2]);
+  // first prime count: coefficients of A, B and gamma, with room for the growth of a factor
+  double bits = 0;
+  for (const auto* P : {&Ap, &Bp})
+    for (const auto& r : *P) for (const auto& x : r.c) bits = std::max(bits, (double)x.bitlen());
+  for (const auto& x : gam.c) bits = std::max(bits, (double)x.bitlen());
+  const Tables& Tb = tables();
+  auto primes_for = [&](double b) { int k = 1; while (k < KMAX && Tb.lg[k] <= b + 2.0) ++k; return k; };
+  int k = std::max(2, primes_for(bits + Dx + emax + std::log2((double)Dx + 2.0) * (emax + 1) + 16.0));
+  int64_t shift = 0;
+  const CrtTables tb = global_crt_tables();
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int attempt = 0; attempt < 12; ++attempt) {
+    // points whose leading coefficients or gamma vanish mod a prime are avoided by shifting the point set
+    for (int tries = 0; tries < 64; ++tries) {
+      bool ok = true;
+      for (int i = 0; i < k && ok; ++i) {
+        const uint32_t p = Tb.p[i];
+        for (int j = 0; j <= Dx && ok; ++j) {
+          const uint64_t x = ((uint64_t)j + (uint64_t)shift) % p;
+          ok = eval_mod(Ap.back(), x, p) && eval_mod(Bp.back(), x, p) && eval_mod(gam, x, p);
+        }
+      }
+      if (ok) break;
+      shift += Dx + 1 + 7 * tries;
+    }
+    YgcdLayout Y;
+    ygcd_layout(k, T, nl, Dx, emax, Y);
+    if (Y.total > ws_bytes) {
+      ctx->err = "bivariate gcd: " + std::to_string(k) + " primes need " + std::to_string(Y.total) + " bytes of workspace";
+      return SNC_ENOMEM;
+    }
+    uint8_t* ws = (uint8_t*)d_ws;
+    // upload block: the reduction job, the coefficient limbs
+    std::vector<uint8_t> hdr(Y.regions, 0);
+    ResJob jr{};
+    jr.k = k; jr.T = T; jr.nl = nl;
+    jr.coef_off = (int64_t)(Y.coef / 4);
+    jr.res_off = (int64_t)(Y.res / 4);
+    std::memcpy(hdr.data() + Y.jr, &jr, sizeof jr);
+    const int64_t pr[2] = {0, (int64_t)k * ((T + 255) / 256)};
+    std::memcpy(hdr.data() + Y.pref_red, pr, sizeof pr);
+    std::memcpy(hdr.data() + Y.coef, coef.data(), coef.size() * 4);
+    HIPCHK(hipMemcpyAsync(ws, hdr.data(), Y.regions, hipMemcpyHostToDevice, stream));
+    launch_reduce((const ResJob*)(ws + Y.jr), (const int64_t*)(ws + Y.pref_red), 1, pr[1], (const uint32_t*)ws,
+                  (uint32_t*)ws, nullptr, stream);
+    YGcdArgs ya{};
+    ya.primes = tb.primes; ya.res = (const uint32_t*)(ws + Y.res); ya.T = T; ya.k = k; ya.npts = (int)Y.n1;
+    ya.mA = mA; ya.dxA = dxA; ya.offA = offA; ya.mB = mB; ya.dxB = dxB; ya.offB = offB;
+    ya.offG = offG; ya.dg = gam.deg(); ya.emax = emax; ya.cap = std::max(mA, mB); ya.shift = (uint32_t)shift;
+    ya.e_out = (int32_t*)(ws + Y.e_out);
+    ya.w = (uint32_t*)ws;
+    ya.w_off = (int64_t)(Y.regions / 4);  // pts region of job i at regions + i job_words
+    ya.w_stride = Y.job_words;
+    launch_ygcd(ya, stream);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> e((size_t)k * Y.n1);
+    HIPCHK(hipMemcpyAsync(e.data(), ws + Y.e_out, e.size() * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const int emin = *std::min_element(e.begin(), e.end());
+    const int emx = *std::max_element(e.begin(), e.end());
+    if (emin < 0 || emin != emx) { shift += Dx + 1; continue; }  // a bad or unlucky image: other points
+    if (emin == 0) { H = {c}; return SNC_OK; }                     // the primitive parts are coprime
+    // interpolation and Chinese remaindering of W's coefficients 0..emin (jobs 0..emin)
+    const int nj = emin + 1;
+    std::vector<ResJob> jobs(nj);
+    for (int i = 0; i < nj; ++i) {
+      ResJob& J = jobs[i];
+      std::memset(&J, 0, sizeof J);
+      J.D = Dx; J.k = k; J.L = (int)Y.L; J.nl = 1;
+      int64_t w = (int64_t)(Y.regions / 4) + (int64_t)i * Y.job_words;
+      J.pts_off = w; w += (int64_t)align_words((size_t)k * Y.n1);
+      J.val_off = w; w += (int64_t)align_words((size_t)k * Y.n1);
+      J.nq_off = w; w += (int64_t)align_words((size_t)k * ((Y.n1 + 63) / 64) * 64);
+      J.dig_off = w; w += (int64_t)align_words((size_t)Y.n1 * k);
+      J.out_off = w;
+    }
+    const bool blk = interp_blk_fits(Dx, k);
+    std::vector<int64_t> pip(nj + 1, 0), pcr(nj + 1, 0), pcc(nj + 1, 0);
+    const int cc = crt_small_class(k);
+    for (int i = 0; i < nj; ++i) {
+      pip[i + 1] = pip[i] + (blk ? (int64_t)k * ((Y.n1 + 63) / 64) : k);
+      pcr[i + 1] = pcr[i] + (cc >= 0 ? (Y.n1 + 63) / 64 : (Y.n1 + CRT_COEF_PER_BLOCK - 1) / CRT_COEF_PER_BLOCK);
+      pcc[i + 1] = pcc[i] + (Y.n1 + CRT_COMB_PER_BLOCK - 1) / CRT_COMB_PER_BLOCK;
+    }
+    std::vector<int32_t> lst(nj);
+    for (int i = 0; i < nj; ++i) lst[i] = i;
+    HIPCHK(hipMemcpyAsync(ws + Y.jobs, jobs.data(), sizeof(ResJob) * nj, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + Y.pref_ip, pip.data(), 8 * (nj + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + Y.pref_crt, pcr.data(), 8 * (nj + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + Y.pref_crt2, pcc.data(), 8 * (nj + 1), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + Y.list_crt, lst.data(), 4 * nj, hipMemcpyHostToDevice, stream));
+    const ResJob* jd = (const ResJob*)(ws + Y.jobs);
+    uint32_t* zero = (uint32_t*)(ws + Y.zero);
+    if (blk) launch_interp_blk(jd, (const int64_t*)(ws + Y.pref_ip), nj, pip[nj], (uint32_t*)ws, zero, stream);
+    else launch_interp(jd, (const int64_t*)(ws + Y.pref_ip), nj, pip[nj], Dx, (uint32_t*)ws, zero, stream);
+    if (cc >= 0) {
+      launch_crt_small(cc, jd, (const int32_t*)(ws + Y.list_crt), (const int64_t*)(ws + Y.pref_crt), nj, pcr[nj],
+                       (uint32_t*)ws, stream);
+    } else {
+      launch_crt_digits(tb, jd, (const int32_t*)(ws + Y.list_crt), (const int64_t*)(ws + Y.pref_crt), nj, pcr[nj],
+                        (uint32_t*)ws, stream);
+      launch_crt_combine(tb, jd, (const int32_t*)(ws + Y.list_crt), (const int64_t*)(ws + Y.pref_crt2), nj, pcc[nj],
+                         k, (uint32_t*)ws, stream);
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<uint32_t> outl((size_t)nj * Y.n1 * Y.L);
+    for (int i = 0; i < nj; ++i)
+      HIPCHK(hipMemcpyAsync(outl.data() + (size_t)i * Y.n1 * Y.L, ws + 4 * (size_t)jobs[i].out_off,
+                            4 * (size_t)Y.n1 * Y.L, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<UPoly> W(nj);
+    for (int i = 0; i < nj; ++i) {
+      W[i].c.resize(Y.n1);
+      for (int64_t t = 0; t < Y.n1; ++t)
+        W[i].c[t] = BigInt::from_twos(outl.data() + ((size_t)i * Y.n1 + t) * Y.L, (int)Y.L);
+      trim(W[i]);
+      taylor_shift_back(W[i], shift);
+    }
+    // h0 = pp_y(W): W's rows divided by their gcd in Z[x]
+    std::vector<std::vector<UPoly>> wr(1);
+    for (const auto& r : W) if (!r.c.empty()) wr[0].push_back(r);
+    std::vector<UPoly> wc;
+    st = content_rows_multi(ctx, wr, d_ws, ws_bytes, stream, wc, nullptr);
+    if (st) return st;
+    std::vector<UPoly> h0(nj), qa, qb;
+    bool good = !wc[0].c.empty();
+    for (int i = 0; i < nj && good; ++i)
+      good = W[i].c.empty() || poly_divexact(W[i], wc[0], h0[i]);
+    if (good && bivariate_divexact(Ap, h0, qa) && bivariate_divexact(Bp, h0, qb)) {
+      H.resize(nj);
+      for (int i = 0; i < nj; ++i) {
+        // H_i = c h0_i
+        H[i].c.assign(h0[i].c.empty() ? 0 : h0[i].c.size() + c.c.size() - 1, BigInt());
+        for (size_t u = 0; u < h0[i].c.size(); ++u)
+          for (size_t v = 0; v < c.c.size(); ++v) H[i].c[u + v] = H[i].c[u + v] + h0[i].c[u] * c.c[v];
+        trim(H[i]);
+      }
+      if (!H.back().c.empty() && H.back().c.back().neg)
+        for (auto& r : H) for (auto& x : r.c) x = -x;
+      return SNC_OK;
+    }
+    k = std::min(KMAX, 2 * k);  // too few primes for W's coefficients
+  }
+  ctx->err = "bivariate gcd: no certified result";
+  return SNC_EINTERNAL;
+}
+
+// workspace of the bivariate gcd's device pass with up to four times the first prime count
+static size_t bivariate_gcd_ws(const std::vector<UPoly>& A, const std::vector<UPoly>& B) {
+  const int mA = (int)A.size() - 1, mB = (int)B.size() - 1;
+  if (mA < 1 || mB < 1) return 0;
+  const int dxA = max_rowdeg(A), dxB = max_rowdeg(B);
+  const int Dx = std::max(dxA, dxB) + std::min(dxA, dxB);
+  double bits = 0;
+  int nl = 1;
+  for (const auto* P : {&A, &B})
+    for (const auto& r : *P) for (const auto& x : r.c) { bits = std::max(bits, (double)x.bitlen()); nl = std::max(nl, x.twos_limbs()); }
+  const Tables& Tb = tables();
+  int k = 1;
+  const int emax = std::min(mA, mB);
+  while (k < KMAX && Tb.lg[k] <= bits + Dx + emax + std::log2((double)Dx + 2.0) * (emax + 1) + 18.0) ++k;
+  k = std::min(KMAX, 4 * std::max(k, 2));
+  const int T = (mA + 1) * (dxA + 1) + (mB + 1) * (dxB + 1) + Dx + 1;
+  YgcdLayout Y;
+  ygcd_layout(k, T, nl + 1, Dx, emax, Y);
+  return Y.total;
+}
+
 static int fastlift_q_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t ws_bytes, hipStream_t stream,
                           snc_upoly* out) {
   std::vector<UPoly> rows, fx, fy;
@@ -1513,9 +1834,17 @@ static int fastlift_q_run(snc_ctx* ctx, const snc_bipoly* f, void* d_ws, size_t 
     ++tries;
     ydeg0 = d == 0;
   }
-  if (!ydeg0) {
-    ctx->err = "fastlift Q: gcd(f_x, f_y) depends on y (no bivariate gcd in this library)";
-    return SNC_ENOTSUP;
+  if (!ydeg0) {  // h depends on y: the bivariate modular gcd, then exact division of f_x and f_y
+    std::vector<UPoly> H, qx, qy;
+    st = bivariate_gcd_run(ctx, fx, fy, d_ws, ws_bytes, stream, H);
+    if (st) return st;
+    if (!bivariate_divexact(fx, H, qx) || !bivariate_divexact(fy, H, qy)) {
+      ctx->err = "fastlift Q: h does not divide f_x, f_y";
+      return SNC_EINTERNAL;
+    }
+    std::vector<uint32_t> bx, by;
+    const snc_bipoly px = bipoly_of(qx, bx), py = bipoly_of(qy, by);
+    return snc_resultant_y(ctx, &px, &py, d_ws, ws_bytes, stream, out);
   }
   // h in Z[x]: the gcd of every row of f_x and f_y
   std::vector<UPoly> all;
@@ -1578,7 +1907,8 @@ static int fastlift_q_plan(const snc_bipoly* f, snc_plan* out) {
     st = content_level(nullptr, all, nullptr, 0, nullptr, nullptr, &need);
     if (st) return st;
   }
-  out->workspace_bytes = std::max(out->workspace_bytes, need);
+  // a y-dependent h: the bivariate gcd's device pass (its plan, a bound for up to four times its first primes)
+  out->workspace_bytes = std::max({out->workspace_bytes, need, bivariate_gcd_ws(fx, fy)});
   return SNC_OK;
 }
 
@@ -1645,6 +1975,97 @@ static void bound_quick(int da, int db, double ba, double bb, Quick& Q) {
   Q.target0 = std::min(Q.kmax, std::max(3, primes_for_bits(bits_needed_opt(sz)) + 2));
 }
 
+
+// ---- arrangement batches: every curve and every pair of a set (Section 3) ----
+// The contents in y of all curves come from one binary tree: per level, the
+// rows of every curve are paired and all pairs of all curves go to one
+// batched gcd submission (an odd last row is carried to the next level).
+// first_need (if set): only the workspace of the first level is computed.
+static int content_rows_multi(snc_ctx* ctx, std::vector<std::vector<UPoly>>& rows, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream, std::vector<UPoly>& h, size_t* first_need) {
+  const size_t n = rows.size();
+  for (;;) {
+    std::vector<int> owner;
+    std::vector<std::vector<uint32_t>> la, lb, lo;
+    std::vector<snc_upoly> ua, ub, uo;
+    for (size_t i = 0; i < n; ++i)
+      for (size_t q = 0; q + 1 < rows[i].size(); q += 2) owner.push_back((int)i);
+    const int np = (int)owner.size();
+    if (np == 0) break;
+    la.resize(np); lb.resize(np); lo.resize(np); ua.resize(np); ub.resize(np); uo.resize(np);
+    {
+      int t = 0;
+      for (size_t i = 0; i < n; ++i)
+        for (size_t q = 0; q + 1 < rows[i].size(); q += 2, ++t) {
+          to_limbs(rows[i][q], la[t], ua[t]);
+          to_limbs(rows[i][q + 1], lb[t], ub[t]);
+        }
+    }
+    std::vector<snc_plan> each(np);
+    snc_plan tot{};
+    int st = gcd_plan(np, ua.data(), ub.data(), false, each.data(), &tot);
+    if (st) return st;
+    if (first_need) { *first_need = tot.workspace_bytes; return SNC_OK; }
+    if (tot.workspace_bytes > ws_bytes) {
+      ctx->err = "contents: a level of the row gcds needs " + std::to_string(tot.workspace_bytes) +
+                 " bytes of workspace";
+      return SNC_ENOMEM;
+    }
+    for (int t = 0; t < np; ++t) {
+      lo[t].assign((size_t)(std::max(each[t].deg_bound, 0) + 1) * each[t].out_nlimbs, 0u);
+      uo[t] = snc_upoly{lo[t].data(), each[t].deg_bound, each[t].out_nlimbs};
+    }
+    st = gcd_run(ctx, np, ua.data(), ub.data(), false, d_ws, ws_bytes, stream, uo.data());
+    if (st) return st;
+    std::vector<std::vector<UPoly>> next(n);
+    int t = 0;
+    for (size_t i = 0; i < n; ++i) {
+      for (size_t q = 0; q + 1 < rows[i].size(); q += 2, ++t) {
+        UPoly g;
+        int nl = 1;
+        st = parse_upoly(&uo[t], g, nl, ctx->err);
+        if (st) return st;
+        next[i].push_back(std::move(g));
+      }
+      if (rows[i].size() % 2) next[i].push_back(std::move(rows[i].back()));
+    }
+    rows.swap(next);
+  }
+  if (first_need) { *first_need = 0; return SNC_OK; }
+  h.assign(n, UPoly());
+  for (size_t i = 0; i < n; ++i) {
+    if (rows[i].empty()) continue;  // f_i = 0
+    h[i] = std::move(rows[i][0]);
+    if (h[i].c.back().neg)
+      for (auto& x : h[i].c) x = -x;
+  }
+  return SNC_OK;
+}
+
+// non-zero rows of each curve (the input of the content tree)
+static int curves_rows(int n, const snc_bipoly* f, std::vector<std::vector<UPoly>>& rows, std::string& err) {
+  rows.assign(n, {});
+  for (int i = 0; i < n; ++i) {
+    const int st = bipoly_rows(&f[i], rows[i], err);
+    if (st) { err = "curve " + std::to_string(i) + ": " + err; return st; }
+  }
+  return SNC_OK;
+}
+
+// bound on a curve's content: it divides the row of least degree (Mignotte)
+static void content_bound(const std::vector<UPoly>& rows, snc_plan& out) {
+  out = snc_plan{};
+  out.out_nlimbs = 1;
+  if (rows.empty()) return;
+  size_t best = 0;
+  for (size_t i = 1; i < rows.size(); ++i)
+    if (rows[i].deg() < rows[best].deg()) best = i;
+  int nl = 1;
+  for (const auto& x : rows[best].c) nl = std::max(nl, x.twos_limbs());
+  out.deg_bound = rows[best].deg();
+  out.out_nlimbs = nl + (out.deg_bound + (int)std::ceil(std::log2(out.deg_bound + 2.0))) / 32 + 1;
+}
+
 static int sqfree_plan(const snc_upoly* a, snc_plan* out) {
   std::string err;
   int st = check_upoly(a, err);
@@ -1679,6 +2100,24 @@ static int sqfree_plan(const snc_upoly* a, snc_plan* out) {
 }
 
 }  // namespace snc
+
+
+// A prepared arrangement: the contents of the curves (computed at
+// preparation), the primitive parts f_i / cont_y(f_i) and their
+// y-derivatives as operand limbs, and the resultant pairs
+//   (f~_i, d f~_i / dy) for every curve, then (f~_i, f~_j) for i < j,
+// run as one prepared resultant batch.
+struct snc_arrangement {
+  snc_ctx* c = nullptr;
+  int n = 0;
+  std::vector<snc::UPoly> h;                    // contents
+  std::vector<std::vector<uint32_t>> limbs;     // 2n operands: f~_i, then d f~_i / dy
+  std::vector<snc_bipoly> ops;
+  std::vector<snc_bipoly> F, G;                 // n + n(n-1)/2 pairs
+  snc_prepared* prep = nullptr;
+  void* prep_ws = nullptr;
+  size_t prep_bytes = 0;
+};
 
 using namespace snc;
 
@@ -1787,6 +2226,142 @@ int snc_sqfree(snc_ctx* ctx, const snc_upoly* a, void* d_ws, size_t ws_bytes, vo
       ++pos;
     }
   }
+  return SNC_OK;
+}
+
+int snc_content_y_batch_plan(int32_t n, const snc_bipoly* f, snc_plan* out_each, snc_plan* out_total) {
+  if (n < 0 || (n > 0 && !f) || !out_total) return SNC_EINVAL;
+  std::string err;
+  std::vector<std::vector<UPoly>> rows;
+  int st = curves_rows(n, f, rows, err);
+  if (st) return st;
+  *out_total = snc_plan{};
+  out_total->out_nlimbs = 1;
+  for (int i = 0; i < n; ++i) {
+    snc_plan b;
+    content_bound(rows[i], b);
+    if (out_each) out_each[i] = b;
+    out_total->deg_bound = std::max(out_total->deg_bound, b.deg_bound);
+    out_total->out_nlimbs = std::max(out_total->out_nlimbs, b.out_nlimbs);
+  }
+  size_t need = 0;
+  std::vector<UPoly> h;
+  st = content_rows_multi(nullptr, rows, nullptr, 0, nullptr, h, &need);
+  if (st) return st;
+  out_total->workspace_bytes = need;
+  return SNC_OK;
+}
+
+static int write_upoly(snc_ctx* ctx, const UPoly& P, snc_upoly* out) {
+  int nl = 1;
+  for (const auto& x : P.c) nl = std::max(nl, x.twos_limbs());
+  if (out->deg < P.deg() || out->nlimbs < nl || (!P.c.empty() && !out->limbs)) {
+    out->deg = P.deg();
+    out->nlimbs = nl;
+    ctx->err = "output buffer too small";
+    return SNC_ERANGE;
+  }
+  for (size_t k = 0; k < P.c.size(); ++k) (void)P.c[k].to_twos(out->limbs + k * out->nlimbs, out->nlimbs);
+  out->deg = P.deg();
+  return SNC_OK;
+}
+
+int snc_content_y_batch(snc_ctx* ctx, int32_t n, const snc_bipoly* f, void* d_ws, size_t ws_bytes, void* stream,
+                        snc_upoly* out) {
+  if (!ctx || n < 0 || (n > 0 && (!f || !out))) return SNC_EINVAL;
+  std::vector<std::vector<UPoly>> rows;
+  int st = curves_rows(n, f, rows, ctx->err);
+  if (st) return st;
+  std::vector<UPoly> h;
+  st = content_rows_multi(ctx, rows, d_ws, ws_bytes, (hipStream_t)stream, h, nullptr);
+  if (st) return st;
+  int range = SNC_OK;
+  for (int i = 0; i < n; ++i)
+    if (write_upoly(ctx, h[i], &out[i]) == SNC_ERANGE) range = SNC_ERANGE;
+  return range;
+}
+
+int snc_arrangement_prepare(snc_ctx* ctx, int32_t n, const snc_bipoly* curves, void* d_ws, size_t ws_bytes,
+                            void* stream, snc_arrangement** out) {
+  if (!ctx || !out || n < 0 || (n > 0 && !curves)) return SNC_EINVAL;
+  *out = nullptr;
+  std::vector<std::vector<UPoly>> rows;
+  int st = curves_rows(n, curves, rows, ctx->err);
+  if (st) return st;
+  auto* A = new snc_arrangement();
+  A->c = ctx;
+  A->n = n;
+  st = content_rows_multi(ctx, rows, d_ws, ws_bytes, (hipStream_t)stream, A->h, nullptr);
+  if (st) { delete A; return st; }
+  A->limbs.resize(2 * (size_t)n);
+  A->ops.resize(2 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    std::vector<UPoly> all, prim, dprim;
+    st = bipoly_all_rows(&curves[i], all, ctx->err);
+    if (st) { delete A; return st; }
+    prim.resize(all.size());
+    for (size_t r = 0; r < all.size(); ++r) {
+      if (all[r].c.empty()) continue;
+      if (!poly_divexact(all[r], A->h[i], prim[r])) {
+        ctx->err = "arrangement: the content of curve " + std::to_string(i) + " does not divide a row";
+        delete A;
+        return SNC_EINTERNAL;
+      }
+    }
+    while (!prim.empty() && prim.back().c.empty()) prim.pop_back();
+    dprim.resize(prim.size() > 1 ? prim.size() - 1 : 0);
+    for (size_t r = 1; r < prim.size(); ++r)
+      for (const auto& x : prim[r].c) dprim[r - 1].c.push_back(x.mul_small((uint32_t)r));
+    while (!dprim.empty() && dprim.back().c.empty()) dprim.pop_back();
+    A->ops[i] = bipoly_of(prim, A->limbs[i]);
+    A->ops[n + i] = bipoly_of(dprim, A->limbs[n + i]);
+  }
+  for (int i = 0; i < n; ++i) { A->F.push_back(A->ops[i]); A->G.push_back(A->ops[n + i]); }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) { A->F.push_back(A->ops[i]); A->G.push_back(A->ops[j]); }
+  *out = A;
+  return SNC_OK;
+}
+
+int snc_arrangement_plan(const snc_arrangement* A, snc_plan* content_each, snc_plan* res_each, snc_plan* res_total) {
+  if (!A || !res_total) return SNC_EINVAL;
+  if (content_each)
+    for (int i = 0; i < A->n; ++i) {
+      int nl = 1;
+      for (const auto& x : A->h[i].c) nl = std::max(nl, x.twos_limbs());
+      content_each[i] = snc_plan{};
+      content_each[i].deg_bound = std::max(A->h[i].deg(), 0);
+      content_each[i].out_nlimbs = nl;
+    }
+  return snc_resultant_y_batch_plan((int32_t)A->F.size(), A->F.data(), A->G.data(), res_each, res_total);
+}
+
+int snc_arrangement_run(snc_arrangement* A, void* d_ws, size_t ws_bytes, void* stream, snc_upoly* contents,
+                        snc_upoly* resultants) {
+  if (!A || (A->n > 0 && (!contents || !resultants))) return SNC_EINVAL;
+  snc_ctx* ctx = A->c;
+  int range = SNC_OK;
+  for (int i = 0; i < A->n; ++i)
+    if (write_upoly(ctx, A->h[i], &contents[i]) == SNC_ERANGE) range = SNC_ERANGE;
+  if (range) return range;
+  if (A->prep && (A->prep_ws != d_ws || A->prep_bytes != ws_bytes)) {
+    destroy_prepared(A->prep);
+    A->prep = nullptr;
+  }
+  if (!A->prep) {
+    const int st = prepare_resultants(ctx, (int)A->F.size(), A->F.data(), A->G.data(), d_ws, ws_bytes,
+                                      (hipStream_t)stream, /*graph=*/true, &A->prep);
+    if (st) return st;
+    A->prep_ws = d_ws;
+    A->prep_bytes = ws_bytes;
+  }
+  return run_prepared(A->prep, (hipStream_t)stream, resultants);
+}
+
+int snc_arrangement_destroy(snc_arrangement* A) {
+  if (!A) return SNC_EINVAL;
+  if (A->prep) destroy_prepared(A->prep);
+  delete A;
   return SNC_OK;
 }
 

@@ -104,6 +104,7 @@ int ensure_device_tables(int device, std::string& err) {
   const Tables& T = tables();
   hipError_t e = configure_kernels();
   if (e == hipSuccess) e = configure_gcd_kernels();
+  if (e == hipSuccess) e = configure_ygcd_kernel();
   if (e != hipSuccess) { err = std::string("kernel attributes: ") + hipGetErrorString(e); return SNC_EDEVICE; }
   e = init_noalloc_scratch(device);
   if (e != hipSuccess) { err = std::string("scratch address: ") + hipGetErrorString(e); return SNC_EDEVICE; }

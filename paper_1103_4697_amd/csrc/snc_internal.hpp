@@ -196,6 +196,27 @@ void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* s
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();
 
+// Per-(prime, point) images of a bivariate gcd (k_ygcd): A and B (rows in y
+// of polynomials in x, dense rectangles of residues) evaluated at
+// x_j = j + shift, W_j = gamma(x_j) * monic gcd_y(A(x_j, y), B(x_j, y)) mod p.
+struct YGcdArgs {
+  const PrimeC* primes;
+  const uint32_t* res;   // Montgomery residues [k][T]
+  int32_t T, k, npts;    // residues per prime, primes, points
+  int32_t mA, dxA, offA; // A: row i, coefficient of x^t at offA + i (dxA + 1) + t
+  int32_t mB, dxB, offB;
+  int32_t offG, dg;      // gamma: coefficient of x^t at offG + t, degree dg
+  int32_t emax;          // coefficients 0..emax of W are written
+  int32_t cap;           // LDS columns hold cap + 1 words (cap >= mA, mB)
+  uint32_t shift;
+  int32_t* e_out;        // [k][npts]: degree of the gcd, -1 at a point where a leading coefficient vanishes
+  uint32_t* w;           // coefficient i of W at w[w_off + i w_stride + pi npts + j] (Montgomery)
+  int64_t w_off, w_stride;
+};
+size_t ygcd_lds_bytes(int cap);
+hipError_t configure_ygcd_kernel();
+void launch_ygcd(const YGcdArgs& a, hipStream_t s);
+
 int fast_class_of(int maxy);  // index of the register class for a y-degree, -1 if none
 int fast_class_cap(int cls);
 

@@ -241,6 +241,53 @@ def random_curve_set(rng, d: int, bits: int, ncurves: int = 5):
     return pairs
 
 
+def circle(a: int, b: int, r2: int):
+    """(x - a)^2 + (y - b)^2 - r2 as rows in y (row i = coefficient of y^i)."""
+    return [[a * a + b * b - r2, -2 * a, 1], [-2 * b], [1]]
+
+
+def ellipse(A: int, B: int, a: int, b: int, C: int):
+    """A (x - a)^2 + B (y - b)^2 - C as rows in y."""
+    return [[A * a * a + B * b * b - C, -2 * A * a, A], [-2 * B * b], [B]]
+
+
+def arrangement_set(rng, ncurves: int, kinds=("circle", "ellipse", "random", "graph", "content")):
+    """A set of `ncurves` planar curves for an arrangement (rows in y of
+    Python ints), cycling through the families: circles and ellipses with
+    integer centres and radii, random dense curves of total degree 3..8
+    with signed 10-bit coefficients, graphs of rational functions
+    q(x) y - p(x) (deg p <= 4, deg q <= 3), and random curves of degree
+    3..5 times a factor in x alone (x - c or x^2 + c1 x + c0), whose content
+    in y is that factor times the integer content."""
+    curves = []
+    for i in range(ncurves):
+        kind = kinds[i % len(kinds)]
+        if kind == "circle":
+            a, b = (int(v) for v in rng.integers(-20, 21, size=2))
+            curves.append(circle(a, b, int(rng.integers(1, 226))))
+        elif kind == "ellipse":
+            A, B = (int(v) for v in rng.integers(1, 10, size=2))
+            a, b = (int(v) for v in rng.integers(-20, 21, size=2))
+            curves.append(ellipse(A, B, a, b, int(rng.integers(1, 400))))
+        elif kind == "random":
+            d = int(rng.integers(3, 9))
+            F = dense_bivariate(rng, d, bits=10)
+            curves.append([[int(c) for c in row] for row in F])
+        elif kind == "graph":
+            pp = [int(c) for c in rng.integers(-50, 51, size=int(rng.integers(1, 6)))]
+            qq = [int(c) for c in rng.integers(-50, 51, size=int(rng.integers(1, 5)))]
+            if not any(qq):
+                qq = [1]
+            curves.append([[-c for c in pp], qq])
+        else:
+            d = int(rng.integers(3, 6))
+            F = [[int(c) for c in row] for row in dense_bivariate(rng, d, bits=8)]
+            c = int(rng.integers(-9, 10))
+            h = [-c, 1] if rng.integers(0, 2) else [int(rng.integers(-9, 10)), int(rng.integers(-9, 10)), 1]
+            curves.append([univariate_product(h, row) for row in F])
+    return curves
+
+
 def sqfree_request(rng, degs=(120, 60, 30), bits=8, content=-6):
     """Square-free factorisation input a = content * prod_i f_i^i with monic
     random f_i of the given degrees (coefficients uniform signed `bits`-bit),

@@ -428,10 +428,37 @@ def test_fastlift_q(snc, name, f):
     assert snc.fastlift_q(f) == want
 
 
-def test_fastlift_q_y_factor_unsupported(snc):
-    """f = (y - x)^2 (y + 1): f_x and f_y share y - x; the library reports the
-    bivariate gcd it does not have instead of a wrong Q."""
-    f = [[0, 0, 1], [0, -2, 1], [1, -2], [1]]  # (y^2 - 2xy + x^2)(y + 1), rows in y
-    with pytest.raises(snc.SncError) as e:
-        snc.fastlift_q(f)
-    assert e.value.status == snc.SNC_ENOTSUP
+def _fastlift_y_cases():
+    """Curves whose f_x and f_y share a factor that depends on y."""
+    rng = np.random.default_rng(43)
+    cases = [("square_y_minus_x", [[0, 0, 1], [0, -2, 1], [1, -2], [1]])]  # (y - x)^2 (y + 1)
+
+    def bi(rows):
+        return [[int(c) for c in r] for r in rows]
+
+    g = [[1, -2], [3]]                       # 3y - 2x + 1
+    k = bi(synth.dense_bivariate(rng, 2, bits=5))
+    cases.append(("square_times_random", bi(synth.bivariate_product(synth.bivariate_product(g, g), k))))
+    g3 = [[0, 1], [2], [1]]                  # y^2 + 2y + x
+    cases.append(("cube", bi(synth.bivariate_product(synth.bivariate_product(g3, g3), g3))))
+    # x^2 (y - x^2)^2 (y^2 + 5): the shared factor carries a content in x
+    a = [[0, 0, -1], [1]]
+    f = synth.bivariate_product(synth.bivariate_product(a, a), [[5], [0], [1]])
+    cases.append(("content_and_square", bi([zx.mul([0, 0, 1], [int(c) for c in r]) for r in f])))
+    # a 40-bit square factor times a random cubic
+    g4 = [[int(c) for c in synth.uniform_signed(rng, (3,), 40)], [int(c) for c in synth.uniform_signed(rng, (2,), 40)],
+          [1]]
+    k4 = bi(synth.dense_bivariate(rng, 3, bits=8))
+    cases.append(("square_40bit", bi(synth.bivariate_product(synth.bivariate_product(g4, g4), k4))))
+    return cases
+
+
+@pytest.mark.parametrize("name,f", _fastlift_y_cases(), ids=[c[0] for c in _fastlift_y_cases()])
+def test_fastlift_q_y_factor(snc, name, f):
+    """h = gcd(f_x, f_y) depending on y: the library's bivariate modular gcd
+    (images per (prime, point) on the device, interpolation and Chinese
+    remaindering, exact division) gives the oracle's Q."""
+    from oracle import fastlift as FL
+    want, h = FL.fastlift_q(f)
+    assert len(h) > 1  # h depends on y
+    assert snc.fastlift_q(f) == want
