@@ -291,7 +291,8 @@ def batch_stage_roofline(snc, pairs, plans, stages, ceilings, workload_tag):
     src_res = "paper_1103_4697_amd/csrc/kernels_res.hip"
     recs = {
         "eval_elim": roof("eval_elim (all register classes)", ee_ops, ee_ms,
-                          profiled_traffic("eval_elim", src_res, workload_tag), ceilings, ee_bytes),
+                          profiled_traffic("eval_elim", "paper_1103_4697_amd/csrc/eval_elim.hpp", workload_tag),
+                          ceilings, ee_bytes),
         "interp": roof("interp", ip_ops, stages.get("interp", float("nan")),
                        profiled_traffic("interp", src_res, workload_tag), ceilings, ip_bytes),
         "crt": roof("crt (all launches: digits and binary value)", crt_ops, crt_ms,
@@ -409,6 +410,36 @@ def curve_sets(snc, synth, ctx):
     return {"workload": "five random dense curves of total degree d with signed b-bit coefficients: "
                         "res_y(f, f_y) of each and res_y(f, h) of every pair (15 resultants) in one batch",
             "sets": sets}
+
+
+def arrangements(snc, synth, ctx):
+    """The projection phase of an arrangement of a curve set: contents of all
+    curves in one tree of batched gcds (at preparation), then res_y(p, p_y)
+    of every primitive part and res_y(p_i, p_j) of every pair as one batch."""
+    import numpy as np
+    import torch
+    out = {"workload": "sets of planar curves cycling through circles, ellipses, random dense curves of degree 3..8 "
+                       "(10-bit), graphs of rational functions and curves with a factor in x alone; n contents, "
+                       "then n + n(n-1)/2 resultants per run"}
+    for n in (20, 50):
+        curves = synth.arrangement_set(np.random.default_rng(3000 + n), n)
+        t0 = time.perf_counter()
+        A = snc.Arrangement(curves, ctx)
+        prep = time.perf_counter() - t0
+        A.run()
+        torch.cuda.synchronize()
+        nrep = 5
+        t0 = time.perf_counter()
+        for _ in range(nrep):
+            A.run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / nrep * 1e3
+        npairs = n + n * (n - 1) // 2
+        out[f"n{n}"] = {"resultants": npairs, "contents_and_primitive_parts_ms": round(prep * 1e3, 2),
+                        "run_ms": round(ms, 3), "resultants_per_s": round(npairs / (ms * 1e-3), 1)}
+        progress(f"arrangement of {n} curves: {npairs} resultants in {ms:.2f} ms")
+        A.close()
+    return out
 
 
 def timed(fn, nrep):
@@ -664,6 +695,16 @@ def main():
         q, qt = timed(lambda: snc.fastlift_q(f, ctx), 5)
         out["fastlift_q"] = {"workload": "Q = res_y(f_x / h, f_y / h), h = gcd(f_x, f_y), for the curve-analysis f",
                              "ms": round(qt * 1e3, 3), "deg_Q": len(q) - 1}
+        # a curve with a squared component: h = gcd(f_x, f_y) depends on y (bivariate modular gcd)
+        gsq = [[int(c) for c in row] for row in synth.dense_bivariate(np.random.default_rng(77), 4, bits=8)]
+        ksq = [[int(c) for c in row] for row in synth.dense_bivariate(np.random.default_rng(78), 6, bits=8)]
+        fsq = synth.bivariate_product(synth.bivariate_product(gsq, gsq), ksq)
+        q2, qt2 = timed(lambda: snc.fastlift_q(fsq, ctx), 3)
+        out["fastlift_q_y_factor"] = {"workload": "f = g^2 k with g, k random dense of total degrees 4 and 6 "
+                                                  "(8-bit): h = gcd(f_x, f_y) has y-degree 4 (bivariate modular gcd)",
+                                      "ms": round(qt2 * 1e3, 3), "deg_Q": len(q2) - 1}
+        progress("arrangements")
+        out["arrangements"] = arrangements(snc, synth, ctx)
         progress("square-free factorisation")
         a, want = synth.sqfree_request(np.random.default_rng(2024))
         got, st_ = timed(lambda: snc.sqfree_factor(a, ctx), 5)

@@ -129,15 +129,18 @@ __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* 
 constexpr int EL_NORMAL = 0, EL_ZERO = 1, EL_ABN = 2;
 
 // Check of a new remainder X (entries 0..C, top-aligned) after a step.
-// Lanes whose leading coefficient vanished scan the rest of it; on a
-// normal step the test is one comparison.
+// Lanes whose leading coefficient vanished scan the rest of it.  The scan
+// sits behind a wavefront-uniform branch (a ballot of those lanes), which is
+// almost never taken: a leading coefficient vanishes with probability about
+// 1/p per step, so a normal step costs one comparison and no scan.
 template <int N, int C>
 __device__ __forceinline__ void lead_check(const uint32_t (&X)[N + 1], int& st, const PrimeC& c) {
-  if (canon(X[0], c.p) == 0 && st == EL_NORMAL) {
+  const bool z = canon(X[0], c.p) == 0 && st == EL_NORMAL;
+  if (__builtin_amdgcn_ballot_w64(z)) {
     uint32_t nz = 0;
 #pragma unroll
     for (int i = 1; i <= C; ++i) nz |= canon(X[i], c.p);
-    st = nz ? EL_ABN : EL_ZERO;
+    if (z) st = nz ? EL_ABN : EL_ZERO;
   }
 }
 
