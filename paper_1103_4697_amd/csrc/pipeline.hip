@@ -72,8 +72,14 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   lay.pref_interp_blk = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtd = off; off = align256(off + 8 * (NJ + 1));
   lay.pref_crtc = off; off = align256(off + 8 * (NJ + 1));
+  // one lane per coefficient pays off only when the batch's few-prime coefficients fill the device
+  // (a wavefront per CU); otherwise the lanes go over the primes of each coefficient
+  int64_t small_coefs = 0;
+  for (int j = 0; j < NJ; ++j)
+    if (crt_small_class(plans[lay.dev[j]].k) >= 0) small_coefs += plans[lay.dev[j]].D + 1;
+  lay.crt_small_on = small_coefs >= CRT_SMALL_MIN_COEFS;
   for (int j = 0; j < NJ; ++j) {
-    const int cc = crt_small_class(plans[lay.dev[j]].k);
+    const int cc = lay.crt_small_on ? crt_small_class(plans[lay.dev[j]].k) : -1;
     if (cc >= 0) lay.n_crts_jobs[cc]++; else lay.n_crtb_jobs++;
   }
   for (int c = 0; c < NCRT_SMALL; ++c) {
@@ -122,7 +128,7 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.nb_red += (int64_t)P.k * ((P.T + 255) / 256);
     lay.nb_interp += P.k;
     lay.nb_interp_blk += (int64_t)P.k * ((n1 + 63) / 64);
-    const int cc = crt_small_class(P.k);
+    const int cc = lay.crt_small_on ? crt_small_class(P.k) : -1;
     if (cc >= 0) {
       lay.nb_crts[cc] += (int64_t)((n1 + 63) / 64);
     } else {
@@ -346,7 +352,7 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
     pr[j + 1] = pr[j] + (int64_t)P.k * ((P.T + 255) / 256);
     pi[j + 1] = pi[j] + P.k;
     pib[j + 1] = pib[j] + (int64_t)P.k * ((P.D + 1 + 63) / 64);
-    const int cc = crt_small_class(P.k);
+    const int cc = lay.crt_small_on ? crt_small_class(P.k) : -1;
     if (cc >= 0) {
       ls[cc][ns[cc]] = j;
       ps[cc][ns[cc] + 1] = ps[cc][ns[cc]] + (n1 + 63) / 64;

@@ -62,6 +62,7 @@ struct BatchLayout {
   size_t pref_crts[NCRT_SMALL] = {0}, list_crts[NCRT_SMALL] = {0}, list_crtb = 0;  // bytes
   int64_t nb_crts[NCRT_SMALL] = {0};
   int n_crts_jobs[NCRT_SMALL] = {0}, n_crtb_jobs = 0;
+  bool crt_small_on = false;         // the few-prime jobs take k_crt_small (enough coefficients)
   EEVariant ee_var[NCLS];            // launch variant of each register class (autotuner, or the defaults)
   size_t ee_counter_off = 0;         // bytes: the NCLS work counters of persistent evaluation launches
   size_t header_bytes = 0;

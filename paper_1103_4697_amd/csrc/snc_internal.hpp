@@ -172,6 +172,7 @@ void launch_crt_combine(const CrtTables& tb, const ResJob* jobs_d, const int32_t
 // the modulus table: one lane per coefficient (digits and binary value in one
 // kernel); blocks of 64 coefficients, prefix over the launch's jobs
 constexpr int NCRT_SMALL = 3;
+constexpr int64_t CRT_SMALL_MIN_COEFS = 64 * 256;  // a wavefront per CU
 constexpr int CRT_SMALL_K[NCRT_SMALL] = {32, 64, 128};
 inline int crt_small_class(int k) {
   for (int c = 0; c < NCRT_SMALL; ++c)
