@@ -55,6 +55,10 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} not found: build it with python -m paper_1103_4697_amd.build")
+            # torch's HIP runtime libraries first: the library then binds to the
+            # same runtime (identical sonames) instead of loading the system
+            # copy, which would leave one of the two without a visible device
+            import torch  # noqa: F401
             L = C.CDLL(LIB_PATH)
             P, I32, SZ, VP = C.POINTER, C.c_int32, C.c_size_t, C.c_void_p
             sig = {

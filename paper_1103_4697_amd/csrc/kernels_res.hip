@@ -265,8 +265,31 @@ __global__ void k_ifact_init() {
 
 void launch_ffact_init(hipStream_t s);
 
+// Montgomery coefficients of x^0 .. x^63 of F_j = (x - 64j)(x - 64j - 1) ... (x - 64j - 63)
+// (x^64 implied) for every prime and the blocks j < IW_NBLK of the one-wavefront interpolation
+constexpr int IW_NBLK = (IW_MAXD + 1) / 64;
+static_assert(64 * IW_NBLK == IW_MAXD + 1, "whole blocks");
+__device__ uint32_t g_fblk[(int64_t)KMAX * IW_NBLK * 64];
+
+__device__ __forceinline__ uint32_t lane_shr1(uint32_t v);
+
+// one wavefront per (prime, block): F <- F (x - (64 j + t)) for t = 0..63,
+// coefficient of x^lane in lane (the x^64 term leaves lane 63 and is implied)
+__global__ __launch_bounds__(64) void k_fblk_init() {
+  const int pi = blockIdx.x / IW_NBLK, j = blockIdx.x % IW_NBLK, lane = threadIdx.x;
+  const PrimeC c = g_primes[pi];
+  uint32_t f = lane == 0 ? c.r1 : 0u;
+  for (int t = 0; t < 64; ++t) {
+    const uint32_t nk = to_mont(c.p - (uint32_t)(64 * j + t), c);  // -(64 j + t)
+    const uint32_t fprev = lane_shr1(f);
+    f = canon(redc((uint64_t)nk * f + ((uint64_t)fprev << 32), c.p, c.pinv), c.p);
+  }
+  g_fblk[((int64_t)pi * IW_NBLK + j) * 64 + lane] = f;
+}
+
 void launch_ifact_init(hipStream_t s) {
   hipLaunchKernelGGL(k_ifact_init, dim3(KMAX / 64), dim3(64), 0, s);
+  hipLaunchKernelGGL(k_fblk_init, dim3(KMAX * IW_NBLK), dim3(64), 0, s);
   launch_ffact_init(s);
 }
 
@@ -382,6 +405,145 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
     dP = dN;
   }
   for (int t = tid; t < n1; t += INTERP_THREADS) C[t] = from_mont(Pa[IPAD + t], c);
+}
+
+// ---------------------------------------------------------------------------
+// One-wavefront interpolation (batches with many (resultant, prime) pairs and
+// degree bounds up to IW_MAXD): the same Newton convolution, Newton blocks and
+// blockwise expansion as k_interp, by one wavefront per (resultant, prime)
+// with no barriers between wavefronts.  LDS holds only the sliding operand:
+// w_j = (-1)^j / j! for the convolution, then P, updated in place from its top
+// block down (a block's new values depend on its own and the next lower
+// block's old ones).  The uniform operand is a register broadcast by
+// readlane, shared by two output blocks; the Newton blocks Q_j go to the
+// workspace, the F_j come from their table.
+// ---------------------------------------------------------------------------
+// s1 += sum_q u_q S1[-q], and (TWO) s2 += sum_q u_q S2[-q], u_q = lane q of u.
+// One reduction per 8 canonical products: their sum stays below 8 p^2, so
+// REDC's sum below 8 p^2 + 2^32 p < 2^64 and its result below 3p, and
+// s + REDC below 4p < 2^32 (16 products could exceed both bounds).
+template <bool TWO>
+__device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, uint32_t u, const uint32_t* S1,
+                                             const uint32_t* S2, const PrimeC& c) {
+#pragma unroll
+  for (int g = 0; g < 64; g += 8) {
+    uint64_t a1 = 0, a2 = 0;
+#pragma unroll
+    for (int q = g; q < g + 8; ++q) {
+      const uint64_t w = bcast(u, q);
+      a1 += w * S1[-q];
+      if constexpr (TWO) a2 += w * S2[-q];
+    }
+    s1 = canon(s1 + redc(a1, c.p, c.pinv), c.p);
+    if constexpr (TWO) s2 = canon(s2 + redc(a2, c.p, c.pinv), c.p);
+  }
+}
+
+// Newton block -> monomial: Q = sum_{s < len} a_{b0+s} prod_{t < s} (x - (b0 + t)), a_{b0+s} in lane s
+__device__ __forceinline__ uint32_t newton_block(uint32_t a, int b0, int len, int lane, const PrimeC& c) {
+  const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
+  uint32_t q = lane == 0 ? bcast(a, len - 1) : 0u;
+  for (int st = 0; st + 1 < len; ++st) {
+    const int kq = len - 2 - st;  // Q <- Q (x - (b0 + kq)) + a_{b0 + kq}
+    const uint32_t add = bcast(a, kq);
+    const uint32_t qprev = lane_shr1(q) + (lane == 0 ? add : 0u);
+    q = canon(redc((uint64_t)bcast(nk, kq) * q + ((uint64_t)qprev << 32), c.p, c.pinv), c.p);
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
+                                                 int njobs, uint32_t* ws, uint32_t* zero_word) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
+  extern __shared__ uint32_t S[];  // [IPAD + Dp]
+  const int64_t b = blockIdx.x;
+  const int jj = find_job(prefix, njobs, b);
+  const ResJob J = jobs[job_list[jj]];
+  const int pi = (int)(b - prefix[jj]);
+  const PrimeC c = g_primes[pi];
+  const int n1 = J.D + 1;
+  const int nblk = (n1 + 63) / 64;
+  const int Dp = nblk * 64;
+  const uint32_t* V = ws + J.pts_off + (int64_t)pi * n1;
+  uint32_t* C = ws + J.val_off + (int64_t)pi * n1;
+  uint32_t* Qg = ws + J.nq_off + (int64_t)pi * Dp;
+  const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
+  const uint32_t* FB = g_fblk + (int64_t)pi * IW_NBLK * 64;
+  const int lane = threadIdx.x;
+  for (int t = lane; t < IPAD + Dp; t += 64) {
+    const int j = t - IPAD;
+    uint32_t w = 0;
+    if (j >= 0 && j < n1) {
+      const uint32_t f = IF[j];
+      w = (j & 1) ? mneg(f, c.p) : f;
+    }
+    S[t] = w;
+  }
+  __syncthreads();
+  auto uval = [&](int ib) {  // u_{64 ib + lane} = v / (64 ib + lane)!
+    const int i = 64 * ib + lane;
+    return i < n1 ? mmulc(canon(V[i], c.p), IF[i], c.p, c.pinv) : 0u;
+  };
+  for (int ob = 0; ob < nblk; ob += 2) {
+    const int b0 = ob * 64;
+    const uint32_t* w1 = S + IPAD + b0 + lane;
+    uint32_t s1 = 0, s2 = 0;
+    if (ob + 1 < nblk) {
+      for (int ib = 0; ib <= ob; ++ib) toeplitz64_w<true>(s1, s2, uval(ib), w1 - 64 * ib, w1 + 64 - 64 * ib, c);
+      uint32_t dummy = 0;
+      toeplitz64_w<false>(s2, dummy, uval(ob + 1), w1 - 64 * ob, w1, c);
+      Qg[b0 + lane] = newton_block(s1, b0, 64, lane, c);
+      Qg[b0 + 64 + lane] = newton_block(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c);
+    } else {
+      uint32_t dummy = 0;
+      for (int ib = 0; ib <= ob; ++ib) toeplitz64_w<false>(s1, dummy, uval(ib), w1 - 64 * ib, w1, c);
+      Qg[b0 + lane] = newton_block(s1, b0, min(64, n1 - b0), lane, c);
+    }
+  }
+  __syncthreads();
+  // P = Q_{nblk-1}; P <- P F_j + Q_j for j = nblk-2 .. 0, in place from the top block down
+  const int lastb = (nblk - 1) * 64;
+  const int lastlen = n1 - lastb;
+  for (int t = lane; t < IPAD + Dp; t += 64) {
+    const int x = t - IPAD;
+    S[t] = (x >= 0 && x < lastlen) ? Qg[lastb + x] : 0u;
+  }
+  __syncthreads();
+  int dP = lastlen - 1;
+  for (int j = nblk - 2; j >= 0; --j) {
+    const int dN = dP + 64;
+    const int nob = dN / 64 + 1;
+    const uint32_t fj = FB[j * 64 + lane];
+    const uint32_t qj = Qg[j * 64 + lane];
+    for (int ob = nob - 1; ob >= 0; ob -= 2) {
+      const uint32_t* p1 = S + IPAD + ob * 64 + lane;  // P[t - i] = p1[-i]
+      uint32_t s1 = p1[-64];                            // x^64 term of F_j
+      if (ob == 0) s1 = madd(s1, qj, c.p);
+      uint32_t s2 = 0;
+      if (ob >= 1) {
+        s2 = p1[-128];
+        if (ob == 1) s2 = madd(s2, qj, c.p);
+        toeplitz64_w<true>(s1, s2, fj, p1, p1 - 64, c);
+      } else {
+        uint32_t dummy = 0;
+        toeplitz64_w<false>(s1, dummy, fj, p1, p1, c);
+      }
+      __syncthreads();  // every lane's reads of the old blocks before the new values land
+      S[IPAD + ob * 64 + lane] = s1;
+      if (ob >= 1) S[IPAD + (ob - 1) * 64 + lane] = s2;
+      __syncthreads();
+    }
+    dP = dN;
+  }
+  for (int t = lane; t < n1; t += 64) C[t] = from_mont(S[IPAD + t], c);
+}
+
+void launch_interp_w(const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
+                     int64_t nblocks, int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s) {
+  if (nblocks <= 0) return;
+  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_interp_w, dim3((unsigned)nblocks), dim3(64), lds, s, jobs_d, job_list_d, prefix_d, njobs,
+                     ws, zero_word);
 }
 
 // ---------------------------------------------------------------------------

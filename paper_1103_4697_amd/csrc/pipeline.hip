@@ -88,6 +88,8 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
   }
   lay.list_crtb = off; off = align256(off + 4 * std::max(lay.n_crtb_jobs, 1));
   lay.pref_inst = off; off = align256(off + 8 * (NJ + 1));
+  lay.pref_iw = off; off = align256(off + 8 * (NJ + 1));
+  lay.list_iw = off; off = align256(off + 4 * std::max(NJ, 1));
   for (int j = 0; j < NJ; ++j) {
     const ResPlan& P = plans[lay.dev[j]];
     if (P.cls >= 0) lay.n_ee_jobs[P.cls]++; else lay.n_gen_jobs++;
@@ -145,6 +147,10 @@ void layout_batch(const std::vector<ResPlan>& plans, BatchLayout& lay) {
     lay.max_D = std::max(lay.max_D, P.D);
   }
   lay.interp_blk = NJ > 0 && interp_blk_fits(lay.max_D, lay.max_k);
+  // many (resultant, prime) pairs: one wavefront each, no barriers between wavefronts
+  int64_t npairs = 0;
+  for (const ResJob& J : lay.jobs) npairs += J.k;
+  lay.interp_w = NJ > 0 && !lay.interp_blk && lay.max_D <= IW_MAXD && npairs >= IW_MIN_PAIRS;
   // every job on the evaluation kernel's LDS variant: it reduces the inputs itself
   lay.reduce_in_eval = NJ > 0 && lay.n_gen_jobs == 0;
   for (int c = 0; c < NCLS; ++c)
@@ -241,6 +247,9 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   if (tm) tm->mark("elim_general", 1);
   if (lay.interp_blk)
     launch_interp_blk(jobs, (const int64_t*)(ws + lay.pref_interp_blk), NJ, lay.nb_interp_blk, wsw, abn_count, s);
+  else if (lay.interp_w)
+    launch_interp_w(jobs, (const int32_t*)(ws + lay.list_iw), (const int64_t*)(ws + lay.pref_iw), NJ, lay.nb_interp,
+                    lay.max_D, wsw, abn_count, s);
   else
     launch_interp(jobs, (const int64_t*)(ws + lay.pref_interp), NJ, lay.nb_interp, lay.max_D, wsw, abn_count, s);
   if (tm) tm->mark("interp", 1);
@@ -370,6 +379,20 @@ void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, cons
       lg[ng] = j;
       pg[ng + 1] = pg[ng] + (int64_t)P.k * n1;
       ng++;
+    }
+  }
+  // the one-wavefront interpolation's jobs by degree bound, largest first (the
+  // longest wavefronts start first)
+  {
+    std::vector<int> ord(NJ);
+    for (int j = 0; j < NJ; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lay.jobs[x].D > lay.jobs[y].D; });
+    int32_t* li = (int32_t*)(h + lay.list_iw);
+    int64_t* pw = (int64_t*)(h + lay.pref_iw);
+    pw[0] = 0;
+    for (int t = 0; t < NJ; ++t) {
+      li[t] = ord[t];
+      pw[t + 1] = pw[t] + lay.jobs[ord[t]].k;
     }
   }
   // a class's jobs most expensive first: a persistent launch hands out the

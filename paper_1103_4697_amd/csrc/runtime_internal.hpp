@@ -55,6 +55,8 @@ struct BatchLayout {
   size_t pref_interp_blk = 0;        // bytes: block prefix of the block-parallel interpolation
   size_t pref_inst = 0;              // bytes: instance prefix k (D+1) over the jobs
   bool interp_blk = false;           // every job fits the block-parallel interpolation
+  bool interp_w = false;             // one-wavefront interpolation (many (resultant, prime) pairs)
+  size_t pref_iw = 0, list_iw = 0;   // bytes: its job list (degree bound descending) and block prefix
   bool reduce_in_eval = false;       // the evaluation kernel reduces the inputs (no reduction launch)
   size_t pref_ee[NCLS] = {0}, list_ee[NCLS] = {0}, list_gen = 0;                   // bytes
   // Chinese remaindering: the small-prime classes (one lane per coefficient)

@@ -129,6 +129,12 @@ inline bool interp_blk_fits(int max_D, int max_k) { return max_D + 1 <= 64 * IFF
 void launch_interp_blk(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks, uint32_t* ws,
                        uint32_t* zero_word, hipStream_t s);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+// one-wavefront interpolation per (resultant, prime): degree bounds up to IW_MAXD, for batches with at
+// least IW_MIN_PAIRS (resultant, prime) pairs; jobs from job_list_d (prefix: k per job)
+constexpr int IW_MAXD = 4095;
+constexpr int64_t IW_MIN_PAIRS = 4096;
+void launch_interp_w(const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
+                     int64_t nblocks, int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s);
 // zero_word (may be null) is set to zero by the same launch
 void launch_reduce(const ResJob* jobs_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
                    const uint32_t* ws, uint32_t* res_base, uint32_t* zero_word, hipStream_t s);

@@ -308,7 +308,7 @@ def test_sqfree_check_large_degree(snc):
     assert stages["sqfree_full_gcd"] == 1          # only u^2 w needs the full gcd
     assert stages["sqfree_euclid"] > 0              # (pair, prime) items of the fused check
     batch.run_sqfree()                             # replay of the captured pipeline
-    assert batch.sqfree_results() == G_all
+    assert batch.sqfree_results() == G_all   # short lists of small polynomials
 
 
 def test_sqfree_factor_against_oracle(snc):

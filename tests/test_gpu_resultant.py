@@ -209,7 +209,7 @@ def test_largest_degree_bound(snc):
             assert zx.evaluate(r, x0) % q == R.resultant_at_mod(f, g, x0, q)
 
 
-def test_batch_matches_plain_and_oracle(snc):
+def test_batch_matches_plain_and_oracle(snc, assert_same):
     pairs, common = synth.config2(npairs=48, frac_common=0.1)
     batch = snc.resultant_y_batch(pairs)
     for i, (f, g) in enumerate(pairs):
@@ -227,10 +227,11 @@ def test_batch_matches_plain_and_oracle(snc):
     b.run()
     first = b.results()
     b.run()
-    assert b.results() == first == batch
+    assert_same(first, batch)
+    assert_same(b.results(), first)
 
 
-def test_config2_full_draw(snc):
+def test_config2_full_draw(snc, assert_same):
     """The batched workload exactly as it is timed: all 512 pairs of the
     seeded draw in one prepared batch.  The 51 planted common-factor pairs
     are exactly 0 and no other pair is; every pair equals its plain run;
@@ -246,7 +247,7 @@ def test_config2_full_draw(snc):
         assert (got[i] == []) == (i in common), i
     plain = snc.PlainResultants(pairs)
     plain.run()
-    assert plain.results() == got
+    assert_same(plain.results(), got)
     rng = random.Random(512)
     for i, (f, g) in enumerate(pairs):
         x0 = rng.randrange(Q61)
@@ -255,7 +256,7 @@ def test_config2_full_draw(snc):
     for i in cost[:3]:
         assert got[i] == R.resultant_y_by_points(*pairs[i], processes=1), i
     b.run()
-    assert b.results() == got   # a second replay of the captured graph
+    assert_same(b.results(), got)   # a second replay of the captured graph
 
 
 @pytest.mark.parametrize("da,db", [(63, 20), (64, 32), (1000, 500), (1023, 300), (1024, 512)])
@@ -334,7 +335,7 @@ def _class_spanning_pairs(seed):
     return pairs
 
 
-def test_eval_variants_identical(snc):
+def test_eval_variants_identical(snc, assert_same):
     """Every launch variant of the evaluation kernel the autotuner can pick
     (register budget for 1..4 wavefronts per SIMD; one workgroup per block
     or a persistent grid taking 1 or 4 blocks at a time) gives the same
@@ -360,7 +361,7 @@ def test_eval_variants_identical(snc):
             rep, _ = ctx.tuning()
             assert {e["source"] for e in rep} == {"forced"}
             assert all(e["wpe"] == wpe and e["chunk"] == chunk for e in rep)
-            assert got == ref, (wpe, chunk)
+            assert_same(got, ref, f"variant {(wpe, chunk)}")
     for cap in (16, 32, 48, 64):
         ctx.set_eval_variant(cap, 0, 0)
     # the prepared graph of a persistent variant replayed several times
@@ -369,13 +370,13 @@ def test_eval_variants_identical(snc):
     b = snc.ResultantBatch(pairs, ctx)
     for _ in range(3):
         b.run()
-        assert b.results() == ref
+        assert_same(b.results(), ref)
     b.close()
     for cap in (16, 32, 48, 64):
         ctx.set_eval_variant(cap, 0, 0)
 
 
-def test_autotuner_measures_and_caches(snc):
+def test_autotuner_measures_and_caches(snc, assert_same):
     """The autotuner times every candidate of each class the batch uses,
     keeps one no slower than the default, and a later preparation of the
     same shape reuses it from its table; results are unchanged."""
@@ -394,7 +395,7 @@ def test_autotuner_measures_and_caches(snc):
         assert 0.0 < e["best_ms"] <= e["default_ms"] + 1e-6
         assert 1 <= e["wpe"] <= 4 and e["chunk"] in (0, 1, 4)
     b.run()
-    assert b.results() == ref
+    assert_same(b.results(), ref)
     b.close()
     ctx.set_tuning(1)
     b2 = snc.ResultantBatch(pairs, ctx)
@@ -402,5 +403,26 @@ def test_autotuner_measures_and_caches(snc):
     assert {e["source"] for e in rep2} == {"cached"}
     assert [(e["wpe"], e["chunk"]) for e in rep2] == [(e["wpe"], e["chunk"]) for e in rep]
     b2.run()
-    assert b2.results() == ref
+    assert_same(b2.results(), ref)
     b2.close()
+
+
+def test_one_wavefront_interpolation_batch(snc, assert_same):
+    """A batch with more than 4096 (pair, prime) instances and degree bounds
+    below 4096 takes the one-wavefront interpolation (in place from the top
+    block down); every result equals the single-pair call, which
+    interpolates with the workgroup kernels.  Degree bounds 63 and 64 sit on
+    the 64-point block boundary, 1600 is the largest."""
+    rng = np.random.default_rng(8811)
+    shapes = [(7, 9, 12, 12), (8, 8, 16, 16), (9, 7, 20, 8), (16, 8, 30, 30), (8, 16, 30, 30), (31, 33, 24, 24),
+              (40, 40, 32, 32), (20, 25, 32, 32)]
+    pairs = [synth.random_pair(rng, *sh) for sh in shapes]
+    while sum(snc.resultant_plan(f, g).nprimes for f, g in pairs) < 4300:
+        df, dg = int(rng.integers(8, 41)), int(rng.integers(8, 41))
+        pairs.append(synth.random_pair(rng, df, dg, int(rng.integers(8, 33)), int(rng.integers(8, 33))))
+    got = snc.resultant_y_batch(pairs)
+    assert_same(got, [snc.resultant_y(f, g) for f, g in pairs])
+    qr = random.Random(8812)
+    f, g = pairs[6]
+    x0 = qr.randrange(Q61)
+    assert zx.evaluate(got[6], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
