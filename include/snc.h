@@ -224,6 +224,24 @@ int snc_prepared_sqfree_plan(const snc_prepared* prep, snc_plan* gcd_each, snc_p
 int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, void* stream, snc_upoly* R,
                             snc_upoly* G);
 
+/* The Euclid of the square-free check (Section 2.1, gcd(R, R') mod p for
+ * each of the resultant's primes; Section 4, "Symbolic Speedups").
+ * snc_set_gcd_variant: 0 = automatic (one wavefront per (pair, prime), the
+ * faster of the two on gfx950), 1 = one wavefront, 2 = the blocked Euclid
+ * where the resultant degree needs 6, 9, 12 or 16 register slots per lane
+ * (a workgroup of eight wavefronts per (pair, prime): a leading wavefront
+ * decides blocks of up to 31 steps from the top 64 coefficients, another
+ * accumulates each block's 2x2 polynomial matrix, the others apply the
+ * previous block's matrix to the full remainders).  The variants give
+ * identical degrees.  snc_prepared_sqfree_degrees: after snc_prepared_run_sqfree, for
+ * pair `pair` and the first min(k, cap) of its k primes (the resultant's,
+ * snc_prime(0), snc_prime(1), ...): d[q] = deg (R mod p_q) and e[q] = deg
+ * gcd(R mod p_q, R' mod p_q) (-1 when R = 0 mod p_q; -2 marks a result to be
+ * ignored).  Returns k (0 for a pair without a Euclid: trivial, or deg R < 1),
+ * SNC_EINVAL before the first projection step or for a bad argument. */
+int snc_set_gcd_variant(snc_ctx* ctx, int variant);
+int snc_prepared_sqfree_degrees(const snc_prepared* prep, int pair, int32_t* d, int32_t* e, int cap);
+
 /* Square-free factorisation (Section 2.1: R's square-free part and the
  * multiplicities of its real roots come from Yun's algorithm on R):
  *   a = content * prod_i f_i^{m_i},

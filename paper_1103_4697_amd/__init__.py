@@ -72,6 +72,8 @@ def lib():
                 "snc_microbench": (C.c_int, [VP, C.c_int, I32, VP, SZ, VP, P(C.c_double)]),
                 "snc_set_tuning": (C.c_int, [VP, C.c_int]),
                 "snc_set_eval_variant": (C.c_int, [VP, I32, I32, I32]),
+                "snc_set_gcd_variant": (C.c_int, [VP, C.c_int]),
+                "snc_prepared_sqfree_degrees": (C.c_int, [VP, C.c_int, P(I32), P(I32), C.c_int]),
                 "snc_get_tuning": (C.c_int, [VP, P(I32), P(C.c_float), C.c_int, P(C.c_float)]),
                 "snc_prime": (C.c_uint32, [I32]),
                 "snc_resultant_y_plan": (C.c_int, [P(Bipoly), P(Bipoly), P(Plan)]),
@@ -288,6 +290,12 @@ class Context:
         """Evaluation autotuner: 0 off, 1 tune untuned classes (default), 2 retune."""
         self.check(lib().snc_set_tuning(self.h, mode), "snc_set_tuning")
 
+    def set_gcd_variant(self, variant: int):
+        """Euclid of the square-free check: 0 automatic, 1 one wavefront per
+        (pair, prime), 2 the blocked Euclid (a workgroup per (pair, prime))
+        wherever it applies (snc_set_gcd_variant)."""
+        self.check(lib().snc_set_gcd_variant(self.h, variant), "snc_set_gcd_variant")
+
     def set_eval_variant(self, class_cap: int, wpe: int, chunk: int = 0):
         """Force the evaluation kernel variant of a register class (wpe 0 clears)."""
         self.check(lib().snc_set_eval_variant(self.h, class_cap, wpe, chunk), "snc_set_eval_variant")
@@ -450,6 +458,20 @@ class ResultantBatch:
 
     def degrees(self):
         return [self.out[i].deg for i in range(self.n)]
+
+    def sqfree_degrees(self, i: int):
+        """After run_sqfree: (d, e) for pair i over its primes, d[q] = deg R
+        mod p_q and e[q] = deg gcd(R, R') mod p_q (snc_prepared_sqfree_degrees)."""
+        k = lib().snc_prepared_sqfree_degrees(self.h, i, None, None, 0)
+        if k < 0:
+            raise SncError(k, "snc_prepared_sqfree_degrees")
+        d = (C.c_int32 * max(k, 1))()
+        e = (C.c_int32 * max(k, 1))()
+        if k:
+            st = lib().snc_prepared_sqfree_degrees(self.h, i, d, e, k)
+            if st < 0:
+                raise SncError(st, "snc_prepared_sqfree_degrees")
+        return list(d)[:k], list(e)[:k]
 
     def results(self):
         return [_read_upoly(self.out[i], self.bufs[i]) for i in range(self.n)]

@@ -1102,15 +1102,17 @@ static int sqfree_setup(snc_prepared* pr, const SqfreeLayout& S, hipStream_t str
   return SNC_OK;
 }
 
+// the projection step's layout and per-pair bounds, made on its first run
+struct SqCache {
+  SqfreeLayout S;
+  std::vector<Quick> B;
+};
+
 int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStream_t stream, snc_upoly* R,
                         snc_upoly* Gout) {
   snc_ctx* ctx = pr->c;
   const int n = pr->n;
   const BatchLayout& lay = pr->lay;
-  struct SqCache {
-    SqfreeLayout S;
-    std::vector<Quick> B;
-  };
   if (!pr->sq_cache) {
     auto sc = std::make_shared<SqCache>();
     sqfree_layout(pr, sc->S, &sc->B);
@@ -1159,8 +1161,12 @@ int run_prepared_sqfree(snc_prepared* pr, void* d_gws, size_t gws_bytes, hipStre
     const int32_t* items_d = (const int32_t*)(ws + base + S.items);
     if (timing) HIPCHK(hipEventRecord(t0, s));
     for (size_t r = 0; r < pr->sq_ranges.size(); r += 4) {
-      const int* q = &pr->sq_ranges[r];
-      launch_gcd_euclid(descs_d, items_d + 2 * q[1], q[2], q[0], q[3], ws, s);
+      const int* q = &pr->sq_ranges[r];  // register class, first item, items, largest degree
+      const bool blocked = ctx->gcd_variant == 2 && gcd_lehmer_class(q[0]);
+      if (blocked)
+        launch_gcd_lehmer(descs_d, items_d + 2 * q[1], q[2], q[0], ws, s);
+      else
+        launch_gcd_euclid(descs_d, items_d + 2 * q[1], q[2], q[0], q[3], ws, s);
     }
     HIPCHK(hipGetLastError());
     if (timing) HIPCHK(hipEventRecord(t1, s));
@@ -2157,6 +2163,25 @@ int snc_prepared_run_sqfree(snc_prepared* prep, void* d_gws, size_t gws_bytes, v
                             snc_upoly* G) {
   if (!prep || !R || !G) return SNC_EINVAL;
   return run_prepared_sqfree(prep, d_gws, gws_bytes, (hipStream_t)stream, R, G);
+}
+
+int snc_prepared_sqfree_degrees(const snc_prepared* prep, int pair, int32_t* d, int32_t* e, int cap) {
+  if (!prep || pair < 0 || pair >= prep->n || cap < 0 || (cap > 0 && (!d || !e))) return SNC_EINVAL;
+  if (!prep->sq_cache || !prep->h_ed) return SNC_EINVAL;  // no projection step has run
+  const SqfreeLayout& S = static_cast<const SqCache*>(prep->sq_cache.get())->S;
+  const BatchLayout& lay = prep->lay;
+  for (int j = 0; j < (int)lay.dev.size(); ++j) {
+    if (lay.dev[j] != pair) continue;
+    const ResJob& J = lay.jobs[j];
+    if (J.D < 1) return 0;
+    const int32_t* ed = (const int32_t*)prep->h_ed;
+    for (int q = 0; q < std::min(J.k, cap); ++q) {
+      e[q] = ed[S.job_base[j] + q];
+      d[q] = ed[(S.d - S.e) + S.job_base[j] + q];
+    }
+    return J.k;
+  }
+  return 0;  // a trivial pair: no Euclid
 }
 
 int snc_gcd_z_deriv_plan(const snc_upoly* a, snc_plan* out) {

@@ -315,6 +315,12 @@ int snc_set_tuning(snc_ctx* c, int mode) {
   return SNC_OK;
 }
 
+int snc_set_gcd_variant(snc_ctx* c, int variant) {
+  if (!c || variant < 0 || variant > 2) return SNC_EINVAL;
+  c->gcd_variant = variant;
+  return SNC_OK;
+}
+
 int snc_set_eval_variant(snc_ctx* c, int32_t class_cap, int32_t wpe, int32_t chunk) {
   if (!c) return SNC_EINVAL;
   const int cls = fast_class_of(class_cap);

@@ -105,6 +105,7 @@ struct snc_ctx {
   bool timing = false;
   // evaluation autotuner: 0 off (defaults, cache lookups only), 1 tune classes the cache lacks, 2 retune
   int tune_mode = 1;
+  int gcd_variant = 0;  // Euclid of the square-free check: 0 automatic (one wavefront), 1 one wavefront, 2 blocked
   snc::EEVariant forced[snc::NCLS];  // wpe > 0: variant forced for every launch of that class (0: none)
   std::vector<EETuneReport> tune_report;  // the last batched preparation's choices
   float tune_ms = 0.f;                    // host wall time spent tuning in that preparation

@@ -202,6 +202,12 @@ void launch_gcd_euclid(const GcdDesc* descs, const int32_t* items, int nitems, i
 void launch_gcd_gather(const GcdDesc& G, const int32_t* sel_d, const uint32_t* scales_d, const PrimeC* sprimes_d,
                        int ks, int e, uint32_t* ws, int64_t wv, int64_t uv, int64_t vv, hipStream_t s);
 hipError_t configure_gcd_kernels();
+// blocked Euclid of the square-free check (a workgroup of eight wavefronts per
+// (problem, prime), fused descriptors only) for the register classes 6, 9, 12, 16
+bool gcd_lehmer_class(int slots);
+size_t gcd_lehmer_lds_bytes(int slots);
+void launch_gcd_lehmer(const GcdDesc* descs, const int32_t* items, int nitems, int slots, uint32_t* ws,
+                       hipStream_t s);
 
 // Per-(prime, point) images of a bivariate gcd (k_ygcd): A and B (rows in y
 // of polynomials in x, dense rectangles of residues) evaluated at

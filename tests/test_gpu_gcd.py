@@ -462,3 +462,52 @@ def test_fastlift_q_y_factor(snc, name, f):
     want, h = FL.fastlift_q(f)
     assert len(h) > 1  # h depends on y
     assert snc.fastlift_q(f) == want
+
+
+def test_blocked_euclid_matches_one_wavefront(snc, assert_same):
+    """The square-free check's Euclid as a workgroup per (pair, prime) (blocks
+    of up to 31 normal steps decided from the top 64 coefficients, each
+    block's 2x2 polynomial matrix applied to the full remainders) against one
+    wavefront per (pair, prime): identical d = deg R mod p and e = deg gcd(R,
+    R') mod p for every prime, in the four register classes it serves
+    (resultant degrees 300, 552, 700, 1000), for square-free resultants,
+    repeated factors of degree 20 and 100 (the zero remainder arrives inside a
+    block), a leading coefficient divisible by the first prime, and x^552 + 5
+    (the first remainder is a constant); e and d equal the oracle's on sampled
+    primes, and the gcds agree."""
+    rng = random.Random(31)
+
+    def rand_poly(n, bits=24):
+        return [rng.randint(-(1 << bits), 1 << bits) for _ in range(n)] + [rng.choice((-1, 1)) * rng.randint(1, 99)]
+
+    cases = [rand_poly(d) for d in (300, 552, 700, 1000)]
+    u20, u100 = rand_poly(20, 8), rand_poly(100, 8)
+    cases.append(zx.mul(zx.mul(u20, u20), rand_poly(512, 8)))
+    cases.append(zx.mul(zx.mul(u100, u100), rand_poly(350, 8)))
+    lead_div = rand_poly(552)
+    lead_div[-1] = snc.prime(0) * 3
+    cases.append(lead_div)
+    cases.append([5] + [0] * 551 + [1])
+    pairs = [_sq_pair(r, [0]) for r in cases]
+    batch = snc.ResultantBatch(pairs)
+    ctx = batch.ctx
+    got = {}
+    try:
+        for v in (1, 2):
+            ctx.set_gcd_variant(v)
+            batch.run_sqfree()
+            got[v] = ([batch.sqfree_degrees(i) for i in range(len(pairs))], batch.sqfree_results())
+    finally:
+        ctx.set_gcd_variant(0)
+    assert_same(got[2][0], got[1][0], "per-prime (d, e)")
+    assert_same(got[2][1], got[1][1], "gcds")
+    for i, r in enumerate(cases):
+        d, e = got[2][0][i]
+        assert len(d) == len(e) > 0
+        for q in sorted(set(rng.sample(range(len(e)), min(3, len(e))) + [0])):
+            p = snc.prime(q)
+            rp = zx.trim([c % p for c in r])
+            assert d[q] == len(rp) - 1, (i, q)
+            assert e[q] == G._gcd_mod_degree(r, zx.deriv(r), p), (i, q)
+    assert max(got[2][0][4][1]) == 20 and max(got[2][0][5][1]) == 100
+    assert got[2][0][6][0][0] == 551      # the leading coefficient vanishes mod the first prime
