@@ -120,13 +120,21 @@ def pair_shape(f, g):
     return len(rf) - 1, len(rg) - 1, sum(rf) + sum(rg)
 
 
-def profiled_traffic(kernel: str, source: str, workload: str):
+def source_sha(source) -> str:
+    """sha256 of a kernel's source file, or of the concatenation of several."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in ((source,) if isinstance(source, str) else source):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel: str, source, workload: str):
     """HBM bytes per launch of a kernel on a workload from the committed
     counter summary (profiles/<kernel>_<workload>_counters.md: FETCH_SIZE +
     WRITE_SIZE scaled by a copy of known size), or None when there is none
-    or the kernel source changed since."""
-    import hashlib
-    sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    or the kernel source (one file or several) changed since."""
+    sha = source_sha(source)
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
@@ -375,7 +383,7 @@ def curve_analysis(snc, synth, ctx, nsteps):
     ee_ms = sum(v for kk, v in st.items() if kk.startswith("eval_elim"))
     eu_ops = gcd_euclid_lane_ops(d, d - 1) * eu_primes
     ee_ops = eval_elim_lane_ops(m, n, T) * k * (D + 1)
-    src_gcd = "paper_1103_4697_amd/csrc/kernels_gcd.hip"
+    src_gcd = ("paper_1103_4697_amd/csrc/kernels_gcd.hip", "paper_1103_4697_amd/csrc/gcd_reg.hpp")
     return {"workload": "curve-analysis projection: f dense total degree 24, uniform signed 16-bit "
                         "coefficients, g = df/dy; res_y then gcd(R, R') in one pass",
             "deg_bound": D, "primes": k, "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 2),
@@ -383,7 +391,7 @@ def curve_analysis(snc, synth, ctx, nsteps):
             "stage_ms": {kk: round(v, 4) for kk, v in st.items()},
             "euclid": roof("gcd_euclid", eu_ops, eu_ms, profiled_traffic("gcd_euclid", src_gcd, "curve_d552"), {}),
             "eval_elim": roof("eval_elim", ee_ops, ee_ms,
-                              profiled_traffic("eval_elim", "paper_1103_4697_amd/csrc/kernels_res.hip",
+                              profiled_traffic("eval_elim", "paper_1103_4697_amd/csrc/eval_elim.hpp",
                                                "curve_d552"), {})}
 
 

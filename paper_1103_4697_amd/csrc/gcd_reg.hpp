@@ -244,6 +244,21 @@ __device__ __forceinline__ int euclid_levels(uint32_t (&X)[E], int dX, uint32_t 
   }
 }
 
+// coefficients 0..deg of a residue row, top-aligned, through LDS: consecutive
+// lanes load consecutive words (each load instruction touches a few cache
+// lines instead of one per lane), then every lane takes its block of E
+template <int E>
+__device__ __forceinline__ void reg_load_staged(uint32_t (&X)[E], const uint32_t* row, int deg, uint32_t* sm, int lane) {
+  for (int t = lane; t <= deg; t += 64) sm[t] = row[t];
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int i = lane * E + s;
+    X[s] = i <= deg ? sm[deg - i] : 0u;
+  }
+  wave_sync();
+}
+
 // load coefficients 0..deg of a residue row (scaled by sc) top-aligned
 template <int E>
 __device__ __forceinline__ void reg_load(uint32_t (&X)[E], const uint32_t* row, int deg, int lane) {

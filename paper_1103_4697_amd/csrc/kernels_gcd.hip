@@ -160,8 +160,8 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd_modp(const GcdDesc* descs, 
 
 template <int E>
 __device__ __forceinline__ void reg_cofactor(uint32_t (&R)[E], const uint32_t (&G)[E], int e, const uint32_t* row,
-                                             int deg, uint32_t* q, int lane, const PrimeC& c) {
-  reg_load<E>(R, row, deg, lane);
+                                             int deg, uint32_t* q, uint32_t* sm, int lane, const PrimeC& c) {
+  reg_load_staged<E>(R, row, deg, sm, lane);
   for (int i = lane; i <= deg; i += 64) q[i] = 0u;
   const int dR = reg_trim<E>(R, deg, c);
   for (int t = dR - e; t >= 0; --t) {
@@ -186,16 +186,16 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   extern __shared__ uint32_t sm[];  // 2 * 64 * E words
   uint32_t X[E], Y[E], Gm[E];
   if (G.fused) {  // given residues of a (plain), b = a': element i of b is (da - i) times element i of a
-    const uint32_t* va = G.vals + (int64_t)slot * G.vstride;
+    reg_load_staged<E>(X, G.vals + (int64_t)slot * G.vstride, G.da, sm, lane);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const int i = lane * E + s;
-      X[s] = i <= G.da ? to_mont(va[G.da - i], c) : 0u;
+      X[s] = i <= G.da ? to_mont(X[s], c) : 0u;
       Y[s] = i <= G.db ? mmulc(X[s], to_mont((uint32_t)(G.da - i), c), c.p, c.pinv) : 0u;
     }
   } else {
-    reg_load<E>(X, ra, G.da, lane);
-    reg_load<E>(Y, rb, G.db, lane);
+    reg_load_staged<E>(X, ra, G.da, sm, lane);
+    reg_load_staged<E>(Y, rb, G.db, sm, lane);
   }
   const int dX = reg_trim<E>(X, G.da, c);
   const int dY = reg_trim<E>(Y, G.db, c);
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(64) void k_gcd_modp_reg(const GcdDesc* descs, const
   }
   uint32_t* u = ws + G.u_off + (int64_t)slot * (G.da + 1);
   uint32_t* v = ws + G.v_off + (int64_t)slot * (G.db + 1);
-  reg_cofactor<E>(X, Gm, e, ra, G.da, u, lane, c);
-  reg_cofactor<E>(X, Gm, e, rb, G.db, v, lane, c);
+  reg_cofactor<E>(X, Gm, e, ra, G.da, u, sm, lane, c);
+  reg_cofactor<E>(X, Gm, e, rb, G.db, v, sm, lane, c);
 }
 
 static const int kGcdE[] = {2, 4, 6, 9, 12, 16, 24, 32};
