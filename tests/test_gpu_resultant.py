@@ -237,7 +237,8 @@ def test_config2_full_draw(snc, assert_same):
     are exactly 0 and no other pair is; every pair equals its plain run;
     every pair agrees with the oracle's determinant modulo a 61-bit prime at
     a random point; the three cheapest pairs equal the oracle's resultant
-    coefficient by coefficient."""
+    coefficient by coefficient; the stage-by-stage run (timing on) gives the
+    same results as the graph."""
     pairs, common = synth.config2()
     assert len(pairs) == 512 and len(common) == 51
     b = snc.ResultantBatch(pairs)
@@ -257,6 +258,14 @@ def test_config2_full_draw(snc, assert_same):
         assert got[i] == R.resultant_y_by_points(*pairs[i], processes=1), i
     b.run()
     assert_same(b.results(), got)   # a second replay of the captured graph
+    # with stage timing on, the same launches go to the stream one by one
+    # between events instead of the captured graph: the same results
+    b.ctx.set_timing(True)
+    try:
+        b.run()
+        assert_same(b.results(), got)
+    finally:
+        b.ctx.set_timing(False)
 
 
 @pytest.mark.parametrize("da,db", [(63, 20), (64, 32), (1000, 500), (1023, 300), (1024, 512)])
