@@ -51,9 +51,12 @@ def eval_elim_lane_ops(m: int, n: int, T: int) -> int:
     coefficients (four 64-bit multiply-adds, low multiply, multiply-add);
     every normal remainder (the first one when deg A = deg B + 1, and all
     later ones) is one fused update of three products and one REDC, 5 per
-    coefficient of the new remainder; a first remainder with a larger degree
-    gap takes elementary steps, 4 per two-product update lc(Y) X_i -
-    lc(X) Y_i and 3 per scale-only update lc(Y) X_i."""
+    coefficient of the new remainder; a first remainder with another degree
+    gap takes s = m - n + 1 elementary steps, each an update of two products
+    and one REDC (4) on the n coefficients that meet B, plus 6 for the
+    entries above them, which are only scaled by lc(B): one coefficient
+    enters the updated part per step, scaled by the running power of lc(B)
+    (3), and that power takes one more product (3)."""
     ops = (3 * T) // 2
     if m < n:
         m, n = n, m
@@ -62,10 +65,7 @@ def eval_elim_lane_ops(m: int, n: int, T: int) -> int:
     if m == n + 1:
         ops += 5 * n
     else:
-        dX = m
-        for _ in range(m - n + 1):
-            ops += 4 * n + 3 * (dX - n)
-            dX -= 1
+        ops += (m - n + 1) * (4 * n + 6)
     b = n - 1
     while b >= 1:
         ops += 5 * b

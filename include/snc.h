@@ -141,8 +141,9 @@ int snc_microbench(snc_ctx* ctx, int kind, int32_t iters, void* d_buf, size_t bu
  *   default; batched calls only: snc_resultant_y_prepare/_batch), 2 =
  *   measure again.  Choices are kept per (class, LDS variant, log2 of the
  *   class's block count) and appended to the cache file
- *   $SNC_TUNE_DIR/eval_elim_<arch>_<CUs>cu.tune (default directory
- *   $HOME/.cache/snc), read by later processes.
+ *   $SNC_TUNE_DIR/eval_elim_<arch>_<CUs>cu_r<rev>.tune (default directory
+ *   $HOME/.cache/snc), read by later processes; <rev> is the revision of
+ *   the evaluation kernels, so a library with changed kernels tunes again.
  * snc_set_eval_variant: force (wpe, chunk) for every launch of the class
  *   whose largest y-degree is class_cap on this context (wpe 0 clears).
  * snc_get_tuning: the last batched preparation's choice per class used:

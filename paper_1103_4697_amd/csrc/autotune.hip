@@ -53,7 +53,7 @@ std::string cache_path(const std::string& tag) {
   } else {
     return "";
   }
-  return dir + "/eval_elim_" + tag + ".tune";
+  return dir + "/eval_elim_" + tag + "_r" + std::to_string(EE_KERNEL_REV) + ".tune";
 }
 
 void mkdirs(const std::string& file) {

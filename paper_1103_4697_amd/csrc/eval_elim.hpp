@@ -9,6 +9,22 @@
 
 namespace snc {
 
+// Width step of the elimination's register phases: a step of divisor degree
+// b computes at most 3 entries beyond its b.  Steps of 8 measured the same on
+// the degree-48 class and 4% slower on the degree-32 class; finer steps grow
+// the code past what the instruction cache holds.
+constexpr int EE_PHASE = 4;
+
+// A zero that the compiler cannot see through.  An array entry set to a
+// literal zero inside a loop and multiplied in the next iteration becomes a
+// 64-bit loop value whose products take the full 64 x 32 multiply sequence
+// (two multiply-adds and two moves instead of one multiply-add).
+__device__ __forceinline__ uint32_t zero_v() {
+  uint32_t z;
+  asm("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
 // block index -> job index: largest jj with prefix[jj] <= b (prefix[0] = 0)
 __device__ __forceinline__ int find_job(const int64_t* prefix, int njobs, int64_t b) {
   int lo = 0, hi = njobs - 1;
@@ -69,9 +85,9 @@ __device__ __forceinline__ uint32_t horner_grouped(const uint32_t* r, const RowD
 // wavefront).  A chunk of four coefficients is one step of Horner's rule in
 // x^4 with the powers x, x^2, x^3, x^4 kept per lane:
 //   acc <- acc x^4 + v0 + v1 x + v2 x^2 + v3 x^3,
-// four 64-bit multiply-adds and one reduction (v0 enters as v0 2^32).  With
-// canonical coefficients and powers and acc < 4p the sum stays below
-// 7 p^2 + 2^32 p and the result below 4p.  Group lengths are padded at the
+// four 64-bit multiply-adds and one reduction, v0 added to its result.  With
+// canonical coefficients and powers and acc < 4p the sum stays below 7 p^2,
+// the reduction below 2.75p and the result below 4p.  Group lengths are padded at the
 // top with zeros, which keep an accumulator at zero.
 struct alignas(16) HChunk {
   uint4 v[HCHUNK];
@@ -84,11 +100,14 @@ struct XPow {
 
 __device__ __forceinline__ uint32_t hstep4(uint32_t acc, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
                                            const XPow& xp, const PrimeC& c) {
-  uint64_t t = (uint64_t)acc * xp.x4 + ((uint64_t)v0 << 32);
+  uint64_t t = (uint64_t)acc * xp.x4;
   t += (uint64_t)v1 * xp.x1;
   t += (uint64_t)v2 * xp.x2;
   t += (uint64_t)v3 * xp.x3;
-  return redc_mv(t, c.p, c.pinv);
+  // v0 is added after the reduction, REDC(t + v0 2^32) = REDC(t) + v0: the
+  // addition also moves the result out of the 64-bit register pair
+  const uint32_t m = (uint32_t)t * c.pinv;
+  return (uint32_t)((t + (uint64_t)m * c.p) >> 32) + v0;
 }
 
 __device__ __forceinline__ void horner_chunk(uint32_t& a0, uint32_t& a1, uint32_t& a2, uint32_t& a3,
@@ -132,11 +151,13 @@ constexpr int EL_NORMAL = 0, EL_ZERO = 1, EL_ABN = 2;
 // Lanes whose leading coefficient vanished scan the rest of it.  The scan
 // sits behind a wavefront-uniform branch (a ballot of those lanes), which is
 // almost never taken: a leading coefficient vanishes with probability about
-// 1/p per step, so a normal step costs one comparison and no scan.
+// 1/p per step, so a normal step costs one comparison and no scan.  The
+// leading coefficient is left canonical, which the next steps rely on.
 template <int N, int C>
-__device__ __forceinline__ void lead_check(const uint32_t (&X)[N + 1], int& st, const PrimeC& c) {
-  const bool z = canon(X[0], c.p) == 0 && st == EL_NORMAL;
-  if (__builtin_amdgcn_ballot_w64(z)) {
+__device__ __forceinline__ void lead_check(uint32_t (&X)[N + 1], int& st, const PrimeC& c) {
+  X[0] = canon(X[0], c.p);
+  const bool z = X[0] == 0 && st == EL_NORMAL;
+  if (__builtin_expect(__builtin_amdgcn_ballot_w64(z) != 0, 0)) {
     uint32_t nz = 0;
 #pragma unroll
     for (int i = 1; i <= C; ++i) nz |= canon(X[i], c.p);
@@ -160,67 +181,122 @@ __device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (
   return lcY;
 }
 
+// First remainder with a degree gap (s = deg X - deg Y + 1 elementary
+// steps, deg Y = b < W): only the window X[0..W-2] meets Y; the entries
+// above it are merely multiplied by lc(Y) and shifted down once per step.
+// Those are kept unscaled and moved down one register per step, and an
+// entry is scaled by lc(Y)^e when it enters the window at step e: one
+// update of two products per window entry and one move per entry above,
+// instead of the two-product update over the whole width.  The same
+// residues as rem_c; after the s steps the entries above the window have
+// all been shifted out (they are zero).
+template <int N, int W>
+__device__ __forceinline__ uint32_t rem_win(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, int& st,
+                                            const PrimeC& c) {
+  const uint32_t lcY = canon(Y[0], c.p);
+  uint32_t pw = c.r1;  // lc(Y)^e
+#pragma nounroll
+  for (int e = 0; e < s; ++e) {
+    const uint32_t nlX = c.p - canon(X[0], c.p);
+#pragma unroll
+    for (int i = 0; i < W - 1; ++i)
+      X[i] = redc_mv((uint64_t)lcY * X[i + 1] + (uint64_t)nlX * Y[i + 1], c.p, c.pinv);
+    pw = mmulc(pw, lcY, c.p, c.pinv);
+    X[W - 1] = redc_mv((uint64_t)pw * X[W], c.p, c.pinv);
+#pragma unroll
+    for (int i = W; i < N; ++i) X[i] = X[i + 1];
+    X[N] = zero_v();
+  }
+  lead_check<N, W>(X, st, c);
+  return lcY;
+}
+
+// rem_win on the narrowest window (N minus a multiple of 8, at least 8)
+// with deg Y = b < W
+template <int N, int C>
+__device__ __forceinline__ uint32_t rem_win_fit(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, int b,
+                                                int& st, const PrimeC& c) {
+  if constexpr (C - 8 >= 8) {
+    if (b < C - 8) return rem_win_fit<N, C - 8>(X, Y, s, b, st, c);
+  }
+  return rem_win<N, C>(X, Y, s, st, c);
+}
+
 // The same remainder for deg X = deg Y + 1 (a normal step, s = 2) as one
 // update with the two elementary steps fused:
 //   X[i] <- a X[i+2] + b Y[i+2] + cc Y[i+1],  a = lc(Y)^2,  b = -lc(Y) lc(X),
 //   cc = lc(X) Y[1] - lc(Y) X[1]
 // (entries above C read as zero): 3 products and one reduction per entry
-// instead of 4 and 2, the same residues.  Values stay below 4p.
-template <int N, int C>
+// instead of 4 and 2, the same residues.  Values stay below 4p; the leading
+// coefficients X[0], Y[0] are canonical (every step's lead check, and the
+// evaluation, leave them so).  With
+// deg X <= K + 1 the new remainder (degree deg X - 2) has at most K
+// entries: only those are computed, the entries K..C are set to zero.
+template <int N, int C, int K>
 __device__ __forceinline__ uint32_t rem2_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int& st,
                                            const PrimeC& c) {
-  const uint32_t q0 = canon(Y[0], c.p), p0 = canon(X[0], c.p);
+  static_assert(K <= C, "at most C entries");
+  const uint32_t q0 = Y[0], p0 = X[0];
   const uint32_t a = mmulc(q0, q0, c.p, c.pinv);
   const uint32_t b = mmulc(q0, c.p - p0, c.p, c.pinv);
   // p0 Y[1] - q0 X[1] with one reduction: below 8 p^2, reduced below 3p
   const uint32_t cc = canon(redc((uint64_t)p0 * Y[1] + (uint64_t)(c.p - q0) * X[1], c.p, c.pinv), c.p);
 #pragma unroll
-  for (int i = 0; i < C; ++i) {
+  for (int i = 0; i < K; ++i) {
     const uint32_t x2 = i + 2 <= C ? X[i + 2] : 0u;
     const uint32_t y2 = i + 2 <= C ? Y[i + 2] : 0u;
     X[i] = redc_mv((uint64_t)a * x2 + (uint64_t)b * y2 + (uint64_t)cc * Y[i + 1], c.p, c.pinv);
   }
-  X[C] = 0;
+#pragma unroll
+  for (int i = K; i <= C; ++i) X[i] = zero_v();
   lead_check<N, C>(X, st, c);
   return q0;
 }
 
-// rem2_c on the narrowest width (a multiple of 8) that holds deg X = a
+// rem2_c on the narrowest width (a multiple of EE_PHASE, at least 8) that
+// holds deg X = a
 template <int N, int C>
 __device__ __forceinline__ uint32_t rem2_fit(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int a, int& st,
                                              const PrimeC& c) {
-  if constexpr (C > 8) {
-    if (a <= C - 8) return rem2_fit<N, C - 8>(X, Y, a, st, c);
+  if constexpr (C - EE_PHASE >= 8) {
+    if (a <= C - EE_PHASE) return rem2_fit<N, C - EE_PHASE>(X, Y, a, st, c);
   }
-  return rem2_c<N, C>(X, Y, st, c);
+  return rem2_c<N, C, C - 1>(X, Y, st, c);
 }
 
 // Scale factors of the normal steps.  A normal step with divisor degree b
 // (s = 2) contributes y^{2(b-1)}, y = lc(divisor), and b drops by one per
 // step, so with prefix products P_j = y_0 ... y_j the whole product is
 // (P_0 P_1 ... P_J)^2 over the steps with b >= 2: two products per step, in
-// straight-line code, instead of a power per step.
+// straight-line code, instead of a power per step.  With y canonical the
+// unreduced products keep P and Q below 2p (a product below 4p^2 reduces to
+// below p^2 2^-30 + p < 2p), which is all the next products need.
 __device__ __forceinline__ void scale_step(uint32_t y, int b, uint32_t& P, uint32_t& Q, const PrimeC& c) {
-  const uint32_t Pn = mmulc(P, y, c.p, c.pinv);
-  const uint32_t Qn = mmulc(Q, Pn, c.p, c.pinv);
+  const uint32_t Pn = mmul(P, y, c.p, c.pinv);
+  const uint32_t Qn = mmul(Q, Pn, c.p, c.pinv);
   P = b >= 2 ? Pn : P;
   Q = b >= 2 ? Qn : Q;
 }
 
-// Remainder pairs (dividend B, divisor A) while the divisor degree bb stays
-// >= C - 8, on arrays of width C; then the next narrower phase.
+// Remainder pairs (dividend B, divisor A) on arrays of width C, entered
+// with deg B = a <= C, while the divisor degree bb stays >= C - EE_PHASE
+// (the narrowest phase, C = 4, runs to the end); then the next narrower
+// phase.  The pair's first step has a dividend of degree <= C, its second
+// one of degree <= C - 1, so they compute C - 1 and C - 2 entries.
 template <int N, int C>
 __device__ __forceinline__ void elim_phases(uint32_t (&A)[N + 1], uint32_t (&B)[N + 1], int& a,
                                             int& bb, int& st, uint32_t& P, uint32_t& Q, int& sg,
                                             const PrimeC& c) {
+  constexpr int nxt = C - EE_PHASE >= 4 ? C - EE_PHASE : 4;
+  constexpr int lo = C > 4 ? nxt : 0;
 #pragma nounroll
-  while (bb >= 2 && bb >= C - 8) {
-    scale_step(rem2_c<N, C>(B, A, st, c), bb, P, Q, c);  // B <- prem(B, A), degree bb-1
+  while (bb >= 2 && bb >= lo) {
+    scale_step(rem2_c<N, C, C - 1>(B, A, st, c), bb, P, Q, c);  // B <- prem(B, A), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
-    scale_step(rem2_c<N, C>(A, B, st, c), bb, P, Q, c);  // A <- prem(A, B), degree bb-1
+    scale_step(rem2_c<N, C, C - 2>(A, B, st, c), bb, P, Q, c);  // A <- prem(A, B), degree bb-1
     sg ^= (a & bb & 1); a = bb; bb -= 1;
   }
-  if constexpr (C > 8) elim_phases<N, C - 8>(A, B, a, bb, st, P, Q, sg, c);
+  if constexpr (C > 4) elim_phases<N, nxt>(A, B, a, bb, st, P, Q, sg, c);
 }
 
 // One block of the evaluation: 64 consecutive points of one prime of one
@@ -283,8 +359,10 @@ __device__ __forceinline__ void eval_elim_block(int64_t b, const PrimeC* primes,
   eval_rows<N>(B, r, rb, X, c);
 
   // formal degrees attained at this point, else the general elimination
-  int st = canon(A[0], c.p) != 0 ? EL_NORMAL : EL_ABN;
-  if (J.n >= 1 && canon(B[0], c.p) == 0) st = EL_ABN;
+  A[0] = canon(A[0], c.p);
+  B[0] = canon(B[0], c.p);
+  int st = A[0] != 0 ? EL_NORMAL : EL_ABN;
+  if (J.n >= 1 && B[0] == 0) st = EL_ABN;
   uint32_t den = c.r1;
   int sg = J.sign;
   int a = J.m, bb = J.n;
@@ -295,7 +373,10 @@ __device__ __forceinline__ void eval_elim_block(int64_t b, const PrimeC* primes,
     // first remainder: A <- prem(A, B) with s = m - n + 1 elementary steps,
     // scale lc(B)^{s (n - 1)}
     const int s0 = a - bb + 1;
-    const uint32_t y0 = s0 == 2 ? rem2_fit<N, N>(A, B, a, st, c) : rem_c<N, N>(A, B, s0, st, c);
+    // (deg B = N only with deg A = N: the whole width meets B)
+    const uint32_t y0 = s0 == 2   ? rem2_fit<N, N>(A, B, a, st, c)
+                        : bb < N  ? rem_win_fit<N, N>(A, B, s0, bb, st, c)
+                                  : rem_c<N, N>(A, B, s0, st, c);
     den = mpow(y0, (uint32_t)(s0 * (bb - 1)), c);
     sg ^= (a & bb & 1); a = bb; bb -= 1;
     // from here on: dividend B (degree a), divisor A (degree bb)
@@ -303,7 +384,7 @@ __device__ __forceinline__ void eval_elim_block(int64_t b, const PrimeC* primes,
     elim_phases<N, N>(A, B, a, bb, st, P, Q, sg, c);
     den = mmulc(den, mmulc(Q, Q, c.p, c.pinv), c.p, c.pinv);
     if (bb == 1) {  // last step: divisor of degree 1, scale y^0
-      rem2_c<N, 8>(B, A, st, c);
+      rem2_c<N, 4, 1>(B, A, st, c);
       sg ^= (a & bb & 1); a = bb; bb -= 1;
       res = mpow(B[0], (uint32_t)a, c);
     } else {

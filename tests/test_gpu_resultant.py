@@ -81,6 +81,32 @@ def test_register_classes_and_ragged_tiles(snc):
         check(snc, f, g)
 
 
+# (deg_y f, deg_y g) through every form of the first remainder and every
+# phase width: the normal step (m = n + 1) at and below a class's top
+# width, m = n (one elementary step) with the whole width meeting g at the
+# top, large gaps with g of degree 1 or 2 (a narrow window, most of f only
+# scaled), and windows of each width in steps of 8
+FIRST_REMAINDER_SHAPES = [(48, 47), (47, 46), (48, 48), (47, 47), (48, 1), (48, 2), (40, 8), (41, 15),
+                          (45, 31), (33, 32), (32, 32), (32, 1), (30, 16), (17, 16), (16, 16), (16, 7),
+                          (9, 9), (8, 8), (8, 7), (8, 2), (7, 1), (64, 64), (64, 63), (64, 5), (4, 4),
+                          (3, 2), (2, 1)]
+
+
+def test_first_remainder_shapes(snc, assert_same):
+    rng = np.random.default_rng(4242)
+    pairs = [rand_pair(rng, m, n, 1, 2, 12) for m, n in FIRST_REMAINDER_SHAPES]
+    pairs += [(g, f) for f, g in pairs[:4]]   # the smaller degree first
+    batch = snc.resultant_y_batch(pairs)
+    rs = random.Random(17)
+    for (f, g), r in zip(pairs, batch):
+        m, n = len(f) - 1, len(g) - 1
+        assert len(r) - 1 <= snc.resultant_plan(f, g).deg_bound, (m, n)
+        for x0 in (0, 1, rs.randrange(Q61)):
+            assert zx.evaluate(r, x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61), (m, n, x0)
+    for i in (0, 2, 4, 21):
+        assert_same(snc.resultant_y(*pairs[i]), batch[i])
+
+
 def test_edge_cases(snc):
     one = [[1]]
     f = [[3, 1], [0, 2], [1]]
