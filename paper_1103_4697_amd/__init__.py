@@ -83,6 +83,8 @@ def lib():
                 "snc_resultant_y_batch": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_resultant_y_prepare": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(VP)]),
                 "snc_prepared_run": (C.c_int, [VP, VP, P(Upoly)]),
+                "snc_prepared_submit": (C.c_int, [VP, VP, P(C.c_int64)]),
+                "snc_prepared_collect": (C.c_int, [VP, C.c_int64, P(Upoly)]),
                 "snc_prepared_destroy": (C.c_int, [VP]),
                 "snc_server_create": (C.c_int, [VP, VP, SZ, I32, I32, P(VP)]),
                 "snc_submit_resultant_y": (C.c_int, [VP, P(Bipoly), P(Bipoly), P(C.c_uint64)]),
@@ -423,6 +425,23 @@ class ResultantBatch:
             self.out[i].nlimbs = nl
         st = lib().snc_prepared_run(self.h, self.ctx.stream_handle(stream), self.out)
         self.ctx.check(st, "snc_prepared_run")
+
+    def submit(self, stream=None) -> int:
+        """Enqueue one run and the download of its results
+        (snc_prepared_submit); returns its ticket.  The next submit's kernels
+        overlap this run's download.  At most two runs are outstanding."""
+        t = C.c_int64(-1)
+        self.ctx.check(lib().snc_prepared_submit(self.h, self.ctx.stream_handle(stream), C.byref(t)),
+                       "snc_prepared_submit")
+        return t.value
+
+    def collect(self, ticket: int):
+        """Wait for a submitted run and write its results into the output
+        buffers (read them with results())."""
+        for i, (d, nl) in enumerate(self.caps):
+            self.out[i].deg = d
+            self.out[i].nlimbs = nl
+        self.ctx.check(lib().snc_prepared_collect(self.h, C.c_int64(ticket), self.out), "snc_prepared_collect")
 
     def run_sqfree(self, stream=None):
         """Run the pipeline and gcd(R_i, R_i') in the same pass

@@ -524,9 +524,9 @@ static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer&
 }
 
 // results of jobs j0 .. j1-1 with j = tid mod nthr from the staged output block into out
-static void collect_jobs(const snc_prepared* pr, snc_upoly* out, int j0, int j1, int tid, int nthr) {
+static void collect_jobs(const snc_prepared* pr, const uint32_t* ho, snc_upoly* out, int j0, int j1, int tid,
+                         int nthr) {
   const BatchLayout& lay = pr->lay;
-  const uint32_t* ho = (const uint32_t*)pr->h_out;
   const size_t base = lay.out_off / 4;
   for (int j = j0 + tid; j < j1; j += nthr) {
     const int i = lay.dev[j];
@@ -552,7 +552,7 @@ static void collect_jobs(const snc_prepared* pr, snc_upoly* out, int j0, int j1,
 }
 
 static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
-  collect_jobs(pr, out, 0, (int)pr->lay.dev.size(), 0, 1);
+  collect_jobs(pr, (const uint32_t*)pr->h_out, out, 0, (int)pr->lay.dev.size(), 0, 1);
 }
 
 // Download and collection of a large output block in chunks: the copy of
@@ -560,11 +560,9 @@ static void prepared_collect(snc_prepared* pr, snc_upoly* out) {
 constexpr size_t COLLECT_CHUNKED_WORDS = (size_t)1 << 20;
 constexpr int COLLECT_CHUNKS = 8;
 
-static int download_collect_chunked(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
-  snc_ctx* c = pr->c;
-  const BatchLayout& lay = pr->lay;
+// job ranges of about equal output words (the jobs' output regions are consecutive)
+static std::vector<int> chunk_bounds(const BatchLayout& lay) {
   const int NJ = (int)lay.dev.size();
-  // job ranges of about equal output words (the jobs' output regions are consecutive)
   std::vector<int> bnd{0};
   const size_t per = (lay.out_words + COLLECT_CHUNKS - 1) / COLLECT_CHUNKS;
   size_t acc = 0;
@@ -573,20 +571,39 @@ static int download_collect_chunked(snc_prepared* pr, hipStream_t stream, snc_up
     if (acc >= per * bnd.size() && j + 1 < NJ && (int)bnd.size() < COLLECT_CHUNKS) bnd.push_back(j + 1);
   }
   bnd.push_back(NJ);
+  return bnd;
+}
+
+// downloads of the output block from src (device, laid out as the
+// workspace's output region) to dst (pinned host) in the chunks of bnd on
+// stream, one event recorded after each
+static int enqueue_chunks(const snc_prepared* pr, const std::vector<int>& bnd, const uint8_t* src, void* dst,
+                          std::vector<hipEvent_t>& ev, hipStream_t stream) {
+  snc_ctx* c = pr->c;
+  const BatchLayout& lay = pr->lay;
+  const int NJ = (int)lay.dev.size();
   const int nch = (int)bnd.size() - 1;
-  while ((int)pr->d2h_ev.size() < nch) {
+  while ((int)ev.size() < nch) {
     hipEvent_t e;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    pr->d2h_ev.push_back(e);
+    ev.push_back(e);
   }
   const size_t base = lay.out_off / 4;
   for (int ch = 0; ch < nch; ++ch) {
     const size_t w0 = lay.jobs[bnd[ch]].out_off - base;
     const size_t w1 = bnd[ch + 1] < NJ ? lay.jobs[bnd[ch + 1]].out_off - base : lay.out_words;
-    HIPCHK(hipMemcpyAsync((uint32_t*)pr->h_out + w0, pr->ws + lay.out_off + w0 * 4, (w1 - w0) * 4,
-                          hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipEventRecord(pr->d2h_ev[ch], stream));
+    HIPCHK(hipMemcpyAsync((uint32_t*)dst + w0, src + w0 * 4, (w1 - w0) * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipEventRecord(ev[ch], stream));
   }
+  return SNC_OK;
+}
+
+// host threads widen each chunk of ho into the caller's buffers as soon as
+// its event has completed
+static int widen_chunks(snc_prepared* pr, const std::vector<int>& bnd, const std::vector<hipEvent_t>& ev,
+                        const uint32_t* ho, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  const int nch = (int)bnd.size() - 1;
   const unsigned hc = std::thread::hardware_concurrency();
   const int nthr = (int)std::max(1u, std::min(8u, hc / 2));
   std::atomic<int> ready{0};
@@ -598,19 +615,26 @@ static int download_collect_chunked(snc_prepared* pr, hipStream_t stream, snc_up
           if (ready.load(std::memory_order_acquire) < 0) return;
           std::this_thread::yield();
         }
-        collect_jobs(pr, out, bnd[ch], bnd[ch + 1], t, nthr);
+        collect_jobs(pr, ho, out, bnd[ch], bnd[ch + 1], t, nthr);
       }
     });
   hipError_t err = hipSuccess;
   for (int ch = 0; ch < nch; ++ch) {
-    err = hipEventSynchronize(pr->d2h_ev[ch]);
+    err = hipEventSynchronize(ev[ch]);
     if (err != hipSuccess) { ready.store(-1, std::memory_order_release); break; }
     ready.store(ch + 1, std::memory_order_release);
-    collect_jobs(pr, out, bnd[ch], bnd[ch + 1], 0, nthr);
+    collect_jobs(pr, ho, out, bnd[ch], bnd[ch + 1], 0, nthr);
   }
   for (auto& w : workers) w.join();
   if (err != hipSuccess) { c->err = std::string("result download: ") + hipGetErrorString(err); return SNC_EDEVICE; }
   return SNC_OK;
+}
+
+static int download_collect_chunked(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
+  const std::vector<int> bnd = chunk_bounds(pr->lay);
+  const int st = enqueue_chunks(pr, bnd, pr->ws + pr->lay.out_off, pr->h_out, pr->d2h_ev, stream);
+  if (st) return st;
+  return widen_chunks(pr, bnd, pr->d2h_ev, (const uint32_t*)pr->h_out, out);
 }
 
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
@@ -629,6 +653,58 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   tm.finish();
   prepared_collect(pr, out);
   return SNC_OK;
+}
+
+int submit_prepared(snc_prepared* pr, hipStream_t stream, int64_t* ticket) {
+  snc_ctx* c = pr->c;
+  int s = (int)(pr->next_ticket & 1);
+  if (pr->slot_ticket[s] >= 0) s ^= 1;
+  if (pr->slot_ticket[s] >= 0) {
+    c->err = "snc_prepared_submit: two runs are outstanding; collect one first";
+    return SNC_EAGAIN;
+  }
+  HIPCHK(hipSetDevice(c->device));
+  const size_t bytes = pr->lay.out_words * 4;
+  if (bytes && !pr->slot_dev[s]) {
+    HIPCHK(hipMalloc((void**)&pr->slot_dev[s], bytes));
+    HIPCHK(hipHostMalloc(&pr->slot_host[s], bytes, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&pr->slot_copied[s], hipEventDisableTiming));
+  }
+  if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+  if (!pr->lay.dev.empty()) {
+    StageTimer tm{c, stream, false};
+    const int st = launch_prepared_all(pr, stream, tm);
+    if (st) return st;
+    // the output region goes to the slot on the device (a short copy on
+    // this stream), and from there to the host on the side stream, so the
+    // next run's kernels can start right after this copy
+    HIPCHK(hipMemcpyAsync(pr->slot_dev[s], pr->ws + pr->lay.out_off, bytes, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipEventRecord(pr->slot_copied[s], stream));
+    HIPCHK(hipStreamWaitEvent(c->side_stream, pr->slot_copied[s], 0));
+    const int st2 = enqueue_chunks(pr, chunk_bounds(pr->lay), pr->slot_dev[s], pr->slot_host[s], pr->slot_ev[s],
+                                   c->side_stream);
+    if (st2) return st2;
+  }
+  pr->slot_ticket[s] = pr->next_ticket;
+  *ticket = pr->next_ticket++;
+  return SNC_OK;
+}
+
+int collect_prepared(snc_prepared* pr, int64_t ticket, snc_upoly* out) {
+  snc_ctx* c = pr->c;
+  const int s = ticket >= 0 && pr->slot_ticket[0] == ticket ? 0 : ticket >= 0 && pr->slot_ticket[1] == ticket ? 1 : -1;
+  if (s < 0) {
+    c->err = "snc_prepared_collect: ticket " + std::to_string(ticket) + " is not an outstanding run";
+    return SNC_EINVAL;
+  }
+  if (!prepared_outputs(pr, out)) return SNC_ERANGE;
+  int st = SNC_OK;
+  if (!pr->lay.dev.empty()) {
+    HIPCHK(hipSetDevice(c->device));
+    st = widen_chunks(pr, chunk_bounds(pr->lay), pr->slot_ev[s], (const uint32_t*)pr->slot_host[s], out);
+  }
+  pr->slot_ticket[s] = -1;
+  return st;
 }
 
 int run_prepared_fork(snc_prepared* pr, hipStream_t stream, const std::function<int(hipStream_t)>& branch,
@@ -674,6 +750,14 @@ int run_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, 
 
 void destroy_prepared(snc_prepared* pr) {
   if (!pr) return;
+  for (int s = 0; s < 2; ++s) {
+    // an uncollected run's download must end before its buffers go
+    if (pr->slot_ticket[s] >= 0 && !pr->slot_ev[s].empty()) (void)hipEventSynchronize(pr->slot_ev[s].back());
+    if (pr->slot_dev[s]) (void)hipFree(pr->slot_dev[s]);
+    if (pr->slot_host[s]) (void)hipHostFree(pr->slot_host[s]);
+    if (pr->slot_copied[s]) (void)hipEventDestroy(pr->slot_copied[s]);
+    for (hipEvent_t e : pr->slot_ev[s]) (void)hipEventDestroy(e);
+  }
   if (pr->gexec) (void)hipGraphExecDestroy(pr->gexec);
   if (pr->h_out) (void)hipHostFree(pr->h_out);
   if (pr->h_ed) (void)hipHostFree(pr->h_ed);

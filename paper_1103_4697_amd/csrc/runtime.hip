@@ -423,6 +423,16 @@ int snc_prepared_run(snc_prepared* p, void* stream, snc_upoly* out) {
   return run_prepared(p, (hipStream_t)stream, out);
 }
 
+int snc_prepared_submit(snc_prepared* p, void* stream, int64_t* ticket) {
+  if (!p || !ticket) return SNC_EINVAL;
+  return submit_prepared(p, (hipStream_t)stream, ticket);
+}
+
+int snc_prepared_collect(snc_prepared* p, int64_t ticket, snc_upoly* out) {
+  if (!p || (p->n > 0 && !out)) return SNC_EINVAL;
+  return collect_prepared(p, ticket, out);
+}
+
 int snc_prepared_destroy(snc_prepared* p) {
   if (!p) return SNC_EINVAL;
   destroy_prepared(p);

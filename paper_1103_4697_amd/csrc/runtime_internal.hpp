@@ -152,6 +152,14 @@ struct snc_prepared {
   bool sq_ready = false;
   std::shared_ptr<void> sq_cache;    // the projection step's plan, built on the first run
   std::vector<int> sq_ranges;        // (register class, first item, items, largest degree) per launch
+  // pipelined runs (snc_prepared_submit / _collect): two staging slots of the
+  // output block, on the device and in pinned host memory
+  uint8_t* slot_dev[2] = {nullptr, nullptr};
+  void* slot_host[2] = {nullptr, nullptr};
+  int64_t slot_ticket[2] = {-1, -1};            // the run a slot holds, -1 free
+  hipEvent_t slot_copied[2] = {nullptr, nullptr};  // output region copied into the slot
+  std::vector<hipEvent_t> slot_ev[2];           // download chunks of the slot
+  int64_t next_ticket = 0;
 };
 
 namespace snc {
@@ -170,6 +178,11 @@ int choose_eval_variants(snc_ctx* c, BatchLayout& lay, uint8_t* ws, hipStream_t 
 int prepare_resultants(snc_ctx* c, int n, const snc_bipoly* f, const snc_bipoly* g, void* d_ws,
                        size_t ws_bytes, hipStream_t stream, bool use_graph, snc_prepared** outp);
 int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
+// pipelined runs: submit enqueues a run and the download of its results
+// into a free staging slot (SNC_EAGAIN when both hold uncollected runs);
+// collect waits for a ticket's download and widens it into out
+int submit_prepared(snc_prepared* pr, hipStream_t stream, int64_t* ticket);
+int collect_prepared(snc_prepared* pr, int64_t ticket, snc_upoly* out);
 // the pipeline with a second branch after the interpolation: branch(stream)
 // enqueues work that follows the interpolation on `stream` while the Chinese
 // remaindering and the download of the results run on the side stream;

@@ -461,3 +461,37 @@ def test_one_wavefront_interpolation_batch(snc, assert_same):
     f, g = pairs[6]
     x0 = qr.randrange(Q61)
     assert zx.evaluate(got[6], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
+
+
+def test_pipelined_submit_collect(snc, assert_same):
+    """snc_prepared_submit / _collect: every collected run equals a plain
+    run of the prepared batch, with two runs outstanding, a third submit
+    refused until one is collected, a prepared run between them, an unknown
+    ticket refused, and a handle destroyed with a run outstanding."""
+    pairs, common = synth.config2(npairs=48, frac_common=0.1)
+    b = snc.ResultantBatch(pairs)
+    b.run()
+    ref = b.results()
+    t0 = b.submit()
+    t1 = b.submit()
+    with pytest.raises(snc.SncError) as ei:
+        b.submit()
+    assert ei.value.status == snc.SNC_EAGAIN
+    b.collect(t0)
+    assert_same(b.results(), ref)
+    t2 = b.submit()
+    b.run()                      # the plain run between pipelined ones
+    assert_same(b.results(), ref)
+    b.collect(t1)
+    assert_same(b.results(), ref)
+    b.collect(t2)
+    assert_same(b.results(), ref)
+    with pytest.raises(snc.SncError) as ei:
+        b.collect(t2)
+    assert ei.value.status == snc.SNC_EINVAL
+    assert [t0, t1, t2] == [0, 1, 2]
+    for i in common:
+        assert ref[i] == []
+    t3 = b.submit()
+    assert t3 == 3
+    b.close()                    # waits for the outstanding download
