@@ -904,7 +904,7 @@ __global__ __launch_bounds__(64 * CRT_COEF_PER_BLOCK) void k_crt_combine(CrtTabl
 //   balanced result: X - M when X > (M-1)/2, decided on the digits on the
 //     way down ((M-1)/2 has digits (p_j - 1)/2); L two's-complement limbs.
 constexpr int CRT_KS = 128;                 // largest prime count of this path
-__device__ uint32_t g_wts[CRT_KS * CRT_KS];  // [i][j] = Montgomery form of P_j mod p_i for j < i, else 0
+__device__ __align__(64) uint32_t g_wts[CRT_KS * CRT_KS];  // [i][j] = Montgomery form of P_j mod p_i for j < i, else 0
 
 __global__ void k_crt_small_init() {
   const int i = blockIdx.x;
@@ -920,7 +920,7 @@ void launch_crt_small_init(hipStream_t s) {
 template <int KC>
 __global__ __launch_bounds__(64) void k_crt_small(const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
                                                   int njobs, uint32_t* ws) {
-  static_assert(KC <= CRT_KS, "prime capacity of the small path");
+  static_assert(KC <= CRT_KS && KC % 16 == 0, "prime capacity of the small path, whole groups of 16 digits");
   constexpr int LC = (30 * KC + 31) / 32 + 2;  // limbs of X (as lx_of)
   __shared__ uint32_t yl[KC * 64];
   const int64_t b = blockIdx.x;
@@ -938,16 +938,18 @@ __global__ __launch_bounds__(64) void k_crt_small(const ResJob* jobs, const int3
     uint32_t S = 0;  // < 2p
     for (int j0 = 0; j0 < i; j0 += 16) {
       // y_j < p and W < p: sixteen products stay below 2^64 (four partial
-      // sums); sum 2^-32 = hi + REDC(lo), hi < 4p, REDC(lo) <= p
+      // sums); sum 2^-32 = hi + REDC(lo), hi < 4p, REDC(lo) <= p.  Past the
+      // last digit (j >= i) the table row is zero and the digit slots hold
+      // finite values (stale or not yet written; KC is a multiple of 16, so
+      // they lie in yl): the products are zero, with no bounds on the loads,
+      // and the sixteen weights come in four 16-byte scalar loads.
+      const uint4* w4 = reinterpret_cast<const uint4*>(w + j0);
+      const uint4 wa = w4[0], wb = w4[1], wc = w4[2], wd = w4[3];
+      const uint32_t wv[16] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w,
+                               wc.x, wc.y, wc.z, wc.w, wd.x, wd.y, wd.z, wd.w};
       uint64_t part[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int j = j0 + u;
-        const bool in = j < i;  // uniform
-        const uint32_t y = in ? yl[64 * (in ? j : 0) + lane] : 0u;
-        const uint32_t wv = in ? w[in ? j : 0] : 0u;
-        part[u & 3] += (uint64_t)y * wv;
-      }
+      for (int u = 0; u < 16; ++u) part[u & 3] += (uint64_t)yl[64 * (j0 + u) + lane] * wv[u];
       const uint64_t sum = (part[0] + part[1]) + (part[2] + part[3]);
       uint32_t hi = (uint32_t)(sum >> 32);
       const uint32_t h2 = hi - 2 * c.p;
