@@ -414,25 +414,29 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
 // with no barriers between wavefronts.  LDS holds only the sliding operand:
 // w_j = (-1)^j / j! for the convolution, then P, updated in place from its top
 // block down (a block's new values depend on its own and the next lower
-// block's old ones).  The uniform operand is a register broadcast by
-// readlane, shared by two output blocks; the Newton blocks Q_j go to the
-// workspace, the F_j come from their table.
+// block's old ones).  The uniform operand, 64 words, is staged in LDS too and
+// read four words at a time at one address for the whole wavefront (a
+// broadcast; no vector-unit instruction per word), shared by two output
+// blocks; the Newton blocks Q_j go to the workspace, the F_j come from their
+// table.
 // ---------------------------------------------------------------------------
-// s1 += sum_q u_q S1[-q], and (TWO) s2 += sum_q u_q S2[-q], u_q = lane q of u.
-// One reduction per 8 canonical products: their sum stays below 8 p^2, so
-// REDC's sum below 8 p^2 + 2^32 p < 2^64 and its result below 3p, and
-// s + REDC below 4p < 2^32 (16 products could exceed both bounds).
+// s1 += sum_q U[q] S1[-q], and (TWO) s2 += sum_q U[q] S2[-q], U in LDS
+// (16-byte aligned).  One reduction per 8 canonical products: their sum stays
+// below 8 p^2, so REDC's sum below 8 p^2 + 2^32 p < 2^64 and its result below
+// 3p, and s + REDC below 4p < 2^32 (16 products could exceed both bounds).
 template <bool TWO>
-__device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, uint32_t u, const uint32_t* S1,
+__device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, const uint32_t* U, const uint32_t* S1,
                                              const uint32_t* S2, const PrimeC& c) {
 #pragma unroll
   for (int g = 0; g < 64; g += 8) {
+    const uint4 ua = *reinterpret_cast<const uint4*>(U + g), ub = *reinterpret_cast<const uint4*>(U + g + 4);
+    const uint32_t w8[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
     uint64_t a1 = 0, a2 = 0;
 #pragma unroll
-    for (int q = g; q < g + 8; ++q) {
-      const uint64_t w = bcast(u, q);
-      a1 += w * S1[-q];
-      if constexpr (TWO) a2 += w * S2[-q];
+    for (int q = 0; q < 8; ++q) {
+      const uint64_t w = w8[q];
+      a1 += w * S1[-(g + q)];
+      if constexpr (TWO) a2 += w * S2[-(g + q)];
     }
     s1 = canon(s1 + redc(a1, c.p, c.pinv), c.p);
     if constexpr (TWO) s2 = canon(s2 + redc(a2, c.p, c.pinv), c.p);
@@ -455,7 +459,8 @@ __device__ __forceinline__ uint32_t newton_block(uint32_t a, int b0, int len, in
 __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
                                                  int njobs, uint32_t* ws, uint32_t* zero_word) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
-  extern __shared__ uint32_t S[];  // [IPAD + Dp]
+  extern __shared__ uint4 S4[];  // [IPAD + Dp] sliding operand, then [64] uniform operand
+  uint32_t* S = reinterpret_cast<uint32_t*>(S4);
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
   const ResJob J = jobs[job_list[jj]];
@@ -470,6 +475,14 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
   const uint32_t* FB = g_fblk + (int64_t)pi * IW_NBLK * 64;
   const int lane = threadIdx.x;
+  uint32_t* U = S + IPAD + Dp;  // 16-byte aligned: IPAD and Dp are multiples of 64
+  // the uniform operand of the next Toeplitz sums (one wavefront: the
+  // barriers only order its own LDS accesses)
+  auto stage_u = [&](uint32_t v) {
+    __syncthreads();
+    U[lane] = v;
+    __syncthreads();
+  };
   for (int t = lane; t < IPAD + Dp; t += 64) {
     const int j = t - IPAD;
     uint32_t w = 0;
@@ -489,14 +502,21 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
     const uint32_t* w1 = S + IPAD + b0 + lane;
     uint32_t s1 = 0, s2 = 0;
     if (ob + 1 < nblk) {
-      for (int ib = 0; ib <= ob; ++ib) toeplitz64_w<true>(s1, s2, uval(ib), w1 - 64 * ib, w1 + 64 - 64 * ib, c);
+      for (int ib = 0; ib <= ob; ++ib) {
+        stage_u(uval(ib));
+        toeplitz64_w<true>(s1, s2, U, w1 - 64 * ib, w1 + 64 - 64 * ib, c);
+      }
       uint32_t dummy = 0;
-      toeplitz64_w<false>(s2, dummy, uval(ob + 1), w1 - 64 * ob, w1, c);
+      stage_u(uval(ob + 1));
+      toeplitz64_w<false>(s2, dummy, U, w1 - 64 * ob, w1, c);
       Qg[b0 + lane] = newton_block(s1, b0, 64, lane, c);
       Qg[b0 + 64 + lane] = newton_block(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c);
     } else {
       uint32_t dummy = 0;
-      for (int ib = 0; ib <= ob; ++ib) toeplitz64_w<false>(s1, dummy, uval(ib), w1 - 64 * ib, w1, c);
+      for (int ib = 0; ib <= ob; ++ib) {
+        stage_u(uval(ib));
+        toeplitz64_w<false>(s1, dummy, U, w1 - 64 * ib, w1, c);
+      }
       Qg[b0 + lane] = newton_block(s1, b0, min(64, n1 - b0), lane, c);
     }
   }
@@ -513,7 +533,7 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   for (int j = nblk - 2; j >= 0; --j) {
     const int dN = dP + 64;
     const int nob = dN / 64 + 1;
-    const uint32_t fj = FB[j * 64 + lane];
+    stage_u(FB[j * 64 + lane]);
     const uint32_t qj = Qg[j * 64 + lane];
     for (int ob = nob - 1; ob >= 0; ob -= 2) {
       const uint32_t* p1 = S + IPAD + ob * 64 + lane;  // P[t - i] = p1[-i]
@@ -523,10 +543,10 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
       if (ob >= 1) {
         s2 = p1[-128];
         if (ob == 1) s2 = madd(s2, qj, c.p);
-        toeplitz64_w<true>(s1, s2, fj, p1, p1 - 64, c);
+        toeplitz64_w<true>(s1, s2, U, p1, p1 - 64, c);
       } else {
         uint32_t dummy = 0;
-        toeplitz64_w<false>(s1, dummy, fj, p1, p1, c);
+        toeplitz64_w<false>(s1, dummy, U, p1, p1, c);
       }
       __syncthreads();  // every lane's reads of the old blocks before the new values land
       S[IPAD + ob * 64 + lane] = s1;
@@ -541,7 +561,7 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
 void launch_interp_w(const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
                      int64_t nblocks, int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s) {
   if (nblocks <= 0) return;
-  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64) * sizeof(uint32_t);
+  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64 + 64) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_interp_w, dim3((unsigned)nblocks), dim3(64), lds, s, jobs_d, job_list_d, prefix_d, njobs,
                      ws, zero_word);
 }
