@@ -417,8 +417,8 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
 // block's old ones).  The uniform operand, 64 words, is staged in LDS too and
 // read four words at a time at one address for the whole wavefront (a
 // broadcast; no vector-unit instruction per word), shared by two output
-// blocks; the Newton blocks Q_j go to the workspace, the F_j come from their
-// table.
+// blocks; the Newton blocks Q_j (two Horner steps per iteration) go to the
+// workspace, the F_j come from their table.
 // ---------------------------------------------------------------------------
 // s1 += sum_q U[q] S1[-q], and (TWO) s2 += sum_q U[q] S2[-q], U in LDS
 // (16-byte aligned).  One reduction per 8 canonical products: their sum stays
@@ -443,15 +443,47 @@ __device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, const u
   }
 }
 
-// Newton block -> monomial: Q = sum_{s < len} a_{b0+s} prod_{t < s} (x - (b0 + t)), a_{b0+s} in lane s
-__device__ __forceinline__ uint32_t newton_block(uint32_t a, int b0, int len, int lane, const PrimeC& c) {
-  const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
-  uint32_t q = lane == 0 ? bcast(a, len - 1) : 0u;
-  for (int st = 0; st + 1 < len; ++st) {
-    const int kq = len - 2 - st;  // Q <- Q (x - (b0 + kq)) + a_{b0 + kq}
-    const uint32_t add = bcast(a, kq);
-    const uint32_t qprev = lane_shr1(q) + (lane == 0 ? add : 0u);
-    q = canon(redc((uint64_t)bcast(nk, kq) * q + ((uint64_t)qprev << 32), c.p, c.pinv), c.p);
+// Newton block -> monomial: Q = sum_{s < len} a_{b0+s} prod_{t < s} (x - (b0 + t)),
+// a_{b0+s} in lane s, by Horner's rule from the top with two steps per
+// iteration:
+//   Q <- (Q (x - c1) + a_k)(x - c2) + a_{k-1}
+//      = Q (x^2 + B x + A) + a_k x + (a_{k-1} - c2 a_k),
+// c1 = b0 + k, c2 = c1 - 1, A = c1 c2, B = -(c1 + c2): per coefficient two
+// products and one reduction, Q[i-1] and Q[i-2] by two lane shifts, instead
+// of two products and two reductions.  Lane it first computes iteration it's
+// constants (Montgomery forms of A and B, the corrections of coefficients 0
+// and 1) into K; a is staged in La.  La: 64 words, K: 4 x 32 words, 16-byte
+// aligned; one wavefront (the barriers order its own LDS accesses).  The sum
+// below REDC stays under 2p^2 + 2p 2^32 + 2^32 p < 2^64, its result under 4p.
+__device__ __forceinline__ uint32_t newton_block2(uint32_t a, int b0, int len, int lane, const PrimeC& c,
+                                                  uint32_t* La, uint32_t* K) {
+  __syncthreads();
+  La[lane] = a;
+  __syncthreads();
+  const int nit = (len - 1) / 2;
+  if (lane < nit) {
+    const int k = len - 2 - 2 * lane;                      // the iteration's first Horner index, >= 1
+    const uint32_t c1 = (uint32_t)(b0 + k), c2 = c1 - 1;  // below 2^13: c1 c2 < p
+    const uint32_t ak = La[k], ak1 = La[k - 1];
+    uint4 v;
+    v.x = to_mont(c1 * c2, c);
+    v.y = to_mont(c.p - c1 - c2, c);
+    v.z = msub(ak1, mmulc(to_mont(c2, c), ak, c.p, c.pinv), c.p);
+    v.w = ak;
+    reinterpret_cast<uint4*>(K)[lane] = v;
+  }
+  __syncthreads();
+  uint32_t q = lane == 0 ? La[len - 1] : 0u;
+  for (int it = 0; it < nit; ++it) {
+    const uint4 v = reinterpret_cast<const uint4*>(K)[it];
+    const uint32_t q1 = lane_shr1(q);
+    const uint32_t q2 = lane_shr1(q1) + (lane == 0 ? v.z : lane == 1 ? v.w : 0u);
+    q = canon(redc((uint64_t)v.x * q + (uint64_t)v.y * q1 + ((uint64_t)q2 << 32), c.p, c.pinv), c.p);
+  }
+  if ((len - 1) & 1) {  // the last step alone, k = 0
+    const uint32_t nk = to_mont(c.p - (uint32_t)b0, c);
+    const uint32_t qprev = lane_shr1(q) + (lane == 0 ? La[0] : 0u);
+    q = canon(redc((uint64_t)nk * q + ((uint64_t)qprev << 32), c.p, c.pinv), c.p);
   }
   return q;
 }
@@ -476,6 +508,7 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   const uint32_t* FB = g_fblk + (int64_t)pi * IW_NBLK * 64;
   const int lane = threadIdx.x;
   uint32_t* U = S + IPAD + Dp;  // 16-byte aligned: IPAD and Dp are multiples of 64
+  uint32_t* K = U + 64;         // constants of the Newton blocks' iterations
   // the uniform operand of the next Toeplitz sums (one wavefront: the
   // barriers only order its own LDS accesses)
   auto stage_u = [&](uint32_t v) {
@@ -509,15 +542,15 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
       uint32_t dummy = 0;
       stage_u(uval(ob + 1));
       toeplitz64_w<false>(s2, dummy, U, w1 - 64 * ob, w1, c);
-      Qg[b0 + lane] = newton_block(s1, b0, 64, lane, c);
-      Qg[b0 + 64 + lane] = newton_block(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c);
+      Qg[b0 + lane] = newton_block2(s1, b0, 64, lane, c, U, K);
+      Qg[b0 + 64 + lane] = newton_block2(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c, U, K);
     } else {
       uint32_t dummy = 0;
       for (int ib = 0; ib <= ob; ++ib) {
         stage_u(uval(ib));
         toeplitz64_w<false>(s1, dummy, U, w1 - 64 * ib, w1, c);
       }
-      Qg[b0 + lane] = newton_block(s1, b0, min(64, n1 - b0), lane, c);
+      Qg[b0 + lane] = newton_block2(s1, b0, min(64, n1 - b0), lane, c, U, K);
     }
   }
   __syncthreads();
@@ -561,7 +594,7 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
 void launch_interp_w(const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
                      int64_t nblocks, int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s) {
   if (nblocks <= 0) return;
-  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64 + 64) * sizeof(uint32_t);
+  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64 + 64 + 128) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_interp_w, dim3((unsigned)nblocks), dim3(64), lds, s, jobs_d, job_list_d, prefix_d, njobs,
                      ws, zero_word);
 }
