@@ -530,7 +530,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the headline batch, its parity and roofline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--cpu-sample-pairs", type=int, default=48)
+    ap.add_argument("--cpu-sample-pairs", type=int, default=64)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference for HBM byte counters)")
     ap.add_argument("--ceilings", action="store_true",
