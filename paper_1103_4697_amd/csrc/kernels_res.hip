@@ -421,25 +421,38 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
 // workspace, the F_j come from their table.
 // ---------------------------------------------------------------------------
 // s1 += sum_q U[q] S1[-q], and (TWO) s2 += sum_q U[q] S2[-q], U in LDS
-// (16-byte aligned).  One reduction per 8 canonical products: their sum stays
-// below 8 p^2, so REDC's sum below 8 p^2 + 2^32 p < 2^64 and its result below
-// 3p, and s + REDC below 4p < 2^32 (16 products could exceed both bounds).
+// (16-byte aligned).  Sixteen canonical products per reduction: their sum a
+// stays below 16 p^2 < 2^64, and a 2^-32 = hi + REDC(lo) mod p splits it
+// without REDC's own sum (which could pass 2^64): hi = a >> 32 < 4p is taken
+// below 2p, REDC(lo) = mulhi(lo pinv, p) + (lo != 0) <= p (lo plus the low
+// word of m p is 0 mod 2^32), so hi + REDC(lo) < 3p and s + it < 4p.
+__device__ __forceinline__ uint32_t fold16(uint32_t s, uint64_t a, const PrimeC& c) {
+  uint32_t hi = (uint32_t)(a >> 32);
+  const uint32_t h2 = hi - 2 * c.p;
+  hi = h2 < hi ? h2 : hi;
+  const uint32_t lo = (uint32_t)a;
+  const uint32_t r = __umulhi(lo * c.pinv, c.p) + (lo != 0u ? 1u : 0u);
+  return canon(s + hi + r, c.p);
+}
+
 template <bool TWO>
 __device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, const uint32_t* U, const uint32_t* S1,
                                              const uint32_t* S2, const PrimeC& c) {
 #pragma unroll
-  for (int g = 0; g < 64; g += 8) {
-    const uint4 ua = *reinterpret_cast<const uint4*>(U + g), ub = *reinterpret_cast<const uint4*>(U + g + 4);
-    const uint32_t w8[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
+  for (int g = 0; g < 64; g += 16) {
+    const uint4* U4 = reinterpret_cast<const uint4*>(U + g);
+    const uint4 ua = U4[0], ub = U4[1], uc = U4[2], ud = U4[3];
+    const uint32_t w16[16] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w,
+                              uc.x, uc.y, uc.z, uc.w, ud.x, ud.y, ud.z, ud.w};
     uint64_t a1 = 0, a2 = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const uint64_t w = w8[q];
+    for (int q = 0; q < 16; ++q) {
+      const uint64_t w = w16[q];
       a1 += w * S1[-(g + q)];
       if constexpr (TWO) a2 += w * S2[-(g + q)];
     }
-    s1 = canon(s1 + redc(a1, c.p, c.pinv), c.p);
-    if constexpr (TWO) s2 = canon(s2 + redc(a2, c.p, c.pinv), c.p);
+    s1 = fold16(s1, a1, c);
+    if constexpr (TWO) s2 = fold16(s2, a2, c);
   }
 }
 
