@@ -539,28 +539,37 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
     S[t] = w;
   }
   __syncthreads();
-  auto uval = [&](int ib) {  // u_{64 ib + lane} = v / (64 ib + lane)!
+  // u_{64 ib + lane} = v / (64 ib + lane)! from the loaded pair (v, 1/i!); the
+  // loads of the next input block are issued before the current block's
+  // Toeplitz sums, which hide their latency
+  uint32_t vn = 0, fn = 0;
+  auto load_u = [&](int ib) {
     const int i = 64 * ib + lane;
-    return i < n1 ? mmulc(canon(V[i], c.p), IF[i], c.p, c.pinv) : 0u;
+    vn = i < n1 ? V[i] : 0u;
+    fn = i < n1 ? IF[i] : 0u;
   };
+  auto uval = [&]() { return mmulc(canon(vn, c.p), fn, c.p, c.pinv); };
   for (int ob = 0; ob < nblk; ob += 2) {
     const int b0 = ob * 64;
     const uint32_t* w1 = S + IPAD + b0 + lane;
     uint32_t s1 = 0, s2 = 0;
+    load_u(0);
     if (ob + 1 < nblk) {
       for (int ib = 0; ib <= ob; ++ib) {
-        stage_u(uval(ib));
+        stage_u(uval());
+        load_u(ib + 1);
         toeplitz64_w<true>(s1, s2, U, w1 - 64 * ib, w1 + 64 - 64 * ib, c);
       }
       uint32_t dummy = 0;
-      stage_u(uval(ob + 1));
+      stage_u(uval());
       toeplitz64_w<false>(s2, dummy, U, w1 - 64 * ob, w1, c);
       Qg[b0 + lane] = newton_block2(s1, b0, 64, lane, c, U, K);
       Qg[b0 + 64 + lane] = newton_block2(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c, U, K);
     } else {
       uint32_t dummy = 0;
       for (int ib = 0; ib <= ob; ++ib) {
-        stage_u(uval(ib));
+        stage_u(uval());
+        if (ib < ob) load_u(ib + 1);
         toeplitz64_w<false>(s1, dummy, U, w1 - 64 * ib, w1, c);
       }
       Qg[b0 + lane] = newton_block2(s1, b0, min(64, n1 - b0), lane, c, U, K);
