@@ -131,7 +131,7 @@ int snc_microbench(snc_ctx* ctx, int kind, int32_t iters, void* d_buf, size_t bu
 /* Autotuner of the evaluation kernel (Section 4, "Symbolic Speedups": the
  * problems over prime fields are distributed over the device).  For each
  * register class of the fused evaluation + elimination kernel (largest
- * y-degree 8, 16, 32, 48, 64) a batch uses, the launch variant is chosen:
+ * y-degree 8, 16, 32, 40, 48, 64) a batch uses, the launch variant is chosen:
  * wpe = minimum wavefronts per SIMD the register allocation is held to
  * (1 = unconstrained .. 4), chunk = 0 for one workgroup per block of 64
  * points or the number of blocks a persistent workgroup takes at a time

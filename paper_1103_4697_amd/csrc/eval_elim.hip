@@ -13,11 +13,12 @@ namespace snc {
 SNC_EXTERN_CLASS(8)
 SNC_EXTERN_CLASS(16)
 SNC_EXTERN_CLASS(32)
+SNC_EXTERN_CLASS(40)
 SNC_EXTERN_CLASS(48)
 SNC_EXTERN_CLASS(64)
 #undef SNC_EXTERN_CLASS
 
-static const int kClassCap[] = {8, 16, 32, 48, 64};
+static const int kClassCap[] = {8, 16, 32, 40, 48, 64};
 
 int fast_class_of(int maxy) {
   for (int i = 0; i < (int)(sizeof(kClassCap) / sizeof(int)); ++i)
@@ -31,6 +32,7 @@ int eval_elim_grid(int cls, int wpe, int max_T) {
     case 8: return eval_elim_grid_cls<8>(wpe, max_T);
     case 16: return eval_elim_grid_cls<16>(wpe, max_T);
     case 32: return eval_elim_grid_cls<32>(wpe, max_T);
+    case 40: return eval_elim_grid_cls<40>(wpe, max_T);
     case 48: return eval_elim_grid_cls<48>(wpe, max_T);
     default: return eval_elim_grid_cls<64>(wpe, max_T);
   }
@@ -48,6 +50,7 @@ void launch_eval_elim(int cls, const EEVariant& v, uint32_t* counter, const ResJ
     case 8: SNC_EE(8); break;
     case 16: SNC_EE(16); break;
     case 32: SNC_EE(32); break;
+    case 40: SNC_EE(40); break;
     case 48: SNC_EE(48); break;
     default: SNC_EE(64); break;
   }

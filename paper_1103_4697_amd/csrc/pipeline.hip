@@ -224,8 +224,8 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   if (tm) tm->mark("reduce", lay.reduce_in_eval ? 0 : 1);
   // one stage per register class (names: eval_elim_<width>), then the
   // jobs above the register classes
-  static const char* const kEEStage[NCLS] = {"eval_elim_8", "eval_elim_16", "eval_elim_32", "eval_elim_48",
-                                             "eval_elim_64"};
+  static const char* const kEEStage[NCLS] = {"eval_elim_8", "eval_elim_16", "eval_elim_32", "eval_elim_40",
+                                             "eval_elim_48", "eval_elim_64"};
   uint32_t* ee_counters = (uint32_t*)(ws + lay.ee_counter_off);
   bool persistent = false;
   for (int c = 0; c < NCLS; ++c) persistent |= lay.n_ee_jobs[c] && lay.ee_var[c].chunk > 0;

@@ -13,7 +13,7 @@
 
 namespace snc {
 
-constexpr int NCLS = 5;        // register classes of the fused evaluate+eliminate kernel
+constexpr int NCLS = 6;        // register classes of the fused evaluate+eliminate kernel
 
 struct Tables {
   std::vector<uint32_t> p;       // primes, descending below 2^30

@@ -363,7 +363,7 @@ def _class_spanning_pairs(seed):
     64, with ragged point tiles, small and multi-word coefficients and one
     planted common factor (resultant 0)."""
     rng = np.random.default_rng(seed)
-    shapes = [(12, 10, 16, 20), (20, 17, 24, 12), (30, 26, 8, 32), (40, 36, 16, 16), (44, 50, 10, 12),
+    shapes = [(12, 10, 16, 20), (20, 17, 24, 12), (30, 26, 8, 32), (40, 36, 16, 16), (44, 46, 10, 12),
               (60, 58, 8, 8)]
     pairs = [synth.random_pair(rng, *sh) for sh in shapes]
     pairs.append(synth.common_factor_pair(rng, 38, 35, 12, 12))
@@ -390,24 +390,24 @@ def test_eval_variants_identical(snc, assert_same):
     assert zx.evaluate(ref[3], x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61)
     for wpe in (1, 2, 3, 4):
         for chunk in (0, 1, 4):
-            for cap in (16, 32, 48, 64):
+            for cap in (16, 32, 40, 48, 64):
                 ctx.set_eval_variant(cap, wpe, chunk)
             got = snc.resultant_y_batch(pairs, ctx)
             rep, _ = ctx.tuning()
             assert {e["source"] for e in rep} == {"forced"}
             assert all(e["wpe"] == wpe and e["chunk"] == chunk for e in rep)
             assert_same(got, ref, f"variant {(wpe, chunk)}")
-    for cap in (16, 32, 48, 64):
+    for cap in (16, 32, 40, 48, 64):
         ctx.set_eval_variant(cap, 0, 0)
     # the prepared graph of a persistent variant replayed several times
-    for cap in (16, 32, 48, 64):
+    for cap in (16, 32, 40, 48, 64):
         ctx.set_eval_variant(cap, 2, 1)
     b = snc.ResultantBatch(pairs, ctx)
     for _ in range(3):
         b.run()
         assert_same(b.results(), ref)
     b.close()
-    for cap in (16, 32, 48, 64):
+    for cap in (16, 32, 40, 48, 64):
         ctx.set_eval_variant(cap, 0, 0)
 
 
@@ -423,7 +423,7 @@ def test_autotuner_measures_and_caches(snc, assert_same):
     b = snc.ResultantBatch(pairs, ctx)
     rep, tune_ms = ctx.tuning()
     assert tune_ms > 0.0
-    assert {e["class"] for e in rep} == {16, 32, 48, 64}
+    assert {e["class"] for e in rep} == {16, 32, 40, 48, 64}
     for e in rep:
         assert e["source"] == "measured"
         assert e["candidates"] >= 4
