@@ -1007,37 +1007,64 @@ __global__ __launch_bounds__(64) void k_crt_small(const ResJob* jobs, const int3
   const int t = live ? t0 : J.D;  // lanes past the last coefficient repeat it and store nothing
   const int k = J.k, n1 = J.D + 1;
   const uint32_t* V = ws + J.val_off + t;
-  for (int i = 0; i < k; ++i) {
-    const PrimeC c = g_primes[i];
-    const uint32_t* w = g_wts + i * CRT_KS;
-    uint32_t S = 0;  // < 2p
-    for (int j0 = 0; j0 < i; j0 += 16) {
-      // y_j < p and W < p: sixteen products stay below 2^64 (four partial
-      // sums); sum 2^-32 = hi + REDC(lo), hi < 4p, REDC(lo) <= p.  Past the
-      // last digit (j >= i) the table row is zero and the digit slots hold
-      // finite values (stale or not yet written; KC is a multiple of 16, so
-      // they lie in yl): the products are zero, with no bounds on the loads,
-      // and the sixteen weights come in four 16-byte scalar loads.
-      const uint4* w4 = reinterpret_cast<const uint4*>(w + j0);
-      const uint4 wa = w4[0], wb = w4[1], wc = w4[2], wd = w4[3];
-      const uint32_t wv[16] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w,
-                               wc.x, wc.y, wc.z, wc.w, wd.x, wd.y, wd.z, wd.w};
-      uint64_t part[4] = {0, 0, 0, 0};
+  // Digits four at a time: the sums of rows i0..i0+3 over the digits before
+  // i0 share each digit read (groups of sixteen: y_j < p_j and W < p_i, so
+  // sixteen products stay below 2^64), then the block's own digits follow in
+  // order with their products inside the block.  The digit slots start at
+  // zero, so a group that reaches past i0 reads zeros for the digits not
+  // computed yet (each lane reads only its own slots: no barrier).
+  for (int j = 0; j < KC; ++j) yl[64 * j + lane] = 0u;
+  // S < 2p, a sum below 2^64: S + a 2^-32 = S + hi + REDC(lo) with hi < 4p
+  // taken below 2p and REDC(lo) <= p, back below 2p
+  auto fold = [](uint32_t S, uint64_t a, const PrimeC& c) {
+    uint32_t hi = (uint32_t)(a >> 32);
+    const uint32_t h2 = hi - 2 * c.p;
+    hi = h2 < hi ? h2 : hi;                                       // [0, 2p)
+    uint32_t v = hi + redc((uint64_t)(uint32_t)a, c.p, c.pinv);  // < 3p + 1
+    const uint32_t v2 = v - 2 * c.p;
+    v = v2 < v ? v2 : v;  // [0, 2p)
+    S += v;
+    const uint32_t s2 = S - 2 * c.p;
+    return s2 < S ? s2 : S;  // [0, 2p)
+  };
+  for (int i0 = 0; i0 < k; i0 += 4) {
+    PrimeC cr[4];
+    uint32_t S[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int u = 0; u < 16; ++u) part[u & 3] += (uint64_t)yl[64 * (j0 + u) + lane] * wv[u];
-      const uint64_t sum = (part[0] + part[1]) + (part[2] + part[3]);
-      uint32_t hi = (uint32_t)(sum >> 32);
-      const uint32_t h2 = hi - 2 * c.p;
-      hi = h2 < hi ? h2 : hi;                                         // [0, 2p)
-      uint32_t v = hi + redc((uint64_t)(uint32_t)sum, c.p, c.pinv);  // < 3p + 1
-      const uint32_t v2 = v - 2 * c.p;
-      v = v2 < v ? v2 : v;  // [0, 2p)
-      S += v;
-      const uint32_t s2 = S - 2 * c.p;
-      S = s2 < S ? s2 : S;  // [0, 2p)
+    for (int r = 0; r < 4; ++r) cr[r] = g_primes[i0 + r];  // i0 + 3 < KC: rows of the table exist
+    for (int j0 = 0; j0 < i0; j0 += 16) {
+      uint32_t wv[4][16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint4* w4 = reinterpret_cast<const uint4*>(g_wts + (i0 + r) * CRT_KS + j0);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const uint4 x = w4[h];
+          wv[r][4 * h] = x.x; wv[r][4 * h + 1] = x.y; wv[r][4 * h + 2] = x.z; wv[r][4 * h + 3] = x.w;
+        }
+      }
+      uint64_t acc[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const uint64_t y = yl[64 * (j0 + u) + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] += y * wv[r][u];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S[r] = fold(S[r], acc[r], cr[r]);
     }
-    const uint32_t r = V[(int64_t)i * n1];
-    yl[64 * i + lane] = canon(redc((uint64_t)msub(r, canon2(S, c.p), c.p) * g_garner[i], c.p, c.pinv), c.p);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + r;
+      if (i >= k) break;  // uniform
+      uint64_t a = 0;
+#pragma unroll
+      for (int q = 0; q < r; ++q) a += (uint64_t)yl[64 * (i0 + q) + lane] * g_wts[i * CRT_KS + i0 + q];
+      const uint32_t Sf = fold(S[r], a, cr[r]);
+      const uint32_t rv = V[(int64_t)i * n1];
+      yl[64 * i + lane] =
+          canon(redc((uint64_t)msub(rv, canon2(Sf, cr[r].p), cr[r].p) * g_garner[i], cr[r].p, cr[r].pinv), cr[r].p);
+    }
   }
   uint32_t X[LC];
 #pragma unroll
