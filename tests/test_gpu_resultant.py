@@ -89,7 +89,7 @@ def test_register_classes_and_ragged_tiles(snc):
 FIRST_REMAINDER_SHAPES = [(48, 47), (47, 46), (48, 48), (47, 47), (48, 1), (48, 2), (40, 8), (41, 15),
                           (45, 31), (33, 32), (32, 32), (32, 1), (30, 16), (17, 16), (16, 16), (16, 7),
                           (9, 9), (8, 8), (8, 7), (8, 2), (7, 1), (64, 64), (64, 63), (64, 5), (4, 4),
-                          (3, 2), (2, 1)]
+                          (3, 2), (2, 1), (40, 40), (40, 39), (40, 1), (39, 38), (36, 20)]
 
 
 def test_first_remainder_shapes(snc, assert_same):
@@ -103,7 +103,7 @@ def test_first_remainder_shapes(snc, assert_same):
         assert len(r) - 1 <= snc.resultant_plan(f, g).deg_bound, (m, n)
         for x0 in (0, 1, rs.randrange(Q61)):
             assert zx.evaluate(r, x0) % Q61 == R.resultant_at_mod(f, g, x0, Q61), (m, n, x0)
-    for i in (0, 2, 4, 21):
+    for i in (0, 2, 4, 21, 27):
         assert_same(snc.resultant_y(*pairs[i]), batch[i])
 
 
