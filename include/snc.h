@@ -190,20 +190,24 @@ int snc_prepared_destroy(snc_prepared* prep);
 /* Pipelined runs of a prepared batch, for callers that run it repeatedly and
  * want throughput: snc_prepared_submit enqueues one run of the device
  * pipeline on stream, a device copy of its output block into one of two
- * staging slots, and the download of that slot to pinned host memory on a
- * second stream of the context; it returns at once with a ticket (0, 1, 2,
- * ... per handle).  The next submit's kernels start right after the copy,
- * while the previous run's results travel.  snc_prepared_collect waits for
- * the ticket's download and writes its n results into out (conventions of
- * snc_prepared_run; SNC_ERANGE leaves the run outstanding).  At most two
- * runs are outstanding: a third submit gives SNC_EAGAIN until one is
- * collected; collecting a ticket that is not outstanding gives SNC_EINVAL.
+ * staging slots in d_stage (caller-owned device memory of at least
+ * snc_prepared_stage_bytes(prep) bytes, 0 for a batch of trivial pairs; it
+ * must stay valid until every submitted run is collected), and the download
+ * of that slot to pinned host memory on a second stream of the context; it
+ * returns at once with a ticket (0, 1, 2, ... per handle).  The next
+ * submit's kernels start right after the copy, while the previous run's
+ * results travel.  snc_prepared_collect waits for the ticket's download and
+ * writes its n results into out (conventions of snc_prepared_run;
+ * SNC_ERANGE leaves the run outstanding).  At most two runs are
+ * outstanding: a third submit gives SNC_EAGAIN until one is collected;
+ * collecting a ticket that is not outstanding gives SNC_EINVAL; a staging
+ * buffer smaller than needed gives SNC_ENOMEM with the sizes in the message.
  * Every run of a handle (submitted or snc_prepared_run) goes to one stream:
- * runs share the workspace and are ordered by that stream only.
- * The slots (two copies of the output block on the device and two in pinned
- * host memory) are allocated on the first submit and freed with the handle,
+ * runs share the workspace and are ordered by that stream only.  The pinned
+ * host slots are allocated on the first submit and freed with the handle,
  * which first waits for any uncollected download. */
-int snc_prepared_submit(snc_prepared* prep, void* stream, int64_t* ticket);
+size_t snc_prepared_stage_bytes(const snc_prepared* prep);
+int snc_prepared_submit(snc_prepared* prep, void* d_stage, size_t stage_bytes, void* stream, int64_t* ticket);
 int snc_prepared_collect(snc_prepared* prep, int64_t ticket, snc_upoly* out);
 
 /* One resultant with no allocation, for callers that cannot allocate (code

@@ -83,7 +83,8 @@ def lib():
                 "snc_resultant_y_batch": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(Upoly)]),
                 "snc_resultant_y_prepare": (C.c_int, [VP, I32, P(Bipoly), P(Bipoly), VP, SZ, VP, P(VP)]),
                 "snc_prepared_run": (C.c_int, [VP, VP, P(Upoly)]),
-                "snc_prepared_submit": (C.c_int, [VP, VP, P(C.c_int64)]),
+                "snc_prepared_stage_bytes": (SZ, [VP]),
+                "snc_prepared_submit": (C.c_int, [VP, VP, SZ, VP, P(C.c_int64)]),
                 "snc_prepared_collect": (C.c_int, [VP, C.c_int64, P(Upoly)]),
                 "snc_prepared_destroy": (C.c_int, [VP]),
                 "snc_server_create": (C.c_int, [VP, VP, SZ, I32, I32, P(VP)]),
@@ -428,11 +429,17 @@ class ResultantBatch:
 
     def submit(self, stream=None) -> int:
         """Enqueue one run and the download of its results
-        (snc_prepared_submit); returns its ticket.  The next submit's kernels
-        overlap this run's download.  At most two runs are outstanding."""
+        (snc_prepared_submit, device staging in a tensor owned by this
+        object); returns its ticket.  The next submit's kernels overlap this
+        run's download.  At most two runs are outstanding."""
+        import torch
+        if not hasattr(self, "stage"):
+            nb = lib().snc_prepared_stage_bytes(self.h)
+            self.stage = torch.empty(max(nb, 256), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
         t = C.c_int64(-1)
-        self.ctx.check(lib().snc_prepared_submit(self.h, self.ctx.stream_handle(stream), C.byref(t)),
-                       "snc_prepared_submit")
+        self.ctx.check(lib().snc_prepared_submit(self.h, C.c_void_p(self.stage.data_ptr()),
+                                                 C.c_size_t(self.stage.numel()), self.ctx.stream_handle(stream),
+                                                 C.byref(t)), "snc_prepared_submit")
         return t.value
 
     def collect(self, ticket: int):

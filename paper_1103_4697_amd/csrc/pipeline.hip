@@ -655,8 +655,18 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out) {
   return SNC_OK;
 }
 
-int submit_prepared(snc_prepared* pr, hipStream_t stream, int64_t* ticket) {
+size_t prepared_stage_bytes(const snc_prepared* pr) {
+  return pr->lay.dev.empty() ? 0 : 2 * align_words(pr->lay.out_words) * 4;
+}
+
+int submit_prepared(snc_prepared* pr, void* d_stage, size_t stage_bytes, hipStream_t stream, int64_t* ticket) {
   snc_ctx* c = pr->c;
+  const size_t need = prepared_stage_bytes(pr);
+  if (stage_bytes < need || (need && !d_stage)) {
+    c->err = "snc_prepared_submit: staging buffer of " + std::to_string(stage_bytes) + " bytes, " +
+             std::to_string(need) + " needed (snc_prepared_stage_bytes)";
+    return SNC_ENOMEM;
+  }
   int s = (int)(pr->next_ticket & 1);
   if (pr->slot_ticket[s] >= 0) s ^= 1;
   if (pr->slot_ticket[s] >= 0) {
@@ -665,24 +675,23 @@ int submit_prepared(snc_prepared* pr, hipStream_t stream, int64_t* ticket) {
   }
   HIPCHK(hipSetDevice(c->device));
   const size_t bytes = pr->lay.out_words * 4;
-  if (bytes && !pr->slot_dev[s]) {
-    HIPCHK(hipMalloc((void**)&pr->slot_dev[s], bytes));
+  if (bytes && !pr->slot_host[s]) {
     HIPCHK(hipHostMalloc(&pr->slot_host[s], bytes, hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&pr->slot_copied[s], hipEventDisableTiming));
   }
   if (!c->side_stream) HIPCHK(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
   if (!pr->lay.dev.empty()) {
+    uint8_t* slot = (uint8_t*)d_stage + (size_t)s * (need / 2);
     StageTimer tm{c, stream, false};
     const int st = launch_prepared_all(pr, stream, tm);
     if (st) return st;
     // the output region goes to the slot on the device (a short copy on
     // this stream), and from there to the host on the side stream, so the
     // next run's kernels can start right after this copy
-    HIPCHK(hipMemcpyAsync(pr->slot_dev[s], pr->ws + pr->lay.out_off, bytes, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(slot, pr->ws + pr->lay.out_off, bytes, hipMemcpyDeviceToDevice, stream));
     HIPCHK(hipEventRecord(pr->slot_copied[s], stream));
     HIPCHK(hipStreamWaitEvent(c->side_stream, pr->slot_copied[s], 0));
-    const int st2 = enqueue_chunks(pr, chunk_bounds(pr->lay), pr->slot_dev[s], pr->slot_host[s], pr->slot_ev[s],
-                                   c->side_stream);
+    const int st2 = enqueue_chunks(pr, chunk_bounds(pr->lay), slot, pr->slot_host[s], pr->slot_ev[s], c->side_stream);
     if (st2) return st2;
   }
   pr->slot_ticket[s] = pr->next_ticket;
@@ -753,7 +762,6 @@ void destroy_prepared(snc_prepared* pr) {
   for (int s = 0; s < 2; ++s) {
     // an uncollected run's download must end before its buffers go
     if (pr->slot_ticket[s] >= 0 && !pr->slot_ev[s].empty()) (void)hipEventSynchronize(pr->slot_ev[s].back());
-    if (pr->slot_dev[s]) (void)hipFree(pr->slot_dev[s]);
     if (pr->slot_host[s]) (void)hipHostFree(pr->slot_host[s]);
     if (pr->slot_copied[s]) (void)hipEventDestroy(pr->slot_copied[s]);
     for (hipEvent_t e : pr->slot_ev[s]) (void)hipEventDestroy(e);

@@ -423,9 +423,11 @@ int snc_prepared_run(snc_prepared* p, void* stream, snc_upoly* out) {
   return run_prepared(p, (hipStream_t)stream, out);
 }
 
-int snc_prepared_submit(snc_prepared* p, void* stream, int64_t* ticket) {
+size_t snc_prepared_stage_bytes(const snc_prepared* p) { return p ? prepared_stage_bytes(p) : 0; }
+
+int snc_prepared_submit(snc_prepared* p, void* d_stage, size_t stage_bytes, void* stream, int64_t* ticket) {
   if (!p || !ticket) return SNC_EINVAL;
-  return submit_prepared(p, (hipStream_t)stream, ticket);
+  return submit_prepared(p, d_stage, stage_bytes, (hipStream_t)stream, ticket);
 }
 
 int snc_prepared_collect(snc_prepared* p, int64_t ticket, snc_upoly* out) {

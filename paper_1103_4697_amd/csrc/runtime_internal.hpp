@@ -153,8 +153,8 @@ struct snc_prepared {
   std::shared_ptr<void> sq_cache;    // the projection step's plan, built on the first run
   std::vector<int> sq_ranges;        // (register class, first item, items, largest degree) per launch
   // pipelined runs (snc_prepared_submit / _collect): two staging slots of the
-  // output block, on the device and in pinned host memory
-  uint8_t* slot_dev[2] = {nullptr, nullptr};
+  // output block, on the device (the caller's staging buffer) and in pinned
+  // host memory
   void* slot_host[2] = {nullptr, nullptr};
   int64_t slot_ticket[2] = {-1, -1};            // the run a slot holds, -1 free
   hipEvent_t slot_copied[2] = {nullptr, nullptr};  // output region copied into the slot
@@ -181,7 +181,8 @@ int run_prepared(snc_prepared* pr, hipStream_t stream, snc_upoly* out);
 // pipelined runs: submit enqueues a run and the download of its results
 // into a free staging slot (SNC_EAGAIN when both hold uncollected runs);
 // collect waits for a ticket's download and widens it into out
-int submit_prepared(snc_prepared* pr, hipStream_t stream, int64_t* ticket);
+size_t prepared_stage_bytes(const snc_prepared* pr);
+int submit_prepared(snc_prepared* pr, void* d_stage, size_t stage_bytes, hipStream_t stream, int64_t* ticket);
 int collect_prepared(snc_prepared* pr, int64_t ticket, snc_upoly* out);
 // the pipeline with a second branch after the interpolation: branch(stream)
 // enqueues work that follows the interpolation on `stream` while the Chinese

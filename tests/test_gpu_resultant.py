@@ -492,6 +492,14 @@ def test_pipelined_submit_collect(snc, assert_same):
     assert [t0, t1, t2] == [0, 1, 2]
     for i in common:
         assert ref[i] == []
+    # a staging buffer below snc_prepared_stage_bytes is refused before any work
+    import ctypes
+    need = snc.lib().snc_prepared_stage_bytes(b.h)
+    assert need >= 2 * 4 * sum(len(r) for r in ref)
+    t = ctypes.c_int64(-1)
+    st = snc.lib().snc_prepared_submit(b.h, ctypes.c_void_p(b.stage.data_ptr()), ctypes.c_size_t(need - 1),
+                                       b.ctx.stream_handle(None), ctypes.byref(t))
+    assert st == snc.SNC_ENOMEM and t.value == -1
     t3 = b.submit()
     assert t3 == 3
     b.close()                    # waits for the outstanding download
