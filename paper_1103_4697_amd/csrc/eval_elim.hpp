@@ -134,10 +134,6 @@ __device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* 
   }
 }
 
-// One remainder step X <- prem(X, Y) on the first C+1 entries of the
-// register arrays (X of formal degree a <= C, Y of degree b >= 1, entries
-// above each degree zero).  Branch-free inside an elementary step.  Returns
-// lc(Y), canonical.
 // Lane state of the elimination: every remainder so far of its expected
 // degree (EL_NORMAL); the first remainder whose leading coefficient vanished
 // was zero altogether (EL_ZERO: the two polynomials share a factor of
@@ -165,6 +161,10 @@ __device__ __forceinline__ void lead_check(uint32_t (&X)[N + 1], int& st, const 
   }
 }
 
+// One remainder X <- prem(X, Y) by s elementary steps on the first C+1
+// entries of the register arrays (X of formal degree a <= C, Y of degree
+// b >= 1, entries above each degree zero).  Branch-free inside an
+// elementary step.  Returns lc(Y), canonical.
 template <int N, int C>
 __device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (&Y)[N + 1], int s, int& st,
                                           const PrimeC& c) {
@@ -175,7 +175,7 @@ __device__ __forceinline__ uint32_t rem_c(uint32_t (&X)[N + 1], const uint32_t (
 #pragma unroll
     for (int i = 0; i < C; ++i)
       X[i] = redc_mv((uint64_t)lcY * X[i + 1] + (uint64_t)nlX * Y[i + 1], c.p, c.pinv);
-    X[C] = 0;
+    X[C] = zero_v();
   }
   lead_check<N, C>(X, st, c);
   return lcY;
