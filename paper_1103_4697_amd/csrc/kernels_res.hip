@@ -302,8 +302,23 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// sum_{q<64} U[q] * S[-q] with U uniform (lane q of u) and S per lane; s canonical in, out
-__device__ __forceinline__ uint32_t toeplitz64(uint32_t s, uint32_t u, const uint32_t* S, const PrimeC& c) {
+// s + a 2^-32 mod p for a sum a of sixteen canonical products: a stays below
+// 16 p^2 < 2^64, and a 2^-32 = hi + REDC(lo) mod p splits it without REDC's
+// own sum (which could pass 2^64): hi = a >> 32 < 4p is taken below 2p,
+// REDC(lo) = mulhi(lo pinv, p) + (lo != 0) <= p (lo plus the low word of m p
+// is 0 mod 2^32), so hi + REDC(lo) < 3p and s + it < 4p.
+__device__ __forceinline__ uint32_t fold16(uint32_t s, uint64_t a, const PrimeC& c) {
+  uint32_t hi = (uint32_t)(a >> 32);
+  const uint32_t h2 = hi - 2 * c.p;
+  hi = h2 < hi ? h2 : hi;
+  const uint32_t lo = (uint32_t)a;
+  const uint32_t r = __umulhi(lo * c.pinv, c.p) + (lo != 0u ? 1u : 0u);
+  return canon(s + hi + r, c.p);
+}
+
+// s + sum_{q<64} u_q S[-q] with u_q = lane q of u (broadcast by readlane) and
+// S per lane; s canonical in, out
+__device__ __forceinline__ uint32_t toeplitz64_bc(uint32_t s, uint32_t u, const uint32_t* S, const PrimeC& c) {
 #pragma unroll
   for (int g = 0; g < IB; g += 8) {
     uint64_t acc = 0;
@@ -314,10 +329,29 @@ __device__ __forceinline__ uint32_t toeplitz64(uint32_t s, uint32_t u, const uin
   return s;
 }
 
+// The same with U in LDS (16-byte aligned), read four words at a time at one
+// address for the whole wavefront (no vector-unit instruction per word), and
+// sixteen products per reduction (fold16).
+__device__ __forceinline__ uint32_t toeplitz64(uint32_t s, const uint32_t* U, const uint32_t* S, const PrimeC& c) {
+#pragma unroll
+  for (int g = 0; g < IB; g += 16) {
+    const uint4* U4 = reinterpret_cast<const uint4*>(U + g);
+    const uint4 ua = U4[0], ub = U4[1], uc = U4[2], ud = U4[3];
+    const uint32_t w16[16] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w,
+                              uc.x, uc.y, uc.z, uc.w, ud.x, ud.y, ud.z, ud.w};
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += (uint64_t)w16[q] * S[-(g + q)];
+    s = fold16(s, acc, c);
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, const int64_t* prefix,
                                                            int njobs, uint32_t* ws, uint32_t* zero_word) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
-  extern __shared__ uint32_t sm[];
+  extern __shared__ uint4 sm4[];  // sections 16-byte aligned: IPAD and Dp are multiples of 64 words
+  uint32_t* sm = reinterpret_cast<uint32_t*>(sm4);
   constexpr int NW = INTERP_THREADS / 64;
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
@@ -355,15 +389,19 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
     // a_k for k = b0 + lane
     const uint32_t* wk = Wp + IPAD + b0 + lane;
     uint32_t a = 0;
-    for (int ib = 0; ib <= ob; ++ib) a = toeplitz64(a, U[ib * IB + lane], wk - ib * IB, c);
-    // Q_ob and F_ob, coefficient of x^lane in lane
+    for (int ib = 0; ib <= ob; ++ib) a = toeplitz64(a, U + ib * IB, wk - ib * IB, c);
+    // Q_ob and F_ob, coefficient of x^lane in lane (F_ob from its table when
+    // the block has one)
     const int len = min(IB, n1 - b0);
     const uint32_t nk = to_mont(c.p - (uint32_t)(b0 + lane), c);  // -(b0 + lane)
     uint32_t q = lane == 0 ? bcast(a, len - 1) : 0u;
-    uint32_t f = lane == 0 ? c.r1 : 0u;
+    const bool ftab = ob < IW_NBLK;  // uniform
+    uint32_t f = ftab ? g_fblk[((int64_t)pi * IW_NBLK + ob) * 64 + lane] : (lane == 0 ? c.r1 : 0u);
     for (int s = 0; s < IB; ++s) {
-      const uint32_t fprev = lane_shr1(f);  // F <- F (x - (b0 + s))
-      f = canon(redc((uint64_t)bcast(nk, s) * f + ((uint64_t)fprev << 32), c.p, c.pinv), c.p);
+      if (!ftab) {
+        const uint32_t fprev = lane_shr1(f);  // F <- F (x - (b0 + s))
+        f = canon(redc((uint64_t)bcast(nk, s) * f + ((uint64_t)fprev << 32), c.p, c.pinv), c.p);
+      }
       const int kq = len - 2 - s;           // Q <- Q (x - (b0 + kq)) + a_{b0 + kq}
       if (kq >= 0) {
         const uint32_t add = bcast(a, kq);
@@ -392,13 +430,12 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
   for (int j = nblk - 2; j >= 0; --j) {
     const int dN = dP + IB;
     const int nob = dN / IB + 1;
-    const uint32_t fj = Fb[j * IB + lane];
     for (int ob = wave; ob < nob; ob += NW) {
       const int t = ob * IB + lane;
       const uint32_t* pt = Pa + IPAD + t;  // P[t - i] = pt[-i]
       uint32_t s = pt[-IB];                // x^64 term of F_j
       if (t < IB) s = madd(s, Qb[j * IB + t], c.p);
-      Pb[IPAD + t] = toeplitz64(s, fj, pt, c);
+      Pb[IPAD + t] = toeplitz64(s, Fb + j * IB, pt, c);
     }
     __syncthreads();
     uint32_t* tmp = Pa; Pa = Pb; Pb = tmp;
@@ -421,20 +458,7 @@ __global__ __launch_bounds__(INTERP_THREADS) void k_interp(const ResJob* jobs, c
 // workspace, the F_j come from their table.
 // ---------------------------------------------------------------------------
 // s1 += sum_q U[q] S1[-q], and (TWO) s2 += sum_q U[q] S2[-q], U in LDS
-// (16-byte aligned).  Sixteen canonical products per reduction: their sum a
-// stays below 16 p^2 < 2^64, and a 2^-32 = hi + REDC(lo) mod p splits it
-// without REDC's own sum (which could pass 2^64): hi = a >> 32 < 4p is taken
-// below 2p, REDC(lo) = mulhi(lo pinv, p) + (lo != 0) <= p (lo plus the low
-// word of m p is 0 mod 2^32), so hi + REDC(lo) < 3p and s + it < 4p.
-__device__ __forceinline__ uint32_t fold16(uint32_t s, uint64_t a, const PrimeC& c) {
-  uint32_t hi = (uint32_t)(a >> 32);
-  const uint32_t h2 = hi - 2 * c.p;
-  hi = h2 < hi ? h2 : hi;
-  const uint32_t lo = (uint32_t)a;
-  const uint32_t r = __umulhi(lo * c.pinv, c.p) + (lo != 0u ? 1u : 0u);
-  return canon(s + hi + r, c.p);
-}
-
+// (16-byte aligned), sixteen products per reduction (fold16).
 template <bool TWO>
 __device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, const uint32_t* U, const uint32_t* S1,
                                              const uint32_t* S2, const PrimeC& c) {
@@ -669,7 +693,7 @@ __global__ __launch_bounds__(256) void k_ffact_init() {
 __global__ __launch_bounds__(64 * IBT) void k_interp_q(const ResJob* jobs, const int64_t* prefix, int njobs,
                                                        uint32_t* ws, uint32_t* zero_word) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
-  __shared__ uint32_t U[64 * IFF_J];          // v_i / i!
+  __shared__ __align__(16) uint32_t U[64 * IFF_J];  // v_i / i!
   __shared__ uint32_t Wp[IPAD + 64 * IFF_J];  // zeros, then (-1)^j / j!
   __shared__ uint32_t part[IFF_J][64];        // convolution units of this Newton block
   const int64_t b = blockIdx.x;
@@ -697,7 +721,7 @@ __global__ __launch_bounds__(64 * IBT) void k_interp_q(const ResJob* jobs, const
   }
   __syncthreads();
   // a_k, k = 64 j + lane: input block ib on wavefront ib
-  if (wave <= j) part[wave][lane] = toeplitz64(0u, U[wave * 64 + lane], Wp + IPAD + 64 * (j - wave) + lane, c);
+  if (wave <= j) part[wave][lane] = toeplitz64(0u, U + wave * 64, Wp + IPAD + 64 * (j - wave) + lane, c);
   __syncthreads();
   if (wave != 0) return;
   uint32_t a = 0;
@@ -741,7 +765,7 @@ __global__ __launch_bounds__(64 * IBT) void k_interp_out(const ResJob* jobs, con
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    outp[wave][lane] = toeplitz64(0u, q, &Gs[wave][64 + lane], c);
+    outp[wave][lane] = toeplitz64_bc(0u, q, &Gs[wave][64 + lane], c);
   }
   __syncthreads();
   if (wave == 0) {
