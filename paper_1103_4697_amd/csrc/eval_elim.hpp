@@ -118,15 +118,40 @@ __device__ __forceinline__ void horner_chunk(uint32_t& a0, uint32_t& a1, uint32_
   a3 = hstep4(a3, h.v[0].w, h.v[1].w, h.v[2].w, h.v[3].w, xp, c);
 }
 
+// deg: the operand's y-degree.  The group that holds row 0 (index deg) is
+// partial unless deg + 1 is a multiple of four; its missing rows would run
+// the full length on zeros (that group has the longest rows of a dense
+// polynomial), so it takes a loop over its rows that exist only.
 template <int N>
-__device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* r, const RowDesc* rd,
+__device__ __forceinline__ void eval_rows(uint32_t (&A)[N + 1], const uint32_t* r, const RowDesc* rd, int deg,
                                           const XPow& X, const PrimeC& c) {
 #pragma unroll
   for (int t0 = 0; t0 <= N; t0 += ROWGRP) {
     const RowDesc d = rd[t0 / ROWGRP];
     const HChunk* q = reinterpret_cast<const HChunk*>(r + d.off);
     uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) horner_chunk(a0, a1, a2, a3, q[ch], X, c);
+    const int nv = deg - t0 + 1;  // rows of the group that exist (uniform)
+    if (nv >= ROWGRP) {
+      for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) horner_chunk(a0, a1, a2, a3, q[ch], X, c);
+    } else if (nv == 1) {
+      for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) {
+        const HChunk& h = q[ch];
+        a0 = hstep4(a0, h.v[0].x, h.v[1].x, h.v[2].x, h.v[3].x, X, c);
+      }
+    } else if (nv == 2) {
+      for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) {
+        const HChunk& h = q[ch];
+        a0 = hstep4(a0, h.v[0].x, h.v[1].x, h.v[2].x, h.v[3].x, X, c);
+        a1 = hstep4(a1, h.v[0].y, h.v[1].y, h.v[2].y, h.v[3].y, X, c);
+      }
+    } else if (nv == 3) {
+      for (int ch = d.len / HCHUNK - 1; ch >= 0; --ch) {
+        const HChunk& h = q[ch];
+        a0 = hstep4(a0, h.v[0].x, h.v[1].x, h.v[2].x, h.v[3].x, X, c);
+        a1 = hstep4(a1, h.v[0].y, h.v[1].y, h.v[2].y, h.v[3].y, X, c);
+        a2 = hstep4(a2, h.v[0].z, h.v[1].z, h.v[2].z, h.v[3].z, X, c);
+      }
+    }
     A[t0] = a0;
     if (t0 + 1 <= N) A[t0 + 1] = a1;
     if (t0 + 2 <= N) A[t0 + 2] = a2;
@@ -355,8 +380,8 @@ __device__ __forceinline__ void eval_elim_block(int64_t b, const PrimeC* primes,
   const RowDesc* ra = rows + J.rows_off;
   const RowDesc* rb = ra + J.rstride;  // J.rstride == N + 1 on this path
   uint32_t A[N + 1], B[N + 1];
-  eval_rows<N>(A, r, ra, X, c);
-  eval_rows<N>(B, r, rb, X, c);
+  eval_rows<N>(A, r, ra, J.m, X, c);
+  eval_rows<N>(B, r, rb, J.n, X, c);
 
   // formal degrees attained at this point, else the general elimination
   A[0] = canon(A[0], c.p);

@@ -153,7 +153,7 @@ struct EEVariant {
 constexpr int EE_WPE_MAX = 4;
 // Revision of the evaluation kernels' code, part of the autotuner's cache
 // file name: a changed kernel is tuned again instead of taking stale choices.
-constexpr int EE_KERNEL_REV = 3;
+constexpr int EE_KERNEL_REV = 4;
 // workgroups of a variant resident on the whole device (0 if the query fails)
 int eval_elim_grid(int cls, int wpe, int max_T);
 // reduce_in: the residues are reduced from the input limbs inside the kernel (LDS variant only)
