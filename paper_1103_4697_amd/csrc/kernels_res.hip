@@ -480,6 +480,44 @@ __device__ __forceinline__ void toeplitz64_w(uint32_t& s1, uint32_t& s2, const u
   }
 }
 
+// Two adjacent outputs per lane: with P at word t (t even) and
+// V_j = P[1 - j], so += sum_{q<64} U[q] V_q and se += sum_{q<64} U[q] V_{q+1}:
+// the Toeplitz sums of outputs t + 1 and t.  One read of the two words
+// P[-2i], P[1-2i] = V_{2i+1}, V_{2i} feeds four products, so the sliding
+// operand costs half the LDS bytes of one output per lane; sixteen products
+// per reduction (fold16), the same sums as toeplitz64_w.
+__device__ __forceinline__ void toeplitz64_pair(uint32_t& se, uint32_t& so, const uint32_t* U, const uint32_t* P,
+                                                const PrimeC& c) {
+  const uint2* P2 = reinterpret_cast<const uint2*>(P);  // P2[-i] = (V_{2i+1}, V_{2i})
+  uint2 cur = P2[0];
+#pragma unroll
+  for (int g = 0; g < 64; g += 16) {
+    uint32_t V[18];  // V[k] = V_{g+k}
+    V[0] = cur.y;
+    V[1] = cur.x;
+#pragma unroll
+    for (int i = 1; i <= 8; ++i) {
+      const uint2 x = P2[-(g / 2 + i)];
+      V[2 * i] = x.y;
+      V[2 * i + 1] = x.x;
+    }
+    cur = make_uint2(V[17], V[16]);
+    const uint4* U4 = reinterpret_cast<const uint4*>(U + g);
+    const uint4 ua = U4[0], ub = U4[1], uc = U4[2], ud = U4[3];
+    const uint32_t w16[16] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w,
+                              uc.x, uc.y, uc.z, uc.w, ud.x, ud.y, ud.z, ud.w};
+    uint64_t ao = 0, ae = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const uint64_t w = w16[q];
+      ao += w * V[q];
+      ae += w * V[q + 1];
+    }
+    so = fold16(so, ao, c);
+    se = fold16(se, ae, c);
+  }
+}
+
 // Newton block -> monomial: Q = sum_{s < len} a_{b0+s} prod_{t < s} (x - (b0 + t)),
 // a_{b0+s} in lane s, by Horner's rule from the top with two steps per
 // iteration:
@@ -525,10 +563,14 @@ __device__ __forceinline__ uint32_t newton_block2(uint32_t a, int b0, int len, i
   return q;
 }
 
+// zero words below index 0 of k_interp_w's sliding operand: the paired
+// outputs of the Newton coefficients reach 127 words below an input block
+constexpr int IPAD_W = 128;
+
 __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32_t* job_list, const int64_t* prefix,
                                                  int njobs, uint32_t* ws, uint32_t* zero_word) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;  // abnormal counter, read by now
-  extern __shared__ uint4 S4[];  // [IPAD + Dp] sliding operand, then [64] uniform operand
+  extern __shared__ uint4 S4[];  // [IPAD_W + Dp] sliding operand, then [64] uniform operand
   uint32_t* S = reinterpret_cast<uint32_t*>(S4);
   const int64_t b = blockIdx.x;
   const int jj = find_job(prefix, njobs, b);
@@ -544,8 +586,8 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   const uint32_t* IF = g_ifact + (int64_t)pi * (MAX_D + 1);
   const uint32_t* FB = g_fblk + (int64_t)pi * IW_NBLK * 64;
   const int lane = threadIdx.x;
-  uint32_t* U = S + IPAD + Dp;  // 16-byte aligned: IPAD and Dp are multiples of 64
-  uint32_t* K = U + 64;         // constants of the Newton blocks' iterations
+  uint32_t* U = S + IPAD_W + Dp;  // 16-byte aligned: IPAD_W and Dp are multiples of 64
+  uint32_t* K = U + 64;           // constants of the Newton blocks' iterations (128 words)
   // the uniform operand of the next Toeplitz sums (one wavefront: the
   // barriers only order its own LDS accesses)
   auto stage_u = [&](uint32_t v) {
@@ -553,8 +595,8 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
     U[lane] = v;
     __syncthreads();
   };
-  for (int t = lane; t < IPAD + Dp; t += 64) {
-    const int j = t - IPAD;
+  for (int t = lane; t < IPAD_W + Dp; t += 64) {
+    const int j = t - IPAD_W;
     uint32_t w = 0;
     if (j >= 0 && j < n1) {
       const uint32_t f = IF[j];
@@ -575,18 +617,26 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   auto uval = [&]() { return mmulc(canon(vn, c.p), fn, c.p, c.pinv); };
   for (int ob = 0; ob < nblk; ob += 2) {
     const int b0 = ob * 64;
-    const uint32_t* w1 = S + IPAD + b0 + lane;
+    const uint32_t* w1 = S + IPAD_W + b0 + lane;
     uint32_t s1 = 0, s2 = 0;
     load_u(0);
     if (ob + 1 < nblk) {
-      for (int ib = 0; ib <= ob; ++ib) {
+      // lane l: outputs b0 + 2l and b0 + 2l + 1; the input block ob + 1
+      // meets only the upper output block (the zeros below index 0 give the
+      // lower lanes nothing)
+      const int te = b0 + 2 * lane;
+      uint32_t se = 0, so = 0;
+      for (int ib = 0; ib <= ob + 1; ++ib) {
         stage_u(uval());
-        load_u(ib + 1);
-        toeplitz64_w<true>(s1, s2, U, w1 - 64 * ib, w1 + 64 - 64 * ib, c);
+        if (ib <= ob) load_u(ib + 1);
+        toeplitz64_pair(se, so, U, S + IPAD_W + te - 64 * ib, c);
       }
-      uint32_t dummy = 0;
-      stage_u(uval());
-      toeplitz64_w<false>(s2, dummy, U, w1 - 64 * ob, w1, c);
+      // back to one output block per lane: b0 + lane and b0 + 64 + lane
+      __syncthreads();
+      reinterpret_cast<uint2*>(K)[lane] = make_uint2(se, so);
+      __syncthreads();
+      s1 = K[lane];
+      s2 = K[64 + lane];
       Qg[b0 + lane] = newton_block2(s1, b0, 64, lane, c, U, K);
       Qg[b0 + 64 + lane] = newton_block2(s2, b0 + 64, min(64, n1 - b0 - 64), lane, c, U, K);
     } else {
@@ -603,8 +653,8 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
   // P = Q_{nblk-1}; P <- P F_j + Q_j for j = nblk-2 .. 0, in place from the top block down
   const int lastb = (nblk - 1) * 64;
   const int lastlen = n1 - lastb;
-  for (int t = lane; t < IPAD + Dp; t += 64) {
-    const int x = t - IPAD;
+  for (int t = lane; t < IPAD_W + Dp; t += 64) {
+    const int x = t - IPAD_W;
     S[t] = (x >= 0 && x < lastlen) ? Qg[lastb + x] : 0u;
   }
   __syncthreads();
@@ -615,32 +665,40 @@ __global__ __launch_bounds__(64) void k_interp_w(const ResJob* jobs, const int32
     stage_u(FB[j * 64 + lane]);
     const uint32_t qj = Qg[j * 64 + lane];
     for (int ob = nob - 1; ob >= 0; ob -= 2) {
-      const uint32_t* p1 = S + IPAD + ob * 64 + lane;  // P[t - i] = p1[-i]
-      uint32_t s1 = p1[-64];                            // x^64 term of F_j
-      if (ob == 0) s1 = madd(s1, qj, c.p);
-      uint32_t s2 = 0;
       if (ob >= 1) {
-        s2 = p1[-128];
-        if (ob == 1) s2 = madd(s2, qj, c.p);
-        toeplitz64_w<true>(s1, s2, U, p1, p1 - 64, c);
+        // blocks ob - 1 and ob, lane l: outputs t = te and te + 1
+        const int te = (ob - 1) * 64 + 2 * lane;
+        uint32_t* pe = S + IPAD_W + te;  // P[t - i] = pe[-i]
+        const uint2 x64 = *reinterpret_cast<const uint2*>(pe - 64);  // x^64 term of F_j
+        uint32_t se = x64.x, so = x64.y;
+        if (ob == 1 && lane < 32) {  // outputs below 64: + Q_j
+          const uint2 q2 = *reinterpret_cast<const uint2*>(Qg + j * 64 + te);
+          se = madd(se, q2.x, c.p);
+          so = madd(so, q2.y, c.p);
+        }
+        toeplitz64_pair(se, so, U, pe, c);
+        __syncthreads();  // every lane's reads of the old blocks before the new values land
+        *reinterpret_cast<uint2*>(pe) = make_uint2(se, so);
+        __syncthreads();
       } else {
+        const uint32_t* p1 = S + IPAD_W + lane;  // P[t - i] = p1[-i]
+        uint32_t s1 = madd(p1[-64], qj, c.p);    // x^64 term of F_j, + Q_j
         uint32_t dummy = 0;
         toeplitz64_w<false>(s1, dummy, U, p1, p1, c);
+        __syncthreads();
+        S[IPAD_W + lane] = s1;
+        __syncthreads();
       }
-      __syncthreads();  // every lane's reads of the old blocks before the new values land
-      S[IPAD + ob * 64 + lane] = s1;
-      if (ob >= 1) S[IPAD + (ob - 1) * 64 + lane] = s2;
-      __syncthreads();
     }
     dP = dN;
   }
-  for (int t = lane; t < n1; t += 64) C[t] = from_mont(S[IPAD + t], c);
+  for (int t = lane; t < n1; t += 64) C[t] = from_mont(S[IPAD_W + t], c);
 }
 
 void launch_interp_w(const ResJob* jobs_d, const int32_t* job_list_d, const int64_t* prefix_d, int njobs,
                      int64_t nblocks, int max_D, uint32_t* ws, uint32_t* zero_word, hipStream_t s) {
   if (nblocks <= 0) return;
-  const size_t lds = (size_t)(IPAD + (max_D + 64) / 64 * 64 + 64 + 128) * sizeof(uint32_t);
+  const size_t lds = (size_t)(IPAD_W + (max_D + 64) / 64 * 64 + 64 + 128) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_interp_w, dim3((unsigned)nblocks), dim3(64), lds, s, jobs_d, job_list_d, prefix_d, njobs,
                      ws, zero_word);
 }
