@@ -139,7 +139,11 @@ int snc_microbench(snc_ctx* ctx, int kind, int32_t iters, void* d_buf, size_t bu
  * snc_set_tuning: mode 0 = no measurements (cached choices, else wpe 1,
  *   chunk 0), 1 = measure the classes not yet tuned on this device (the
  *   default; batched calls only: snc_resultant_y_prepare/_batch), 2 =
- *   measure again.  Choices are kept per (class, LDS variant, log2 of the
+ *   measure again.  A measurement times every variant on the class's own
+ *   launch and keeps, of those within 5% of the fastest, the one that
+ *   spills the fewest bytes per lane (spill traffic slows the kernels that
+ *   follow, which a launch timed alone does not show).  Choices are kept
+ *   per (class, LDS variant, log2 of the
  *   class's block count) and appended to the cache file
  *   $SNC_TUNE_DIR/eval_elim_<arch>_<CUs>cu_r<rev>.tune (default directory
  *   $HOME/.cache/snc), read by later processes; <rev> is the revision of

@@ -6,6 +6,7 @@ namespace snc {
 
 #define SNC_EXTERN_CLASS(NN)                                                                                  \
   extern template int eval_elim_grid_cls<NN>(int, int);                                                      \
+  extern template int eval_elim_scratch_cls<NN>(int, int);                                                   \
   extern template void launch_eval_elim_cls<NN>(const EEVariant&, uint32_t*, const PrimeC*, const ResJob*,   \
                                                 const int32_t*, const int64_t*, int, int64_t, int,            \
                                                 const RowDesc*, uint32_t*, uint32_t*, AbnEntry*, uint32_t,    \
@@ -35,6 +36,17 @@ int eval_elim_grid(int cls, int wpe, int max_T) {
     case 40: return eval_elim_grid_cls<40>(wpe, max_T);
     case 48: return eval_elim_grid_cls<48>(wpe, max_T);
     default: return eval_elim_grid_cls<64>(wpe, max_T);
+  }
+}
+
+int eval_elim_scratch(int cls, int wpe, int max_T) {
+  switch (kClassCap[cls]) {
+    case 8: return eval_elim_scratch_cls<8>(wpe, max_T);
+    case 16: return eval_elim_scratch_cls<16>(wpe, max_T);
+    case 32: return eval_elim_scratch_cls<32>(wpe, max_T);
+    case 40: return eval_elim_scratch_cls<40>(wpe, max_T);
+    case 48: return eval_elim_scratch_cls<48>(wpe, max_T);
+    default: return eval_elim_scratch_cls<64>(wpe, max_T);
   }
 }
 

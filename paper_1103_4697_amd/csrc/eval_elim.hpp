@@ -500,6 +500,15 @@ int eval_elim_grid_cls(int wpe, int max_T) {
   return per_cu * prop.multiProcessorCount;
 }
 
+// private (spill) bytes per lane of a variant's kernel, -1 if unknown
+template <int NN>
+int eval_elim_scratch_cls(int wpe, int max_T) {
+  const void* k = eval_elim_in_lds(max_T) ? ee_kernel_ptr<NN, true>(wpe) : ee_kernel_ptr<NN, false>(wpe);
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, k) != hipSuccess) return -1;
+  return (int)a.localSizeBytes;
+}
+
 template <int NN>
 void launch_eval_elim_cls(const EEVariant& v, uint32_t* counter, const PrimeC* primes, const ResJob* jobs_d,
                           const int32_t* job_list_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
@@ -522,6 +531,7 @@ void launch_eval_elim_cls(const EEVariant& v, uint32_t* counter, const PrimeC* p
 // one translation unit per register class (eval_elim_c<NN>.hip) instantiates these
 #define SNC_EVAL_ELIM_CLASS(NN)                                                                               \
   template int eval_elim_grid_cls<NN>(int, int);                                                              \
+  template int eval_elim_scratch_cls<NN>(int, int);                                                           \
   template void launch_eval_elim_cls<NN>(const EEVariant&, uint32_t*, const PrimeC*, const ResJob*,           \
                                          const int32_t*, const int64_t*, int, int64_t, int, const RowDesc*,    \
                                          uint32_t*, uint32_t*, AbnEntry*, uint32_t, bool, hipStream_t);

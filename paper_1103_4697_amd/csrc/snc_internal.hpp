@@ -151,11 +151,14 @@ struct EEVariant {
   int64_t grid = 0;
 };
 constexpr int EE_WPE_MAX = 4;
-// Revision of the evaluation kernels' code, part of the autotuner's cache
-// file name: a changed kernel is tuned again instead of taking stale choices.
-constexpr int EE_KERNEL_REV = 4;
+// Revision of the evaluation kernels' code and of the tuner's choice rule,
+// part of the autotuner's cache file name: a changed kernel is tuned again
+// instead of taking stale choices.
+constexpr int EE_KERNEL_REV = 5;
 // workgroups of a variant resident on the whole device (0 if the query fails)
 int eval_elim_grid(int cls, int wpe, int max_T);
+// private (spill) bytes per lane of a variant's kernel (-1 if the query fails)
+int eval_elim_scratch(int cls, int wpe, int max_T);
 // reduce_in: the residues are reduced from the input limbs inside the kernel (LDS variant only)
 void launch_eval_elim(int cls, const EEVariant& v, uint32_t* counter, const ResJob* jobs_d,
                       const int32_t* job_list_d, const int64_t* blk_prefix_d, int njobs, int64_t nblocks,
