@@ -43,6 +43,12 @@ void snc_ctx::release() {
   side_stream = nullptr;
   if (ev_mid) (void)hipEventDestroy(ev_mid);
   ev_mid = nullptr;
+  if (fork_stream) (void)hipStreamDestroy(fork_stream);
+  fork_stream = nullptr;
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  ev_fork = nullptr;
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  ev_join = nullptr;
   for (auto e : events) (void)hipEventDestroy(e);
   events.clear();
   if (h_in) (void)hipHostFree(h_in);
@@ -211,7 +217,8 @@ struct StageTimer {
 
 // Device launch sequence for a laid-out batch (everything after the upload).
 // part: PIPE_ALL, PIPE_TO_INTERP (reduction .. interpolation) or PIPE_CRT
-void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part) {
+void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part,
+                     const PipeFork& fk) {
   uint32_t* wsw = (uint32_t*)ws;
   const ResJob* jobs = (const ResJob*)(ws + lay.jobs_off);
   const RowDesc* rows = (const RowDesc*)(ws + lay.rows_off);
@@ -256,11 +263,28 @@ void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTi
   }
   if (part == PIPE_TO_INTERP) return;
   static const char* const kCrtStage[NCRT_SMALL] = {"crt_small_32", "crt_small_64", "crt_small_128"};
+  // The class with the most primes has the fewest, longest workgroups (one
+  // round on the device, each bound by its own latency): on a branch it runs
+  // beside the other classes instead of after them.
+  int nsmall = 0, top = -1;
+  for (int c = 0; c < NCRT_SMALL; ++c)
+    if (lay.n_crts_jobs[c]) { ++nsmall; top = c; }
+  const bool branch = fk.stream && !tm && nsmall >= 2;
+  if (branch) {
+    (void)hipEventRecord(fk.fork, s);
+    (void)hipStreamWaitEvent(fk.stream, fk.fork, 0);
+    launch_crt_small(top, jobs, (const int32_t*)(ws + lay.list_crts[top]), (const int64_t*)(ws + lay.pref_crts[top]),
+                     lay.n_crts_jobs[top], lay.nb_crts[top], wsw, fk.stream);
+  }
   for (int c = 0; c < NCRT_SMALL; ++c) {
-    if (!lay.n_crts_jobs[c]) continue;
+    if (!lay.n_crts_jobs[c] || (branch && c == top)) continue;
     launch_crt_small(c, jobs, (const int32_t*)(ws + lay.list_crts[c]), (const int64_t*)(ws + lay.pref_crts[c]),
                      lay.n_crts_jobs[c], lay.nb_crts[c], wsw, s);
     if (tm) tm->mark(kCrtStage[c], 1);
+  }
+  if (branch) {
+    (void)hipEventRecord(fk.join, fk.stream);
+    (void)hipStreamWaitEvent(s, fk.join, 0);
   }
   if (lay.n_crtb_jobs) {
     const CrtTables tb = global_crt_tables();
@@ -511,9 +535,16 @@ static int launch_prepared_all(snc_prepared* pr, hipStream_t stream, StageTimer&
   hipGraphExec_t& gx = pr->gexec;
   if (!gx) {
     if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->fork_stream) HIPCHK(hipStreamCreateWithFlags(&c->fork_stream, hipStreamNonBlocking));
+    if (!c->ev_fork) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (!c->ev_join) HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    PipeFork fk;
+    fk.stream = c->fork_stream;
+    fk.fork = c->ev_fork;
+    fk.join = c->ev_join;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    launch_pipeline(pr->lay, pr->ws, c->cap_stream, nullptr, part);
+    launch_pipeline(pr->lay, pr->ws, c->cap_stream, nullptr, part, fk);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
     hipError_t e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);

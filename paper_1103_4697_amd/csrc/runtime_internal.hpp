@@ -125,6 +125,10 @@ struct snc_ctx {
   // second stream (default priority) and event for work beside the pipeline
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_mid = nullptr;
+  // branch of the captured pipeline (default priority): the small-prime CRT
+  // class with the most primes runs beside the other classes
+  hipStream_t fork_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   snc_ctx() {
     for (auto& f : forced) f.wpe = 0;
@@ -169,8 +173,16 @@ struct StageTimer;
 // prefixes, class job lists and the packed input limbs (header_bytes)
 void fill_header(const BatchLayout& lay, const std::vector<ResPlan>& plans, const std::vector<Operand>& F,
                  const std::vector<Operand>& G, uint8_t* h);
-// device launch sequence of a laid-out batch whose header is in ws (tm may be null)
-void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part);
+// Stream and events of a branch beside the main stream (all null: no branch).
+struct PipeFork {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+// device launch sequence of a laid-out batch whose header is in ws (tm may be
+// null); with a branch (fk.stream set, tm null) the small-prime CRT class
+// with the most primes runs on the branch beside the other classes
+void launch_pipeline(const BatchLayout& lay, uint8_t* ws, hipStream_t s, StageTimer* tm, int part,
+                     const PipeFork& fk = PipeFork());
 // launch variants of the evaluation kernel for a laid-out batch whose header is on the device:
 // forced variants, then (tune true) measured ones for the classes the cache lacks, else cached
 // choices or the defaults; fills lay.ee_var and the context's report
