@@ -264,7 +264,7 @@ def test_config2_full_draw(snc, assert_same):
     every pair agrees with the oracle's determinant modulo a 61-bit prime at
     a random point; the three cheapest pairs equal the oracle's resultant
     coefficient by coefficient; the stage-by-stage run (timing on) gives the
-    same results as the graph."""
+    same results as the graph, and so do three more graph replays after it."""
     pairs, common = synth.config2()
     assert len(pairs) == 512 and len(common) == 51
     b = snc.ResultantBatch(pairs)
@@ -292,6 +292,11 @@ def test_config2_full_draw(snc, assert_same):
         assert_same(b.results(), got)
     finally:
         b.ctx.set_timing(False)
+    # the captured graph (its CRT classes on two branches) replayed again
+    # after that eager work: the same results on every replay
+    for _ in range(3):
+        b.run()
+        assert_same(b.results(), got)
 
 
 @pytest.mark.parametrize("da,db", [(63, 20), (64, 32), (1000, 500), (1023, 300), (1024, 512)])
